@@ -1,0 +1,129 @@
+"""Element-tensor oracle -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the smoke check (``__graft_entry__.smoke``) and the CPU-baseline leg of
+``bench.py`` import this package.  The product path (the HIP library and its Python
+binding) never imports, links or executes anything here, and this package never imports
+the product.
+
+Two independent evaluators of the element tensor A^K (element matrix, Sec. 2.2; element
+tensor of a multilinear form, Sec. 3.1):
+
+* ``tabulate`` -- plain C, FP64, OpenMP over cells: the defining integral on the
+  physical cell by a collapsed Gauss-Legendre product rule that is exact for the
+  integrand's polynomial degree (``ffc_oracle.c`` states every convention);
+* ``exact.element_tensor`` -- pure-Python exact rational arithmetic on one cell with
+  rational vertices (the pin for ``tabulate``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+KINDS = {"mass": 0, "laplace": 1, "wlaplace": 2, "elasticity": 3, "ns": 4}
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ffc_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle with gcc (OpenMP) into oracle/liboracle.so."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int)
+        L.oracle_tabulate.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_longlong, dp, dp, dp, ctypes.c_int]
+        L.oracle_tabulate.restype = ctypes.c_int
+        L.oracle_n_dofs.argtypes = [ctypes.c_int] * 3
+        L.oracle_n_dofs.restype = ctypes.c_int
+        L.oracle_n_coeffs.argtypes = [ctypes.c_int] * 2
+        L.oracle_n_coeffs.restype = ctypes.c_int
+        L.oracle_simplex_rule.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp]
+        L.oracle_simplex_rule.restype = ctypes.c_int
+        L.oracle_nodes.argtypes = [ctypes.c_int, ctypes.c_int, ip]
+        L.oracle_nodes.restype = ctypes.c_int
+        L.oracle_basis.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp, dp]
+        L.oracle_basis.restype = ctypes.c_int
+        L.oracle_max_threads.argtypes = []
+        L.oracle_max_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def n_dofs(kind: str, dim: int, degree: int) -> int:
+    return lib().oracle_n_dofs(KINDS[kind], dim, degree)
+
+
+def n_coeffs(kind: str, dim: int) -> int:
+    return lib().oracle_n_coeffs(KINDS[kind], dim)
+
+
+def max_threads() -> int:
+    return lib().oracle_max_threads()
+
+
+def tabulate(kind: str, dim: int, degree: int, coords, coeffs=None, lam: float = 1.0, mu: float = 1.0,
+             nthreads: int = 0) -> np.ndarray:
+    """Element tensors [cells, n, n] (row = test function) in FP64."""
+    coords = np.ascontiguousarray(coords, dtype=np.float64)
+    assert coords.ndim == 2 and coords.shape[0] == (dim + 1) * dim
+    cells = coords.shape[1]
+    n = n_dofs(kind, dim, degree)
+    if n < 0:
+        raise ValueError(f"unsupported form {kind} dim={dim} degree={degree}")
+    nc = n_coeffs(kind, dim)
+    cptr = None
+    if nc:
+        if coeffs is None:
+            raise ValueError(f"form {kind} needs {nc} coefficients per cell")
+        coeffs = np.ascontiguousarray(coeffs, dtype=np.float64)
+        assert coeffs.shape == (nc, cells)
+        cptr = _dp(coeffs)
+    out = np.empty((cells, n, n), dtype=np.float64)
+    rc = lib().oracle_tabulate(KINDS[kind], dim, degree, lam, mu, cells, _dp(coords), cptr, _dp(out), nthreads)
+    if rc != 0:
+        raise RuntimeError(f"oracle_tabulate failed ({rc})")
+    return out
+
+
+def simplex_rule(dim: int, m: int):
+    pts = np.zeros((m ** dim, dim))
+    wts = np.zeros(m ** dim)
+    npts = lib().oracle_simplex_rule(dim, m, _dp(pts), _dp(wts))
+    assert npts == m ** dim
+    return pts, wts
+
+
+def nodes(dim: int, degree: int) -> np.ndarray:
+    buf = np.zeros((64, 4), dtype=np.int32)
+    nn = lib().oracle_nodes(dim, degree, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+    return buf[:nn, : dim + 1].copy()
+
+
+def basis(dim: int, degree: int, X) -> tuple[np.ndarray, np.ndarray]:
+    X = np.ascontiguousarray(np.atleast_2d(X), dtype=np.float64)
+    npts = X.shape[0]
+    nn = len(nodes(dim, degree))
+    phi = np.zeros((npts, nn))
+    dphi = np.zeros((npts, nn, dim))
+    lib().oracle_basis(dim, degree, npts, _dp(X), _dp(phi), _dp(dphi))
+    return phi, dphi

@@ -1,0 +1,219 @@
+"""Seeded synthetic meshes and coefficient fields.
+
+This module only generates inputs: vertex coordinates, cell connectivity, the per-cell
+structure-of-arrays gathers the tabulation entry points take, and random coefficient
+values.  It holds none of the element-tensor arithmetic, so both the HIP path and the
+oracle can be fed from it.
+
+Meshes follow the workloads of the paper's benchmarks (Sec. 6: affine simplices, one
+million elements per timing) generalised to jittered structured grids:
+
+* 2D: the unit square cut into n x n squares, each split along its (0,0)-(1,1) diagonal
+  into two positively oriented triangles;
+* 3D: the unit cube cut into n^3 cubes, each split into the six Kuhn tetrahedra (vertex
+  chains along the axes in the order of a permutation), reordered to positive orientation;
+* every coordinate of every interior vertex is moved by an independent U(-0.2h, 0.2h).
+
+Layouts handed to the library:
+* coords: float64 SoA ``[(d+1)*d][cells]``, ``coords[(v*d + k)*cells + c]`` = coordinate k
+  of local vertex v of cell c;
+* coeffs: float64 SoA ``[n_coeff][cells]``: P1 scalar field -> one value per local vertex;
+  P1 vector field -> ``coeffs[(comp*(d+1) + vertex)*cells + c]``.
+"""
+from __future__ import annotations
+
+import itertools
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+JITTER = 0.2
+
+
+def _grid_vertices(n: int, dim: int, rng: np.random.Generator, jitter: float = JITTER):
+    h = 1.0 / n
+    axes = [np.arange(n + 1, dtype=np.float64) * h] * dim
+    grid = np.stack(np.meshgrid(*axes, indexing="ij"), axis=-1).reshape(-1, dim)
+    idx = np.stack(np.meshgrid(*[np.arange(n + 1)] * dim, indexing="ij"), axis=-1).reshape(-1, dim)
+    interior = np.all((idx > 0) & (idx < n), axis=1)
+    noise = rng.uniform(-jitter * h, jitter * h, size=grid.shape)
+    grid = grid + noise * interior[:, None]
+    return grid, idx
+
+
+def unit_square(n: int, seed: int, jitter: float = JITTER):
+    """Jittered unit square, 2 n^2 triangles. Returns (vertices [nv,2], cells [nc,3])."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    verts, _ = _grid_vertices(n, 2, rng, jitter)
+
+    def vid(i, j):
+        return i * (n + 1) + j
+
+    cells = np.empty((2 * n * n, 3), dtype=np.int64)
+    k = 0
+    for i in range(n):
+        for j in range(n):
+            v00, v10, v01, v11 = vid(i, j), vid(i + 1, j), vid(i, j + 1), vid(i + 1, j + 1)
+            cells[k] = (v00, v10, v11)
+            cells[k + 1] = (v00, v11, v01)
+            k += 2
+    return verts, cells
+
+
+_PERMS = list(itertools.permutations(range(3)))
+
+
+def _perm_parity(p):
+    inv = 0
+    for a in range(3):
+        for b in range(a + 1, 3):
+            inv += p[a] > p[b]
+    return inv % 2
+
+
+def unit_cube(n: int, seed: int, jitter: float = JITTER, max_cells: int | None = None):
+    """Jittered unit cube, 6 n^3 Kuhn tetrahedra. Returns (vertices [nv,3], cells [nc,4])."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    verts, _ = _grid_vertices(n, 3, rng, jitter)
+    stride = np.array([(n + 1) * (n + 1), n + 1, 1], dtype=np.int64)
+    corners = np.stack(np.meshgrid(*[np.arange(n)] * 3, indexing="ij"), axis=-1).reshape(-1, 3)
+    base = corners @ stride
+    local = []
+    for p in _PERMS:
+        chain = [np.zeros(3, dtype=np.int64)]
+        cur = np.zeros(3, dtype=np.int64)
+        for ax in p:
+            cur = cur.copy()
+            cur[ax] += 1
+            chain.append(cur)
+        offs = [int(c @ stride) for c in chain]
+        if _perm_parity(p) == 1:  # odd permutation: negative orientation, swap two vertices
+            offs[2], offs[3] = offs[3], offs[2]
+        local.append(offs)
+    local = np.array(local, dtype=np.int64)  # [6,4]
+    cells = (base[:, None, None] + local[None, :, :]).reshape(-1, 4)
+    if max_cells is not None:
+        cells = cells[:max_cells]
+    return verts, cells
+
+
+def soa_coords(verts: np.ndarray, cells: np.ndarray) -> np.ndarray:
+    """Per-cell SoA coordinates [(d+1)*d][cells], contiguous float64."""
+    d = verts.shape[1]
+    g = verts[cells]  # [nc, d+1, d]
+    return np.ascontiguousarray(g.reshape(cells.shape[0], (d + 1) * d).T)
+
+
+def signed_volumes_ok(verts: np.ndarray, cells: np.ndarray) -> bool:
+    """Input validation: every cell positively oriented."""
+    g = verts[cells]
+    e = g[:, 1:, :] - g[:, :1, :]
+    return bool(np.all(np.linalg.det(e) > 0))
+
+
+def p1_scalar_coeffs(cells: np.ndarray, vertex_values: np.ndarray) -> np.ndarray:
+    """Gather a P1 scalar field given at mesh vertices: SoA [d+1][cells]."""
+    return np.ascontiguousarray(vertex_values[cells].T)
+
+
+def p1_vector_coeffs(cells: np.ndarray, vertex_values: np.ndarray) -> np.ndarray:
+    """Gather a P1 vector field [nv, d]: SoA [d*(d+1)][cells], index comp*(d+1)+vertex."""
+    nc, nv1 = cells.shape
+    d = vertex_values.shape[1]
+    g = vertex_values[cells]  # [nc, d+1, d]
+    return np.ascontiguousarray(g.transpose(2, 1, 0).reshape(d * nv1, nc))
+
+
+# --------------------------------------------------------------------------- forms ---
+
+FORM_KINDS = ("mass", "laplace", "wlaplace", "elasticity", "ns")
+
+
+@dataclass
+class Workload:
+    """One mesh with one form: everything a tabulation call needs, on the host."""
+
+    kind: str
+    dim: int
+    degree: int
+    coords: np.ndarray
+    coeffs: np.ndarray | None
+    lam: float = 1.0
+    mu: float = 1.0
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def cells(self) -> int:
+        return int(self.coords.shape[1])
+
+
+def _mesh(dim: int, n: int, seed: int, max_cells: int | None = None):
+    if dim == 2:
+        v, c = unit_square(n, seed)
+        if max_cells is not None:
+            c = c[:max_cells]
+        return v, c
+    return unit_cube(n, seed, max_cells=max_cells)
+
+
+def make_workload(kind, dim, degree, n, seed, max_cells=None, name="", coeff_seed=None):
+    """Mesh of side n (2 n^2 or 6 n^3 cells, optionally cut to max_cells) with the
+    coefficient field the form needs: wlaplace w ~ U(0.5, 2) per vertex, ns w ~ N(0, 1)
+    per vertex and component."""
+    verts, cells = _mesh(dim, n, seed, max_cells)
+    coords = soa_coords(verts, cells)
+    rng = np.random.Generator(np.random.PCG64(seed + 7919 if coeff_seed is None else coeff_seed))
+    coeffs = None
+    if kind == "wlaplace":
+        coeffs = p1_scalar_coeffs(cells, rng.uniform(0.5, 2.0, size=verts.shape[0]))
+    elif kind == "ns":
+        coeffs = p1_vector_coeffs(cells, rng.standard_normal(size=(verts.shape[0], dim)))
+    return Workload(kind, dim, degree, coords, coeffs, name=name)
+
+
+def config1():
+    """2D Poisson, P1 triangles, 64 x 64 squares -> 8192 cells, seed 1."""
+    return make_workload("laplace", 2, 1, 64, 1, name="poisson2d_p1_8192")
+
+
+def config2():
+    """3D elasticity (lambda = mu = 1), vector P2 tets, 6 * 50^3 = 750,000 cells, seed 2."""
+    return make_workload("elasticity", 3, 2, 50, 2, name="elasticity3d_p2_750k")
+
+
+def config3():
+    """3D weighted Laplacian, P3 tets, w in P1 ~ U(0.5, 2), 6 * 63^3 = 1,500,282 cells, seed 3."""
+    return make_workload("wlaplace", 3, 3, 63, 3, name="wlaplace3d_p3_1.5M")
+
+
+# 16 form variants of the mixed batch, mesh k gets variant k mod 16.
+BATCH_VARIANTS = (
+    [("laplace", 2, q) for q in (1, 2, 3, 4)]
+    + [("laplace", 3, q) for q in (1, 2, 3, 4)]
+    + [("mass", 2, q) for q in (1, 2, 3)]
+    + [("mass", 3, q) for q in (1, 2, 3)]
+    + [("ns", 2, 2), ("ns", 3, 2)]
+)
+
+
+def batch_sizes(n_meshes: int = 64, lo: float = 1e3, hi: float = 5e5, seed: int = 4):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return [int(round(math.exp(x))) for x in rng.uniform(math.log(lo), math.log(hi), size=n_meshes)]
+
+
+def config4(n_meshes: int = 64, lo: float = 1e3, hi: float = 5e5, seed: int = 4, scale: float = 1.0):
+    """Mixed batch: n_meshes meshes of log-uniform sizes, variants round-robin. `scale`
+    shrinks every mesh (for quick tests) without changing the variant mix."""
+    out = []
+    for k, size in enumerate(batch_sizes(n_meshes, lo, hi, seed)):
+        size = max(1, int(round(size * scale)))
+        kind, dim, q = BATCH_VARIANTS[k % len(BATCH_VARIANTS)]
+        if dim == 2:
+            n = max(1, math.ceil(math.sqrt(size / 2.0)))
+        else:
+            n = max(1, math.ceil((size / 6.0) ** (1.0 / 3.0)))
+        out.append(make_workload(kind, dim, q, n, seed * 1000 + k, max_cells=size,
+                                 name=f"mesh{k}_{kind}{dim}d_p{q}"))
+    return out
