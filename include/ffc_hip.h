@@ -1,0 +1,165 @@
+/*
+ * ffc_hip -- element tensors in the tensor representation A^K = A^0 : G_K on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The element tensor of a bilinear form on an affine simplex K (element matrix, Sec. 2.2;
+ * element tensor of a multilinear form, Sec. 3.1) is evaluated as the contraction
+ *     A^K_i = A^0_{i alpha} G_K^alpha                      (eq. tensorproduct, Sec. 3.2)
+ * of a reference tensor A^0, integrated once per form on the reference simplex K0 in FP64
+ * on the host (the compile step: "Evaluation of integrals", Sec. 5.3), with a geometry
+ * tensor G_K built per cell from det F'_K, the inverse Jacobian g_ab = dX_a/dx_b and the
+ * coefficient dofs (Sec. 3.2 and test cases 1-4, Sec. 3.3).  On the device:
+ *   1. a geometry kernel, one lane per cell, FP64: coords -> (det J, J^{-1});
+ *   2. a contraction kernel: G_K tile built in LDS, A^0 tiles on the matrix cores
+ *      (MFMA), cells x |alpha| times |alpha| x |i| -- the level-3 BLAS batching the
+ *      paper proposes (Sec. 4.5, "Optimization");
+ * and, as the in-GPU comparison, a plain quadrature kernel (pretabulated basis at the
+ * points of a collapsed-coordinate Gauss-Jacobi rule exact for the integrand, Sec. 6).
+ *
+ * Conventions shared by every entry point
+ *  - Reference simplex K0: vertex 0 at the origin, vertex k at the k-th unit vector
+ *    (affine-map figure, Sec. 3.2).  J = [x^1 - x^0, ..., x^d - x^0] (columns).
+ *  - Lagrange P_q dofs: point evaluation at the equispaced nodes (Sec. 5.3), ordered
+ *    vertices, edges (triangle: edge k opposite vertex k; tetrahedron: (2,3),(1,3),(1,2),
+ *    (0,3),(0,2),(0,1), points from the lower to the higher vertex), faces (face k
+ *    opposite vertex k), interior; inside a sub-simplex with sorted vertices s_0<..<s_m,
+ *    ascending lexicographic order of (b_1..b_m).  Vector elements are component-blocked:
+ *    dof (c, s) -> c * n_scalar + s.
+ *  - Element tensor layout: out[cell][i1 * n + i2], row i1 = test function (first
+ *    argument of a(v, u)), n = element dofs.
+ *  - |det J| is used (the paper's det F'_K for positively oriented cells).
+ *  - coords (device, FP64, SoA): coords[(v * d + k) * cells + c] = coordinate k of local
+ *    vertex v of cell c.
+ *  - coeffs (device, FP64, SoA): coeffs[j * cells + c]; weighted Laplacian: j = vertex
+ *    (w in P1); Navier-Stokes: j = comp * (d + 1) + vertex (w in vector P1).  NULL for
+ *    forms without coefficients.
+ *  - All device pointers are caller-owned (for example torch tensors) and must stay
+ *    valid until the work enqueued on the form's stream has finished.
+ *
+ * Errors: every int-returning call returns FFC_OK (0) or a negative ffc_status; the
+ * message of the last failure on the calling thread is ffc_last_error().  Argument
+ * errors are detected before anything is enqueued.  Device faults surface as
+ * FFC_E_DEVICE from the call that observes them.
+ */
+#ifndef FFC_HIP_H
+#define FFC_HIP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Opaque form handle: the compiled reference tensor, its device tables and workspace. */
+typedef struct ffc_form ffc_form;
+
+typedef enum {
+    FFC_OK = 0,
+    FFC_E_INVALID = -1,     /* bad argument (NULL pointer, negative size, wrong mode) */
+    FFC_E_UNSUPPORTED = -2, /* form / dimension / degree / precision not supported   */
+    FFC_E_DEVICE = -3,      /* HIP runtime error, or no usable gfx950 device        */
+    FFC_E_NOMEM = -5        /* host or device allocation failed (create calls only) */
+} ffc_status;
+
+/* Forms (v = test, u = trial):
+ *  FFC_MASS          int v u                              (test case 1, eq. mass)
+ *  FFC_LAPLACE       int grad v . grad u                  (test case 2, eq. poisson)
+ *  FFC_WLAPLACE      int w grad v . grad u, w in P1       (variable-coefficient diffusion, Sec. 3.1)
+ *  FFC_ELASTICITY    int sigma(u) : eps(v), sigma = 2 mu eps + lambda tr(eps) I, vector P_q
+ *                    (test case 4; the paper's strain-strain term is mu = 1/2, lambda = 0)
+ *  FFC_NS_CONVECTION int v . ((w . grad) u), u, v vector P_q, w vector P1 (test case 3) */
+typedef enum { FFC_MASS = 0, FFC_LAPLACE = 1, FFC_WLAPLACE = 2, FFC_ELASTICITY = 3, FFC_NS_CONVECTION = 4 } ffc_kind;
+
+/* Arithmetic of the contraction.  FP64: FP64 MFMA, FP64 output.  Split modes: G and A^0
+ * are split into BF16 pieces (hi = RN(x), lo = RN(x - hi), [lo2 = RN(x - hi - lo)]) with
+ * the subtractions in FP64, multiplied on BF16 MFMA with FP32 accumulation, FP32 output;
+ * geometry stays FP64.  3 products: hi*hi + hi*lo + lo*hi.  6 products: additionally
+ * hi*lo2 + lo*lo + lo2*hi. */
+typedef enum { FFC_FP64 = 0, FFC_SPLIT_BF16_3 = 1, FFC_SPLIT_BF16_6 = 2 } ffc_precision;
+
+/* Which kernel evaluates A^K.  QUADRATURE is FP64 only. */
+typedef enum { FFC_KERNEL_TENSOR = 1, FFC_KERNEL_QUADRATURE = 2 } ffc_kernel;
+
+typedef struct {
+    int32_t kind;        /* ffc_kind */
+    int32_t dim;         /* 2 (triangles) or 3 (tetrahedra) */
+    int32_t degree;      /* Lagrange degree q of u and v: 1..4 (vector forms: 1..3) */
+    int32_t precision;   /* ffc_precision */
+    int32_t kernel;      /* ffc_kernel */
+    int32_t tile_cells;  /* cells per workgroup tile of the contraction: 0 = default, else 16, 32 or 64 */
+    int32_t waves;       /* waves per workgroup of the contraction: 0 = default, else 1, 2, 4 or 8 */
+    int32_t reserved;    /* must be 0 */
+    double lambda, mu;   /* Lame parameters (FFC_ELASTICITY only) */
+    void* stream;        /* hipStream_t the form's work is enqueued on; NULL = default stream */
+} ffc_form_desc;
+
+typedef struct {
+    int64_t n_dofs;           /* n: element dofs per argument */
+    int64_t n_entries;        /* n_I = n * n entries per element tensor */
+    int64_t n_alpha;          /* |alpha|: entries of G_K per cell */
+    int64_t nnz_a0;           /* nonzero entries of A^0 */
+    int64_t n_coords;         /* (d + 1) * d doubles per cell */
+    int64_t n_coeffs;         /* coefficient doubles per cell (0 if none) */
+    int64_t out_bytes;        /* bytes per output entry: 8 (FP64) or 4 (split modes) */
+    int64_t mfma_k_per_tile;  /* sum over 16-entry output tiles of the padded contraction length */
+    int64_t n_tiles;          /* 16-entry output tiles */
+    int64_t quad_points;      /* points of the quadrature kernel's rule */
+} ffc_form_info;
+
+/* Compile step only, host only, touches no device: the reference tensor A^0 of the form
+ * (A^0_{i alpha} = int_K0 prod dPhi/dX, Sec. 3.2; per-form expressions in Sec. 3.3).
+ * Writes n_I and n_alpha; if A0 != NULL also writes A^0 row-major [n_I][n_alpha] (FP64,
+ * caller-owned host buffer of n_I * n_alpha doubles).  Index conventions of alpha:
+ *   mass: alpha = 0                       G = |det J|
+ *   laplace: alpha = a*d + b              G = |det J| sum_k g_ak g_bk
+ *   wlaplace: alpha = (t*d + a)*d + b     G = w_t |det J| sum_k g_ak g_bk
+ *   elasticity: alpha = ((a*d + j)*d + b)*d + l     G = |det J| g_aj g_bl
+ *   ns: alpha = (k*(d+1) + t)*d + a       G = |det J| g_ak w_{k,t}
+ * with g = J^{-1} (g_ab = dX_a/dx_b). */
+int ffc_compile_reference_tensor(const ffc_form_desc* desc, int64_t* n_I, int64_t* n_alpha, double* A0);
+
+/* Compile step + upload: builds A^0, its MFMA tiles (and BF16 pieces in split modes) and
+ * the quadrature tables, copies them to the current device and returns an opaque form
+ * handle owned by the library (release with ffc_form_destroy).  The handle also owns a
+ * geometry workspace of fixed capacity; longer tabulations are processed in chunks, so
+ * the tabulation calls never allocate. */
+int ffc_form_create(const ffc_form_desc* desc, ffc_form** form);
+int ffc_form_get_info(const ffc_form* form, ffc_form_info* info);
+void ffc_form_destroy(ffc_form* form);
+
+/* Enqueue the evaluation of `cells` element tensors on the form's stream and return
+ * (asynchronous).  coords: device SoA as above; coeffs: device SoA or NULL; out: device
+ * buffer of cells * n_I entries, double (FP64 and quadrature) or float (split modes).
+ * cells == 0 is a no-op.  Not safe for concurrent calls on one form (shared workspace). */
+int ffc_tabulate_tensor(const ffc_form* form, int64_t cells, const double* coords, const double* coeffs, void* out);
+
+/* The geometry pass alone (kernel 1 above), for inspection: affine map of each cell as
+ * SoA [1 + d*d][cells] FP64 into caller-owned device memory: row 0 = det J, row
+ * 1 + a*d + b = g_ab = (J^{-1})_ab.  Asynchronous on `stream` (hipStream_t, NULL =
+ * default). */
+int ffc_compute_geometry(int32_t dim, int64_t cells, const double* coords, double* affine_map, void* stream);
+
+/* Mixed batches (many meshes, mixed forms, one persistent launch).  A batch is built
+ * from `n` (form, cells, coords, coeffs, out) items; all forms must share one precision
+ * and use the tensor kernel.  ffc_batch_run enqueues the whole batch as one launch of a
+ * persistent kernel whose workgroups pull (item, cell-tile) work units from an atomic
+ * queue.  The arrays are copied; the device pointers must stay valid while the batch
+ * exists.  The batch owns its device-side work list. */
+typedef struct ffc_batch ffc_batch;
+int ffc_batch_create(int32_t n, const ffc_form* const* forms, const int64_t* cells, const double* const* coords,
+                     const double* const* coeffs, void* const* outs, void* stream, ffc_batch** batch);
+int ffc_batch_run(ffc_batch* batch);
+int ffc_batch_info(const ffc_batch* batch, int64_t* total_cells, int64_t* work_units, int32_t* grid);
+void ffc_batch_destroy(ffc_batch* batch);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* ffc_last_error(void);
+
+/* Library version string. */
+const char* ffc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FFC_HIP_H */

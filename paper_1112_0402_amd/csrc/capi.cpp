@@ -1,0 +1,389 @@
+// C-ABI of libffc_hip: argument checking, the compile step + upload, workspace handling
+// and kernel dispatch.  Declarations and conventions: include/ffc_hip.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/ffc_hip.h"
+#include "kernels.h"
+#include "reference_tensor.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(FFC_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                         \
+    do {                                            \
+        hipError_t _e = (expr);                     \
+        if (_e != hipSuccess) return hip_fail(_e, what); \
+    } while (0)
+
+// A usable device is a gfx950 (MI355X); anything else is refused loudly.
+int check_device(int* device_out) {
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count <= 0) return fail(FFC_E_DEVICE, "no HIP device available");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(FFC_E_DEVICE, std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950");
+    *device_out = dev;
+    return FFC_OK;
+}
+
+template <typename T>
+int upload(const std::vector<T>& host, T** dev) {
+    *dev = nullptr;
+    if (host.empty()) return FFC_OK;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(dev), host.size() * sizeof(T));
+    if (e != hipSuccess) return fail(FFC_E_NOMEM, "hipMalloc failed for form tables");
+    HIP_TRY(hipMemcpy(*dev, host.data(), host.size() * sizeof(T), hipMemcpyHostToDevice), "hipMemcpy");
+    return FFC_OK;
+}
+
+bool valid_tile(int t) { return t == 16 || t == 32 || t == 64; }
+bool valid_waves(int w) { return w == 1 || w == 2 || w == 4 || w == 8; }
+
+int check_desc(const ffc_form_desc* d, ffc::FormSpec* spec) {
+    if (!d) return fail(FFC_E_INVALID, "desc is NULL");
+    spec->kind = d->kind;
+    spec->dim = d->dim;
+    spec->degree = d->degree;
+    spec->lambda = d->lambda;
+    spec->mu = d->mu;
+    std::string why;
+    if (!ffc::supported(*spec, &why)) return fail(FFC_E_UNSUPPORTED, why);
+    if (d->precision < FFC_FP64 || d->precision > FFC_SPLIT_BF16_6)
+        return fail(FFC_E_UNSUPPORTED, "unknown precision");
+    if (d->kernel != FFC_KERNEL_TENSOR && d->kernel != FFC_KERNEL_QUADRATURE)
+        return fail(FFC_E_UNSUPPORTED, "unknown kernel");
+    if (d->kernel == FFC_KERNEL_QUADRATURE && d->precision != FFC_FP64)
+        return fail(FFC_E_UNSUPPORTED, "the quadrature kernel is FP64 only");
+    if (d->tile_cells != 0 && !valid_tile(d->tile_cells)) return fail(FFC_E_INVALID, "tile_cells must be 0, 16, 32 or 64");
+    if (d->waves != 0 && !valid_waves(d->waves)) return fail(FFC_E_INVALID, "waves must be 0, 1, 2, 4 or 8");
+    if (d->reserved != 0) return fail(FFC_E_INVALID, "reserved must be 0");
+    return FFC_OK;
+}
+
+}  // namespace
+
+struct ffc_form {
+    ffc_form_desc desc{};
+    ffc::ReferenceTensor rt;
+    int n_tiles = 0, kpad = 0, n_seg = 0, gpiece[6] = {0, 0, 0, 0, 0, 0};
+    int64_t mfma_k = 0;
+    int tile_cells = 64, waves = 4;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int32_t* d_koff = nullptr;
+    int32_t* d_alpha = nullptr;
+    double* d_b = nullptr;
+    uint16_t* d_bb = nullptr;
+    uint8_t* d_nz = nullptr;
+    double* d_pts = nullptr;
+    double* d_wts = nullptr;
+    double* d_phi = nullptr;
+    double* d_dphi = nullptr;
+    int quad_npts = 0, quad_cpb = 1;
+    double* d_amap = nullptr;
+    int64_t amap_cap = 0;
+
+    ~ffc_form() {
+        for (void* p : {static_cast<void*>(d_koff), static_cast<void*>(d_alpha), static_cast<void*>(d_b),
+                        static_cast<void*>(d_bb), static_cast<void*>(d_nz), static_cast<void*>(d_pts),
+                        static_cast<void*>(d_wts), static_cast<void*>(d_phi), static_cast<void*>(d_dphi),
+                        static_cast<void*>(d_amap)})
+            if (p) (void)hipFree(p);
+    }
+};
+
+extern "C" {
+
+const char* ffc_last_error(void) { return g_last_error.c_str(); }
+
+const char* ffc_version(void) { return "ffc_hip 0.1 (gfx950)"; }
+
+int ffc_compile_reference_tensor(const ffc_form_desc* desc, int64_t* n_I, int64_t* n_alpha, double* A0) {
+    ffc::FormSpec spec;
+    int rc = check_desc(desc, &spec);
+    if (rc) return rc;
+    if (!n_I || !n_alpha) return fail(FFC_E_INVALID, "n_I / n_alpha is NULL");
+    ffc::ReferenceTensor rt;
+    std::string err;
+    if (!ffc::build_reference_tensor(spec, &rt, &err)) return fail(FFC_E_UNSUPPORTED, err);
+    *n_I = rt.n_I;
+    *n_alpha = rt.n_alpha;
+    if (A0) std::memcpy(A0, rt.A0.data(), rt.A0.size() * sizeof(double));
+    return FFC_OK;
+}
+
+int ffc_form_create(const ffc_form_desc* desc, ffc_form** out) {
+    if (!out) return fail(FFC_E_INVALID, "form output pointer is NULL");
+    *out = nullptr;
+    ffc::FormSpec spec;
+    int rc = check_desc(desc, &spec);
+    if (rc) return rc;
+    int dev = 0;
+    rc = check_device(&dev);
+    if (rc) return rc;
+    std::unique_ptr<ffc_form> f(new ffc_form());
+    f->desc = *desc;
+    f->device = dev;
+    f->stream = static_cast<hipStream_t>(desc->stream);
+    f->tile_cells = desc->tile_cells ? desc->tile_cells : 64;
+    f->waves = desc->waves ? desc->waves : 4;
+    std::string err;
+    if (!ffc::build_reference_tensor(spec, &f->rt, &err)) return fail(FFC_E_UNSUPPORTED, err);
+    const ffc::ReferenceTensor& rt = f->rt;
+    if (desc->kernel == FFC_KERNEL_QUADRATURE) {
+        ffc::QuadTables qt = ffc::make_quad_tables(spec);
+        f->quad_npts = qt.npts;
+        f->quad_cpb = ffc::quad_cells_per_block(spec.dim, spec.kind, qt.ns, qt.npts);
+        if ((rc = upload(qt.pts, &f->d_pts)) || (rc = upload(qt.wts, &f->d_wts)) || (rc = upload(qt.phi, &f->d_phi)) ||
+            (rc = upload(qt.dphi, &f->d_dphi)))
+            return rc;
+    } else if (desc->precision == FFC_FP64) {
+        ffc::TilesF64 t = ffc::make_tiles_f64(rt);
+        f->n_tiles = t.n_tiles;
+        f->mfma_k = t.koff.back();
+        if ((rc = upload(t.koff, &f->d_koff)) || (rc = upload(t.alpha, &f->d_alpha)) || (rc = upload(t.b, &f->d_b)))
+            return rc;
+    } else {
+        ffc::TilesBF16 t = ffc::make_tiles_bf16(rt, desc->precision == FFC_SPLIT_BF16_3 ? 3 : 6);
+        f->n_tiles = t.n_tiles;
+        f->kpad = t.kpad;
+        f->n_seg = t.n_seg;
+        std::copy(t.gpiece, t.gpiece + 6, f->gpiece);
+        f->mfma_k = static_cast<int64_t>(t.kpad) * t.n_tiles;
+        if ((rc = upload(t.b, &f->d_bb)) || (rc = upload(t.nonzero, &f->d_nz))) return rc;
+    }
+    if (desc->kernel == FFC_KERNEL_TENSOR) {
+        f->amap_cap = int64_t(1) << 21;
+        const size_t bytes = static_cast<size_t>(f->amap_cap) * (1 + spec.dim * spec.dim) * sizeof(double);
+        if (hipMalloc(reinterpret_cast<void**>(&f->d_amap), bytes) != hipSuccess)
+            return fail(FFC_E_NOMEM, "hipMalloc failed for the geometry workspace");
+        const size_t lds = ffc::contract_lds_bytes(spec.dim, spec.kind, f->tile_cells, rt.n_alpha, f->kpad,
+                                                   desc->precision != FFC_FP64);
+        if (lds > 160 * 1024) return fail(FFC_E_UNSUPPORTED, "tile does not fit the 160 KiB LDS of a CU");
+    }
+    *out = f.release();
+    return FFC_OK;
+}
+
+int ffc_form_get_info(const ffc_form* f, ffc_form_info* info) {
+    if (!f || !info) return fail(FFC_E_INVALID, "NULL argument");
+    const auto& rt = f->rt;
+    const int d = f->desc.dim;
+    info->n_dofs = rt.n;
+    info->n_entries = rt.n_I;
+    info->n_alpha = rt.n_alpha;
+    info->nnz_a0 = rt.nnz;
+    info->n_coords = (d + 1) * d;
+    info->n_coeffs = rt.n_coeff;
+    info->out_bytes = (f->desc.kernel == FFC_KERNEL_TENSOR && f->desc.precision != FFC_FP64) ? 4 : 8;
+    info->mfma_k_per_tile = f->mfma_k;
+    info->n_tiles = f->n_tiles;
+    info->quad_points = f->quad_npts;
+    return FFC_OK;
+}
+
+void ffc_form_destroy(ffc_form* f) { delete f; }
+
+int ffc_compute_geometry(int32_t dim, int64_t cells, const double* coords, double* affine_map, void* stream) {
+    if (dim != 2 && dim != 3) return fail(FFC_E_UNSUPPORTED, "dim must be 2 or 3");
+    if (cells < 0) return fail(FFC_E_INVALID, "cells < 0");
+    if (cells == 0) return FFC_OK;
+    if (!coords || !affine_map) return fail(FFC_E_INVALID, "NULL device pointer");
+    int dev;
+    int rc = check_device(&dev);
+    if (rc) return rc;
+    hipError_t e = ffc::launch_geometry(dim, cells, coords, cells, affine_map, cells, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "geometry kernel launch");
+    return FFC_OK;
+}
+
+int ffc_tabulate_tensor(const ffc_form* f, int64_t cells, const double* coords, const double* coeffs, void* out) {
+    if (!f) return fail(FFC_E_INVALID, "form is NULL");
+    if (cells < 0) return fail(FFC_E_INVALID, "cells < 0");
+    if (cells == 0) return FFC_OK;
+    if (!coords || !out) return fail(FFC_E_INVALID, "coords / out is NULL");
+    const auto& rt = f->rt;
+    if (rt.n_coeff > 0 && !coeffs) return fail(FFC_E_INVALID, "this form needs coefficients (coeffs is NULL)");
+    const int d = f->desc.dim;
+    const int kind = f->desc.kind;
+    if (f->desc.kernel == FFC_KERNEL_QUADRATURE) {
+        ffc::QuadArgs a{};
+        a.cells = cells;
+        a.coords = coords;
+        a.cstride = cells;
+        a.coeffs = coeffs;
+        a.kstride = cells;
+        a.out = static_cast<double*>(out);
+        a.ns = rt.ns;
+        a.n = rt.n;
+        a.n_I = rt.n_I;
+        a.npts = f->quad_npts;
+        a.pts = f->d_pts;
+        a.wts = f->d_wts;
+        a.phi = f->d_phi;
+        a.dphi = f->d_dphi;
+        a.lambda = f->desc.lambda;
+        a.mu = f->desc.mu;
+        a.cells_per_block = f->quad_cpb;
+        hipError_t e = ffc::launch_quadrature(d, kind, a, f->stream);
+        if (e != hipSuccess) return hip_fail(e, "quadrature kernel launch");
+        return FFC_OK;
+    }
+    const bool bf16 = f->desc.precision != FFC_FP64;
+    const size_t obytes = bf16 ? 4 : 8;
+    for (int64_t c0 = 0; c0 < cells; c0 += f->amap_cap) {
+        const int64_t n = std::min(f->amap_cap, cells - c0);
+        hipError_t e = ffc::launch_geometry(d, n, coords + c0, cells, f->d_amap, f->amap_cap, f->stream);
+        if (e != hipSuccess) return hip_fail(e, "geometry kernel launch");
+        ffc::ContractArgs a{};
+        a.cells = n;
+        a.amap = f->d_amap;
+        a.astride = f->amap_cap;
+        a.coeffs = coeffs ? coeffs + c0 : nullptr;
+        a.cstride = cells;
+        a.out = static_cast<char*>(out) + static_cast<size_t>(c0) * rt.n_I * obytes;
+        a.n_I = rt.n_I;
+        a.n_alpha = rt.n_alpha;
+        a.n_tiles = f->n_tiles;
+        a.lambda = f->desc.lambda;
+        a.mu = f->desc.mu;
+        a.koff = f->d_koff;
+        a.alpha = f->d_alpha;
+        a.b = f->d_b;
+        a.bb = f->d_bb;
+        a.nonzero = f->d_nz;
+        a.kpad = f->kpad;
+        a.n_seg = f->n_seg;
+        std::copy(f->gpiece, f->gpiece + 6, a.gpiece);
+        e = bf16 ? ffc::launch_contract_bf16(d, kind, f->tile_cells, f->waves, a, f->stream)
+                 : ffc::launch_contract_f64(d, kind, f->tile_cells, f->waves, a, f->stream);
+        if (e != hipSuccess) return hip_fail(e, "contraction kernel launch");
+    }
+    return FFC_OK;
+}
+
+// ------------------------------------------------------------------ batches ----
+
+struct ffc_batch {
+    std::vector<ffc::BatchItem> items;
+    ffc::BatchItem* d_items = nullptr;
+    int* d_counter = nullptr;
+    int64_t total_cells = 0, total_units = 0;
+    int grid = 0;
+    bool bf16 = false;
+    size_t lds = 0;
+    hipStream_t stream = nullptr;
+    ~ffc_batch() {
+        if (d_items) (void)hipFree(d_items);
+        if (d_counter) (void)hipFree(d_counter);
+    }
+};
+
+int ffc_batch_create(int32_t n, const ffc_form* const* forms, const int64_t* cells, const double* const* coords,
+                     const double* const* coeffs, void* const* outs, void* stream, ffc_batch** out) {
+    if (!out) return fail(FFC_E_INVALID, "batch output pointer is NULL");
+    *out = nullptr;
+    if (n <= 0 || !forms || !cells || !coords || !outs) return fail(FFC_E_INVALID, "empty batch or NULL array");
+    std::unique_ptr<ffc_batch> b(new ffc_batch());
+    b->stream = static_cast<hipStream_t>(stream);
+    int max_alpha = 1, max_kpad = 0;
+    int64_t units = 0;
+    for (int i = 0; i < n; ++i) {
+        const ffc_form* f = forms[i];
+        if (!f) return fail(FFC_E_INVALID, "NULL form in batch");
+        if (f->desc.kernel != FFC_KERNEL_TENSOR) return fail(FFC_E_UNSUPPORTED, "batches use the tensor kernel only");
+        const bool bf = f->desc.precision != FFC_FP64;
+        if (i == 0) b->bf16 = bf;
+        if (bf != b->bf16) return fail(FFC_E_INVALID, "all forms of a batch must share one precision");
+        if (cells[i] < 0) return fail(FFC_E_INVALID, "cells < 0");
+        if (cells[i] > 0 && (!coords[i] || !outs[i])) return fail(FFC_E_INVALID, "NULL coords / out in batch");
+        if (cells[i] > 0 && f->rt.n_coeff > 0 && (!coeffs || !coeffs[i]))
+            return fail(FFC_E_INVALID, "batch item needs coefficients");
+        ffc::BatchItem it{};
+        it.cells = cells[i];
+        it.unit_begin = units;
+        it.coords = coords[i];
+        it.coeffs = coeffs ? coeffs[i] : nullptr;
+        it.out = outs[i];
+        it.dim = f->desc.dim;
+        it.kind = f->desc.kind;
+        it.n_I = f->rt.n_I;
+        it.n_alpha = f->rt.n_alpha;
+        it.n_tiles = f->n_tiles;
+        it.kpad = f->kpad;
+        it.n_seg = f->n_seg;
+        it.n_coeff = f->rt.n_coeff;
+        it.koff = f->d_koff;
+        it.alpha = f->d_alpha;
+        it.b = f->d_b;
+        it.bb = f->d_bb;
+        it.nonzero = f->d_nz;
+        std::copy(f->gpiece, f->gpiece + 6, it.gpiece);
+        units += (cells[i] + 63) / 64;
+        b->total_cells += cells[i];
+        max_alpha = std::max(max_alpha, f->rt.n_alpha);
+        max_kpad = std::max(max_kpad, f->kpad);
+        b->items.push_back(it);
+    }
+    b->total_units = units;
+    b->lds = ffc::batch_lds_bytes(max_alpha, max_kpad, b->bf16);
+    if (b->lds > 160 * 1024) return fail(FFC_E_UNSUPPORTED, "batch tile does not fit LDS");
+    int dev;
+    int rc = check_device(&dev);
+    if (rc) return rc;
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+    const int per_cu = std::max(1, std::min(4, static_cast<int>((160 * 1024) / std::max<size_t>(b->lds, 1))));
+    b->grid = static_cast<int>(std::min<int64_t>(static_cast<int64_t>(prop.multiProcessorCount) * per_cu,
+                                                 std::max<int64_t>(units, 1)));
+    if (hipMalloc(reinterpret_cast<void**>(&b->d_items), n * sizeof(ffc::BatchItem)) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&b->d_counter), 2 * sizeof(int)) != hipSuccess)
+        return fail(FFC_E_NOMEM, "hipMalloc failed for the batch work list");
+    HIP_TRY(hipMemcpy(b->d_items, b->items.data(), n * sizeof(ffc::BatchItem), hipMemcpyHostToDevice), "hipMemcpy");
+    // queue counters start at zero; every run leaves them at zero again (last workgroup out)
+    const int zeros[2] = {0, 0};
+    HIP_TRY(hipMemcpy(b->d_counter, zeros, sizeof(zeros), hipMemcpyHostToDevice), "hipMemcpy");
+    *out = b.release();
+    return FFC_OK;
+}
+
+int ffc_batch_run(ffc_batch* b) {
+    if (!b) return fail(FFC_E_INVALID, "batch is NULL");
+    if (b->total_units == 0) return FFC_OK;
+    hipError_t e = ffc::launch_batch(b->d_items, static_cast<int>(b->items.size()), b->total_units, b->d_counter,
+                                     b->grid, b->bf16, b->lds, b->stream);
+    if (e != hipSuccess) return hip_fail(e, "batch kernel launch");
+    return FFC_OK;
+}
+
+int ffc_batch_info(const ffc_batch* b, int64_t* total_cells, int64_t* work_units, int32_t* grid) {
+    if (!b) return fail(FFC_E_INVALID, "batch is NULL");
+    if (total_cells) *total_cells = b->total_cells;
+    if (work_units) *work_units = b->total_units;
+    if (grid) *grid = b->grid;
+    return FFC_OK;
+}
+
+void ffc_batch_destroy(ffc_batch* b) { delete b; }
+
+}  // extern "C"

@@ -1,0 +1,84 @@
+// Compile step (host, FP64 results from long-double arithmetic): the reference tensor
+// A^0 of each supported form, its tiling for the matrix-core contraction, its BF16
+// split pieces, and the tables of the plain quadrature kernel.
+#pragma once
+
+#include <array>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace ffc {
+
+enum Kind { MASS = 0, LAPLACE = 1, WLAPLACE = 2, ELASTICITY = 3, NS = 4 };
+
+struct FormSpec {
+    int kind = 0, dim = 2, degree = 1;
+    double lambda = 1.0, mu = 1.0;
+};
+
+// Scalar Lagrange basis on K0 in the monomial basis: phi_i(X) = sum_m coef[m][i] X^exp[m].
+struct LagrangeBasis {
+    int dim = 0, degree = 0, n = 0;
+    std::vector<std::array<int, 3>> exps;   // monomials of total degree <= q
+    std::vector<long double> coef;          // [n_mono][n]
+    std::vector<std::array<int, 4>> nodes;  // barycentric multi-indices in dof order
+};
+
+struct ReferenceTensor {
+    FormSpec spec;
+    int ns = 0;       // scalar dofs
+    int n = 0;        // element dofs (d * ns for vector forms)
+    int n_I = 0;      // n * n
+    int n_alpha = 0;  // entries of G_K
+    int n_coeff = 0;  // coefficient doubles per cell
+    int64_t nnz = 0;
+    std::vector<double> A0;  // [n_I][n_alpha]
+};
+
+// Contraction tiles for 16 x 16 x 4 FP64 MFMA: output entries are cut into tiles of 16
+// consecutive entries; each tile keeps only the alpha columns that are nonzero in one of
+// its rows (padded to a multiple of 4 with zero B values).
+struct TilesF64 {
+    int n_tiles = 0;
+    std::vector<int32_t> koff;   // [n_tiles + 1], in k rows
+    std::vector<int32_t> alpha;  // [koff[n_tiles]] alpha index of each k row
+    std::vector<double> b;       // [koff[n_tiles]][16] A^0 values, 0 beyond n_I / padding
+};
+
+// Split-BF16 contraction: concatenated K = n_seg segments of n_alpha, segment s pairs
+// G piece gpiece[s] with A^0 piece apiece[s]; padded to a multiple of 32.
+struct TilesBF16 {
+    int n_tiles = 0;
+    int n_seg = 0;
+    int kpad = 0;                  // padded concatenated K (multiple of 32)
+    int gpiece[6] = {0}, apiece[6] = {0};
+    std::vector<uint16_t> b;       // [n_tiles][kpad / 8][16][8] bf16 bits
+    std::vector<uint8_t> nonzero;  // [n_tiles] 0 if the tile's rows of A^0 are all zero
+};
+
+struct QuadTables {
+    int npts = 0, ns = 0, dim = 0, m = 0;
+    std::vector<double> pts, wts;  // [npts][dim], [npts]
+    std::vector<double> phi;       // [npts][ns]
+    std::vector<double> dphi;      // [npts][ns][dim]
+};
+
+int n_scalar_dofs(int dim, int degree);
+int integrand_degree(int kind, int degree);
+bool supported(const FormSpec& s, std::string* why);
+
+LagrangeBasis make_basis(int dim, int degree);
+bool build_reference_tensor(const FormSpec& s, ReferenceTensor* out, std::string* err);
+TilesF64 make_tiles_f64(const ReferenceTensor& rt);
+TilesBF16 make_tiles_bf16(const ReferenceTensor& rt, int products /* 3 or 6 */);
+QuadTables make_quad_tables(const FormSpec& s);
+
+// Gauss-Jacobi rule for weight (1-x)^a on [0,1], m points (Golub-Welsch).
+void gauss_jacobi01(int m, int a, std::vector<long double>* x, std::vector<long double>* w);
+
+// Round-to-nearest-even of a double to BF16 (returned as the double it represents).
+double round_bf16(double x);
+uint16_t bf16_bits(double representable);
+
+}  // namespace ffc

@@ -1,0 +1,142 @@
+"""Form handles, tabulation and batches over torch CUDA tensors (ctypes marshalling only;
+every step runs in libffc_hip's HIP kernels)."""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import capi
+
+
+def _stream_handle(stream) -> int | None:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _ptr(t: torch.Tensor | None) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _check_tensor(name, t, dtype, shape=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+class Form:
+    """A compiled form on the current device (compile step + upload happen here)."""
+
+    def __init__(self, kind, dim, degree, precision="fp64", kernel="tensor", tile_cells=0, waves=0,
+                 lam=1.0, mu=1.0, stream=None):
+        self.kind, self.dim, self.degree = kind, dim, degree
+        self.precision, self.kernel = precision, kernel
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._desc = capi.make_desc(kind, dim, degree, precision, kernel, tile_cells, waves, lam, mu,
+                                    _stream_handle(self.stream))
+        h = ctypes.c_void_p()
+        capi.check(capi.lib().ffc_form_create(ctypes.byref(self._desc), ctypes.byref(h)))
+        self._h = h
+        info = capi.FormInfo()
+        capi.check(capi.lib().ffc_form_get_info(h, ctypes.byref(info)))
+        self.info = {name: getattr(info, name) for name, _ in capi.FormInfo._fields_}
+        self.n = self.info["n_dofs"]
+        self.n_I = self.info["n_entries"]
+        self.out_dtype = torch.float32 if self.info["out_bytes"] == 4 else torch.float64
+
+    @property
+    def handle(self):
+        return self._h
+
+    def empty_out(self, cells: int) -> torch.Tensor:
+        return torch.empty((cells, self.n, self.n), dtype=self.out_dtype, device="cuda")
+
+    def tabulate(self, coords: torch.Tensor, coeffs: torch.Tensor | None = None,
+                 out: torch.Tensor | None = None) -> torch.Tensor:
+        """Element tensors [cells, n, n] (row = test function), enqueued on the form's stream."""
+        d = self.dim
+        _check_tensor("coords", coords, torch.float64)
+        if coords.dim() != 2 or coords.shape[0] != (d + 1) * d:
+            raise ValueError(f"coords must be [(d+1)*d, cells] = [{(d + 1) * d}, cells]")
+        cells = coords.shape[1]
+        if self.info["n_coeffs"]:
+            if coeffs is None:
+                raise ValueError(f"form {self.kind} needs coefficients [{self.info['n_coeffs']}, cells]")
+            _check_tensor("coeffs", coeffs, torch.float64, (self.info["n_coeffs"], cells))
+        if out is None:
+            out = self.empty_out(cells)
+        _check_tensor("out", out, self.out_dtype)
+        if out.numel() != cells * self.n_I:
+            raise ValueError("out has the wrong number of entries")
+        capi.check(capi.lib().ffc_tabulate_tensor(self._h, cells, _ptr(coords), _ptr(coeffs), _ptr(out)))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            capi.lib().ffc_form_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def compute_geometry(coords: torch.Tensor, dim: int, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Affine map per cell: [1 + d*d, cells] (det J, then g_ab = (J^{-1})_ab)."""
+    _check_tensor("coords", coords, torch.float64)
+    cells = coords.shape[1]
+    if out is None:
+        out = torch.empty((1 + dim * dim, cells), dtype=torch.float64, device=coords.device)
+    _check_tensor("affine_map", out, torch.float64, (1 + dim * dim, cells))
+    capi.check(capi.lib().ffc_compute_geometry(dim, cells, _ptr(coords), _ptr(out), _stream_handle(stream)))
+    return out
+
+
+class Batch:
+    """Many (form, mesh) items evaluated by one persistent launch."""
+
+    def __init__(self, forms, coords, coeffs, outs, stream=None):
+        n = len(forms)
+        self.forms, self.coords, self.coeffs, self.outs = list(forms), list(coords), list(coeffs), list(outs)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        vp = ctypes.c_void_p
+        F = (vp * n)(*[f.handle.value for f in forms])
+        C = (ctypes.c_int64 * n)(*[int(c.shape[1]) for c in coords])
+        X = (vp * n)(*[c.data_ptr() for c in coords])
+        K = (vp * n)(*[(k.data_ptr() if k is not None else None) for k in coeffs])
+        O = (vp * n)(*[o.data_ptr() for o in outs])
+        for f, c, k, o in zip(forms, coords, coeffs, outs):
+            _check_tensor("coords", c, torch.float64)
+            if k is not None:
+                _check_tensor("coeffs", k, torch.float64)
+            _check_tensor("out", o, f.out_dtype)
+            if o.numel() != c.shape[1] * f.n_I:
+                raise ValueError("batch output of the wrong size")
+        h = vp()
+        capi.check(capi.lib().ffc_batch_create(n, F, C, X, K, O, _stream_handle(self.stream), ctypes.byref(h)))
+        self._h = h
+        tc, wu, gr = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+        capi.check(capi.lib().ffc_batch_info(h, ctypes.byref(tc), ctypes.byref(wu), ctypes.byref(gr)))
+        self.total_cells, self.work_units, self.grid = tc.value, wu.value, gr.value
+
+    def run(self):
+        capi.check(capi.lib().ffc_batch_run(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            capi.lib().ffc_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,268 @@
+"""GPU parity: the HIP path (through the C-ABI) against the FP64 oracle, element by
+element, on seeded meshes.  FP64 tensor and quadrature kernels: per-cell relative
+Frobenius error <= 1e-12.  Split-BF16: the measured error is printed per form; the
+6-product split must reach <= 1e-6."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1112_0402_amd import capi, meshgen
+from paper_1112_0402_amd.forms import Batch, Form, compute_geometry
+from tests.gpu_util import rel_fro, require_gpu, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+SPLIT6_TOL = 1e-6
+SPLIT3_BOUND = 1e-4  # sanity bound; the measured value is reported
+
+
+def _small(kind, dim, q, seed=5):
+    # 2D: 2 * 11^2 = 242 cells; 3D: 6 * 5^3 = 750 cells -- several 64-cell tiles plus a
+    # ragged tail
+    n = 11 if dim == 2 else 5
+    return meshgen.make_workload(kind, dim, q, n, seed)
+
+
+ALL_FORMS = [("mass", d, q) for d in (2, 3) for q in (1, 2, 3, 4)] \
+    + [("laplace", d, q) for d in (2, 3) for q in (1, 2, 3, 4)] \
+    + [("wlaplace", 2, q) for q in (1, 2, 3, 4)] + [("wlaplace", 3, q) for q in (1, 2, 3)] \
+    + [("elasticity", d, q) for d in (2, 3) for q in (1, 2, 3)] \
+    + [("ns", d, q) for d in (2, 3) for q in (1, 2, 3)]
+
+
+def _run(form, wl):
+    X = to_dev(wl.coords)
+    C = to_dev(wl.coeffs)
+    out = form.tabulate(X, C)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("kind,dim,q", ALL_FORMS)
+@pytest.mark.parametrize("kernel", ["tensor", "quadrature"])
+def test_fp64_parity_small(kind, dim, q, kernel):
+    require_gpu()
+    say(f"[parity] {kernel} fp64 {kind} d={dim} q={q}")
+    wl = _small(kind, dim, q)
+    ref = oracle.tabulate(kind, dim, q, wl.coords, wl.coeffs)
+    got = _run(Form(kind, dim, q, kernel=kernel), wl)
+    emax, emed = rel_fro(got, ref)
+    say(f"    max {emax:.2e} median {emed:.2e}")
+    assert emax <= FP64_TOL
+
+
+@pytest.mark.parametrize("tile_cells,waves", [(16, 1), (32, 2), (64, 8), (16, 4)])
+def test_fp64_launch_shapes(tile_cells, waves):
+    require_gpu()
+    wl = _small("elasticity", 3, 2)
+    ref = oracle.tabulate("elasticity", 3, 2, wl.coords)
+    got = _run(Form("elasticity", 3, 2, tile_cells=tile_cells, waves=waves), wl)
+    assert rel_fro(got, ref)[0] <= FP64_TOL
+
+
+@pytest.mark.parametrize("kind,dim,q", [("laplace", 2, 1), ("mass", 3, 3), ("laplace", 3, 4), ("wlaplace", 3, 3),
+                                        ("elasticity", 3, 2), ("ns", 3, 2), ("ns", 2, 2), ("mass", 2, 2)])
+@pytest.mark.parametrize("precision", ["bf16x3", "bf16x6"])
+def test_split_bf16_parity_small(kind, dim, q, precision):
+    require_gpu()
+    wl = _small(kind, dim, q)
+    ref = oracle.tabulate(kind, dim, q, wl.coords, wl.coeffs)
+    got = _run(Form(kind, dim, q, precision=precision), wl)
+    assert got.dtype == np.float32
+    emax, emed = rel_fro(got, ref)
+    say(f"[split] {precision} {kind} d={dim} q={q}: max {emax:.2e} median {emed:.2e}")
+    assert emax <= (SPLIT6_TOL if precision == "bf16x6" else SPLIT3_BOUND)
+
+
+# ---------------------------------------------------------------- full sizes ---
+
+def _sample(cells, k, seed):
+    rng = np.random.default_rng(seed)
+    idx = np.unique(np.concatenate([[0, 1, cells - 2, cells - 1], rng.choice(cells, size=k, replace=False)]))
+    return idx
+
+
+def test_config1_full_mesh():
+    """2D Poisson P1, 64 x 64 squares -> 8192 cells: every cell against the oracle."""
+    require_gpu()
+    wl = meshgen.config1()
+    assert wl.cells == 8192
+    ref = oracle.tabulate("laplace", 2, 1, wl.coords)
+    for kernel in ("tensor", "quadrature"):
+        got = _run(Form("laplace", 2, 1, kernel=kernel), wl)
+        emax, emed = rel_fro(got, ref)
+        say(f"[cfg1] {kernel}: max {emax:.2e} median {emed:.2e}")
+        assert emax <= FP64_TOL
+
+
+def test_config2_full_size_sampled():
+    """3D elasticity vector P2, 750,000 cells, default launch shape (the benchmarked one):
+    3000 sampled cells against the oracle, and two runs bitwise identical."""
+    require_gpu()
+    wl = meshgen.config2()
+    assert wl.cells == 750_000
+    X = to_dev(wl.coords)
+    f = Form("elasticity", 3, 2)
+    out1 = f.tabulate(X)
+    out2 = f.tabulate(X)
+    torch.cuda.synchronize()
+    assert torch.equal(out1, out2)
+    idx = _sample(wl.cells, 3000, 2)
+    ref = oracle.tabulate("elasticity", 3, 2, wl.coords[:, idx])
+    emax, emed = rel_fro(out1[torch.from_numpy(idx).cuda()].cpu().numpy(), ref)
+    say(f"[cfg2] tensor fp64 sampled: max {emax:.2e} median {emed:.2e}")
+    assert emax <= FP64_TOL
+    q = Form("elasticity", 3, 2, kernel="quadrature").tabulate(X)
+    torch.cuda.synchronize()
+    emax, emed = rel_fro(q[torch.from_numpy(idx).cuda()].cpu().numpy(), ref)
+    say(f"[cfg2] quadrature fp64 sampled: max {emax:.2e} median {emed:.2e}")
+    assert emax <= FP64_TOL
+
+
+@pytest.mark.parametrize("precision", ["bf16x3", "bf16x6"])
+def test_config3_full_size_sampled(precision):
+    """3D weighted Laplacian P3, w in P1 ~ U(0.5, 2), 1,500,282 cells, split BF16 with
+    FP32 accumulation: 2000 sampled cells against the oracle."""
+    require_gpu()
+    wl = meshgen.config3()
+    assert wl.cells == 1_500_282
+    X, C = to_dev(wl.coords), to_dev(wl.coeffs)
+    out = Form("wlaplace", 3, 3, precision=precision).tabulate(X, C)
+    torch.cuda.synchronize()
+    idx = _sample(wl.cells, 2000, 3)
+    ref = oracle.tabulate("wlaplace", 3, 3, wl.coords[:, idx], wl.coeffs[:, idx])
+    emax, emed = rel_fro(out[torch.from_numpy(idx).cuda()].cpu().numpy(), ref)
+    say(f"[cfg3] {precision}: max {emax:.2e} median {emed:.2e}")
+    assert emax <= (SPLIT6_TOL if precision == "bf16x6" else SPLIT3_BOUND)
+
+
+def test_chunked_tabulation_beyond_workspace():
+    """More cells than the geometry workspace holds (2^21): processed in chunks."""
+    require_gpu()
+    wl = meshgen.make_workload("mass", 2, 1, 1030, 8)  # 2,121,800 cells
+    assert wl.cells > (1 << 21)
+    out = Form("mass", 2, 1).tabulate(to_dev(wl.coords))
+    torch.cuda.synchronize()
+    idx = np.unique(np.concatenate([_sample(wl.cells, 1000, 4), np.arange((1 << 21) - 3, (1 << 21) + 3)]))
+    ref = oracle.tabulate("mass", 2, 1, wl.coords[:, idx])
+    assert rel_fro(out[torch.from_numpy(idx).cuda()].cpu().numpy(), ref)[0] <= FP64_TOL
+
+
+# ---------------------------------------------------------------- edge cases ---
+
+def test_edge_cases():
+    require_gpu()
+    f = Form("wlaplace", 3, 2)
+    # zero cells: no-op
+    X0 = torch.empty((12, 0), dtype=torch.float64, device="cuda")
+    C0 = torch.empty((4, 0), dtype=torch.float64, device="cuda")
+    assert f.tabulate(X0, C0).shape == (0, 10, 10)
+    # one cell
+    wl = _small("wlaplace", 3, 2)
+    X1 = to_dev(wl.coords[:, :1])
+    C1 = to_dev(wl.coeffs[:, :1])
+    got = f.tabulate(X1, C1).cpu().numpy()
+    ref = oracle.tabulate("wlaplace", 3, 2, wl.coords[:, :1], wl.coeffs[:, :1])
+    assert rel_fro(got, ref)[0] <= FP64_TOL
+    # missing coefficients are refused before anything is enqueued
+    with pytest.raises(ValueError):
+        f.tabulate(X1)
+    L = capi.lib()
+    out = torch.empty((1, 10, 10), dtype=torch.float64, device="cuda")
+    assert L.ffc_tabulate_tensor(f.handle, 1, X1.data_ptr(), None, out.data_ptr()) == capi.FFC_E_INVALID
+    assert L.ffc_tabulate_tensor(f.handle, -1, X1.data_ptr(), C1.data_ptr(), out.data_ptr()) == capi.FFC_E_INVALID
+
+
+def test_geometry_pass():
+    require_gpu()
+    for dim in (2, 3):
+        wl = _small("mass", dim, 1)
+        am = compute_geometry(to_dev(wl.coords), dim).cpu().numpy()
+        cells = wl.cells
+        Xv = wl.coords.T.reshape(cells, dim + 1, dim)
+        J = np.transpose(Xv[:, 1:, :] - Xv[:, :1, :], (0, 2, 1))
+        assert np.allclose(am[0], np.linalg.det(J), rtol=1e-13, atol=0)
+        assert np.allclose(am[1:].T.reshape(cells, dim, dim), np.linalg.inv(J), rtol=1e-12, atol=1e-12)
+
+
+def test_degenerate_orientation_reversed_cells():
+    """Negatively oriented cells: |det J| enters, results match the oracle."""
+    require_gpu()
+    wl = _small("laplace", 3, 2)
+    c = wl.coords.reshape(4, 3, -1)[[0, 2, 1, 3]].reshape(12, -1)  # swap vertices 1, 2
+    c = np.ascontiguousarray(c)
+    ref = oracle.tabulate("laplace", 3, 2, c)
+    for kernel in ("tensor", "quadrature"):
+        got = _run(Form("laplace", 3, 2, kernel=kernel), meshgen.Workload("laplace", 3, 2, c, None))
+        assert rel_fro(got, ref)[0] <= FP64_TOL
+
+
+# ------------------------------------------------------------------- batches ---
+
+def _batch_inputs(precision, scale):
+    wls = meshgen.config4(scale=scale)
+    forms = {}
+    for wl in wls:
+        key = (wl.kind, wl.dim, wl.degree)
+        if key not in forms:
+            forms[key] = Form(wl.kind, wl.dim, wl.degree, precision=precision)
+    return wls, forms
+
+
+@pytest.mark.parametrize("precision", ["fp64", "bf16x3"])
+def test_persistent_batch_matches_oracle_and_single_calls(precision):
+    require_gpu()
+    wls, forms = _batch_inputs(precision, scale=0.004)
+    fl = [forms[(w.kind, w.dim, w.degree)] for w in wls]
+    X = [to_dev(w.coords) for w in wls]
+    C = [to_dev(w.coeffs) for w in wls]
+    outs = [f.empty_out(w.cells).zero_() for f, w in zip(fl, wls)]
+    b = Batch(fl, X, C, outs)
+    say(f"[batch] {precision}: {len(wls)} meshes, {b.total_cells} cells, {b.work_units} units, grid {b.grid}")
+    b.run()
+    torch.cuda.synchronize()
+    first = [o.clone() for o in outs]
+    for o in outs:
+        o.zero_()
+    b.run()  # counters reset themselves: a second run gives the same result
+    torch.cuda.synchronize()
+    tol = FP64_TOL if precision == "fp64" else SPLIT3_BOUND
+    for w, f, x, c, o, o1 in zip(wls, fl, X, C, outs, first):
+        assert torch.equal(o, o1)
+        single = f.tabulate(x, c)
+        torch.cuda.synchronize()
+        ref = oracle.tabulate(w.kind, w.dim, w.degree, w.coords, w.coeffs)
+        e_b = rel_fro(o.cpu().numpy(), ref)[0]
+        e_s = rel_fro(single.cpu().numpy(), ref)[0]
+        assert e_b <= tol, (w.name, e_b)
+        assert e_s <= tol, (w.name, e_s)
+
+
+def test_batch_graph_replay():
+    """The persistent launch captured in a graph and replayed several times, with eager
+    work and synchronisations between replays: every replay equals the eager result."""
+    require_gpu()
+    wls, forms = _batch_inputs("fp64", scale=0.002)
+    fl = [forms[(w.kind, w.dim, w.degree)] for w in wls]
+    X = [to_dev(w.coords) for w in wls]
+    C = [to_dev(w.coeffs) for w in wls]
+    outs = [f.empty_out(w.cells) for f, w in zip(fl, wls)]
+    s = torch.cuda.Stream()
+    b = Batch(fl, X, C, outs, stream=s)
+    with torch.cuda.stream(s):
+        b.run()
+    torch.cuda.synchronize()
+    eager = [o.clone() for o in outs]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        b.run()
+    for rep in range(3):
+        for o in outs:
+            o.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for o, e in zip(outs, eager):
+            assert torch.equal(o, e), rep
