@@ -204,7 +204,9 @@ __device__ __forceinline__ void stage_tile_from_coords(const double* __restrict_
 // so the 16 lanes reading one alpha column hit distinct banks), then every 16-entry output
 // tile on the wave that owns it (tile t on wave t mod waves).
 // MFMA operands: lane = 16*kq + r holds A[r][kq] = G[cell r][alpha of k row kq] and
-// B[kq][r] = A^0[entry r][that alpha]; result lane holds rows 4*kq .. 4*kq+3, column r.
+// B[kq][r] = A^0[entry r][that alpha]; the 4 results of lane 16*kq + r are rows
+// kq, kq + 4, kq + 8, kq + 12 of column r (the FP64 16x16x4 result layout on gfx950,
+// which interleaves rows unlike the BF16 instruction below).
 
 template <int D, int KIND, int MT>
 __device__ __forceinline__ void contract_tile_f64(const double* am, const double* cf, double* Gs, int64_t c0,
@@ -241,7 +243,7 @@ __device__ __forceinline__ void contract_tile_f64(const double* am, const double
             for (int m = 0; m < MT; ++m)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const int64_t cell = c0 + m * 16 + lk * 4 + i;
+                    const int64_t cell = c0 + m * 16 + i * 4 + lk;
                     if (cell < cells) __builtin_nontemporal_store(acc[m][i], &out[cell * nI + e]);
                 }
         }
@@ -322,6 +324,7 @@ __device__ __forceinline__ unsigned short bf16_of(double representable) {
 // Gp[c][s * n_alpha + alpha] = piece gpiece[s] of G[c][alpha]; row stride kpad + 8.
 // MFMA operands: lane = 16*kq + r holds 8 consecutive K values kq*8 .. kq*8+7 of row r of
 // the G tile (A) and of column r of the A^0 tile (B); the same K order on both sides.
+// The 4 results of lane 16*kq + r are rows 4*kq .. 4*kq + 3 of column r.
 template <int D, int KIND, int MT, int NSEG>
 __device__ __forceinline__ void contract_tile_bf16(const double* am, const double* cf, unsigned short* Gp, int64_t c0,
                                                    int64_t cells, int nI, int n_tiles, int kpad, const int* gpiece,
