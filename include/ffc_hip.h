@@ -88,6 +88,14 @@ typedef struct {
     int32_t kernel;      /* ffc_kernel */
     int32_t tile_cells;  /* cells per workgroup tile of the contraction: 0 = default, else 16, 32 or 64 */
     int32_t waves;       /* waves per workgroup of the contraction: 0 = default, else 1, 2, 4 or 8 */
+    int32_t tile_window; /* FP64 tensor kernel: grouping of the n_I output entries into the
+                            16-entry MFMA tiles.  0 = default; 16 = consecutive entries; a
+                            multiple of 16 = rows clustered greedily (smallest union of nonzero
+                            A^0 columns) inside windows of that many consecutive entries;
+                            -1 = clustered over all entries.  Ignored by the other kernels. */
+    int32_t persistent;  /* FP64 tensor kernel: 0 = auto (persistent workgroups with the A^0
+                            tiles in registers whenever they fit), 1 = the same, -1 = one
+                            workgroup per cell tile */
     int32_t reserved;    /* must be 0 */
     double lambda, mu;   /* Lame parameters (FFC_ELASTICITY only) */
     void* stream;        /* hipStream_t the form's work is enqueued on; NULL = default stream */
@@ -101,9 +109,15 @@ typedef struct {
     int64_t n_coords;         /* (d + 1) * d doubles per cell */
     int64_t n_coeffs;         /* coefficient doubles per cell (0 if none) */
     int64_t out_bytes;        /* bytes per output entry: 8 (FP64) or 4 (split modes) */
-    int64_t mfma_k_per_tile;  /* sum over 16-entry output tiles of the padded contraction length */
+    int64_t mfma_k_per_tile;  /* sum over the 16-entry output tiles of their padded contraction
+                                 length: one tile of 16 cells executes mfma_k_per_tile * 512
+                                 FP64 MFMA flops (split modes: * 512 BF16 flops) */
     int64_t n_tiles;          /* 16-entry output tiles */
     int64_t quad_points;      /* points of the quadrature kernel's rule */
+    int64_t persistent_waves; /* waves of the persistent FP64 contraction (0 = not used) */
+    int64_t persistent_kmax;  /* register-resident k steps per wave of that kernel */
+    int64_t tile_cells;       /* cells per workgroup tile of the contraction */
+    int64_t waves;            /* waves per workgroup of the (non-persistent) contraction */
 } ffc_form_info;
 
 /* Compile step only, host only, touches no device: the reference tensor A^0 of the form
@@ -132,6 +146,15 @@ void ffc_form_destroy(ffc_form* form);
  * buffer of cells * n_I entries, double (FP64 and quadrature) or float (split modes).
  * cells == 0 is a no-op.  Not safe for concurrent calls on one form (shared workspace). */
 int ffc_tabulate_tensor(const ffc_form* form, int64_t cells, const double* coords, const double* coeffs, void* out);
+
+/* The contraction alone (kernel 2 above) from a precomputed affine map: affine_map is
+ * the device SoA [1 + d*d][cells] that ffc_compute_geometry writes (row 0 = det J, row
+ * 1 + a*d + b = g_ab).  Lets several forms on one mesh share one geometry pass (the
+ * paper's eval reads the same AffineMap for every form, Sec. 5.4).  Tensor kernel only
+ * (FFC_E_INVALID for a quadrature form).  Same asynchrony and layouts as
+ * ffc_tabulate_tensor. */
+int ffc_tabulate_tensor_affine(const ffc_form* form, int64_t cells, const double* affine_map, const double* coeffs,
+                               void* out);
 
 /* The geometry pass alone (kernel 1 above), for inspection: affine map of each cell as
  * SoA [1 + d*d][cells] FP64 into caller-owned device memory: row 0 = det J, row

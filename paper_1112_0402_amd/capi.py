@@ -34,6 +34,8 @@ class FormDesc(ctypes.Structure):
         ("kernel", ctypes.c_int32),
         ("tile_cells", ctypes.c_int32),
         ("waves", ctypes.c_int32),
+        ("tile_window", ctypes.c_int32),
+        ("persistent", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
         ("lambda_", ctypes.c_double),
         ("mu", ctypes.c_double),
@@ -44,7 +46,8 @@ class FormDesc(ctypes.Structure):
 class FormInfo(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in (
         "n_dofs", "n_entries", "n_alpha", "nnz_a0", "n_coords", "n_coeffs", "out_bytes",
-        "mfma_k_per_tile", "n_tiles", "quad_points")]
+        "mfma_k_per_tile", "n_tiles", "quad_points", "persistent_waves", "persistent_kmax", "tile_cells",
+        "waves")]
 
 
 class FFCError(RuntimeError):
@@ -75,6 +78,7 @@ def lib():
     L.ffc_form_destroy.argtypes = [vp]
     L.ffc_form_destroy.restype = None
     L.ffc_tabulate_tensor.argtypes = [vp, i64, vp, vp, vp]
+    L.ffc_tabulate_tensor_affine.argtypes = [vp, i64, vp, vp, vp]
     L.ffc_compute_geometry.argtypes = [i32, i64, vp, vp, vp]
     L.ffc_batch_create.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(i64), ctypes.POINTER(vp),
                                    ctypes.POINTER(vp), ctypes.POINTER(vp), vp, ctypes.POINTER(vp)]
@@ -83,6 +87,7 @@ def lib():
     L.ffc_batch_destroy.argtypes = [vp]
     L.ffc_batch_destroy.restype = None
     for name in ("ffc_compile_reference_tensor", "ffc_form_create", "ffc_form_get_info", "ffc_tabulate_tensor",
+                 "ffc_tabulate_tensor_affine",
                  "ffc_compute_geometry", "ffc_batch_create", "ffc_batch_run", "ffc_batch_info"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -95,7 +100,7 @@ def check(rc: int) -> None:
 
 
 def make_desc(kind, dim, degree, precision="fp64", kernel="tensor", tile_cells=0, waves=0,
-              lam=1.0, mu=1.0, stream=None) -> FormDesc:
+              lam=1.0, mu=1.0, stream=None, tile_window=0, persistent=0) -> FormDesc:
     d = FormDesc()
     d.kind = KINDS[kind] if isinstance(kind, str) else int(kind)
     d.dim = dim
@@ -104,6 +109,8 @@ def make_desc(kind, dim, degree, precision="fp64", kernel="tensor", tile_cells=0
     d.kernel = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
     d.tile_cells = tile_cells
     d.waves = waves
+    d.tile_window = tile_window
+    d.persistent = persistent
     d.reserved = 0
     d.lambda_ = lam
     d.mu = mu

@@ -57,7 +57,10 @@ int upload(const std::vector<T>& host, T** dev) {
 }
 
 bool valid_tile(int t) { return t == 16 || t == 32 || t == 64; }
-bool valid_waves(int w) { return w == 1 || w == 2 || w == 4 || w == 8; }
+
+// default grouping of output entries into FP64 MFMA tiles: greedy clustering over all rows
+constexpr int kDefaultTileWindow = -1;
+bool valid_waves(int w) { return w == 1 || w == 2 || w == 4 || w == 8 || w == 16; }
 
 int check_desc(const ffc_form_desc* d, ffc::FormSpec* spec) {
     if (!d) return fail(FFC_E_INVALID, "desc is NULL");
@@ -75,8 +78,11 @@ int check_desc(const ffc_form_desc* d, ffc::FormSpec* spec) {
     if (d->kernel == FFC_KERNEL_QUADRATURE && d->precision != FFC_FP64)
         return fail(FFC_E_UNSUPPORTED, "the quadrature kernel is FP64 only");
     if (d->tile_cells != 0 && !valid_tile(d->tile_cells)) return fail(FFC_E_INVALID, "tile_cells must be 0, 16, 32 or 64");
-    if (d->waves != 0 && !valid_waves(d->waves)) return fail(FFC_E_INVALID, "waves must be 0, 1, 2, 4 or 8");
+    if (d->waves != 0 && !valid_waves(d->waves)) return fail(FFC_E_INVALID, "waves must be 0, 1, 2, 4, 8 or 16");
     if (d->reserved != 0) return fail(FFC_E_INVALID, "reserved must be 0");
+    if (d->persistent < -1 || d->persistent > 1) return fail(FFC_E_INVALID, "persistent must be -1, 0 or 1");
+    if (d->tile_window != 0 && d->tile_window != -1 && (d->tile_window < 16 || d->tile_window % 16 != 0))
+        return fail(FFC_E_INVALID, "tile_window must be 0, -1 or a positive multiple of 16");
     return FFC_OK;
 }
 
@@ -90,8 +96,10 @@ struct ffc_form {
     int tile_cells = 64, waves = 4;
     hipStream_t stream = nullptr;
     int device = 0;
+    int tile_window = -1;
     int32_t* d_koff = nullptr;
-    int32_t* d_alpha = nullptr;
+    uint32_t* d_apack = nullptr;
+    int32_t* d_entry = nullptr;
     double* d_b = nullptr;
     uint16_t* d_bb = nullptr;
     uint8_t* d_nz = nullptr;
@@ -102,12 +110,21 @@ struct ffc_form {
     int quad_npts = 0, quad_cpb = 1;
     double* d_amap = nullptr;
     int64_t amap_cap = 0;
+    // persistent FP64 contraction
+    int pwaves = 0, pkmax = 0, pgrid = 0, n_zero = 0;
+    int32_t* d_woff = nullptr;
+    int32_t* d_step_kstep = nullptr;
+    int32_t* d_step_end = nullptr;
+    int32_t* d_zero = nullptr;
 
     ~ffc_form() {
-        for (void* p : {static_cast<void*>(d_koff), static_cast<void*>(d_alpha), static_cast<void*>(d_b),
+        for (void* p : {static_cast<void*>(d_koff), static_cast<void*>(d_apack), static_cast<void*>(d_entry),
+                        static_cast<void*>(d_b),
                         static_cast<void*>(d_bb), static_cast<void*>(d_nz), static_cast<void*>(d_pts),
                         static_cast<void*>(d_wts), static_cast<void*>(d_phi), static_cast<void*>(d_dphi),
-                        static_cast<void*>(d_amap)})
+                        static_cast<void*>(d_amap), static_cast<void*>(d_woff),
+                        static_cast<void*>(d_step_kstep), static_cast<void*>(d_step_end),
+                        static_cast<void*>(d_zero)})
             if (p) (void)hipFree(p);
     }
 };
@@ -145,8 +162,8 @@ int ffc_form_create(const ffc_form_desc* desc, ffc_form** out) {
     f->desc = *desc;
     f->device = dev;
     f->stream = static_cast<hipStream_t>(desc->stream);
-    f->tile_cells = desc->tile_cells ? desc->tile_cells : 64;
-    f->waves = desc->waves ? desc->waves : 4;
+    f->tile_cells = desc->tile_cells;
+    f->waves = desc->waves;
     std::string err;
     if (!ffc::build_reference_tensor(spec, &f->rt, &err)) return fail(FFC_E_UNSUPPORTED, err);
     const ffc::ReferenceTensor& rt = f->rt;
@@ -158,11 +175,41 @@ int ffc_form_create(const ffc_form_desc* desc, ffc_form** out) {
             (rc = upload(qt.dphi, &f->d_dphi)))
             return rc;
     } else if (desc->precision == FFC_FP64) {
-        ffc::TilesF64 t = ffc::make_tiles_f64(rt);
+        f->tile_window = desc->tile_window ? desc->tile_window : kDefaultTileWindow;
+        ffc::TilesF64 t = ffc::make_tiles_f64(rt, f->tile_window);
         f->n_tiles = t.n_tiles;
         f->mfma_k = t.koff.back();
-        if ((rc = upload(t.koff, &f->d_koff)) || (rc = upload(t.alpha, &f->d_alpha)) || (rc = upload(t.b, &f->d_b)))
+        if ((rc = upload(t.koff, &f->d_koff)) || (rc = upload(t.apack, &f->d_apack)) ||
+            (rc = upload(t.entry, &f->d_entry)) || (rc = upload(t.b, &f->d_b)))
             return rc;
+        // persistent workgroups: 16 waves with up to 16 register-resident k steps each, or
+        // 8 waves with up to 32; the 16-cell output rows must be stageable in LDS
+        const ffc::LdsPlan pl = ffc::plan_lds(spec.dim, spec.kind, 16, rt.n_I, rt.n_alpha, 0, false, ffc::kLdsBudget);
+        if (desc->persistent >= 0 && pl.staged && (desc->tile_cells == 0 || desc->tile_cells == 16)) {
+            ffc::WaveSchedule ws;
+            for (int w : {16}) {
+                if (desc->waves != 0 && desc->waves != w) continue;
+                ffc::WaveSchedule cand = ffc::make_wave_schedule(t, w - ffc::kIoWaves);
+                if (cand.max_steps <= 24 && 16 * static_cast<int64_t>(rt.n_I) / 2 <=
+                                                static_cast<int64_t>(ffc::kIoSlots - 1) * 64 * ffc::kIoWaves) {
+                    ws = cand;
+                    ws.waves = w;
+                    break;
+                }
+            }
+            if (ws.waves > 0) {
+                f->pwaves = ws.waves;
+                f->pkmax = ws.max_steps <= 8 ? 8 : ws.max_steps <= 16 ? 16 : 24;
+                f->n_zero = static_cast<int>(ws.zero_entries.size());
+                if ((rc = upload(ws.woff, &f->d_woff)) || (rc = upload(ws.step_kstep, &f->d_step_kstep)) ||
+                    (rc = upload(ws.step_end, &f->d_step_end)) || (rc = upload(ws.zero_entries, &f->d_zero)))
+                    return rc;
+                hipDeviceProp_t prop;
+                HIP_TRY(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+                const int per_cu = std::max(1, static_cast<int>((160 * 1024) / pl.total));
+                f->pgrid = prop.multiProcessorCount * std::min(per_cu, 2);
+            }
+        }
     } else {
         ffc::TilesBF16 t = ffc::make_tiles_bf16(rt, desc->precision == FFC_SPLIT_BF16_3 ? 3 : 6);
         f->n_tiles = t.n_tiles;
@@ -177,9 +224,23 @@ int ffc_form_create(const ffc_form_desc* desc, ffc_form** out) {
         const size_t bytes = static_cast<size_t>(f->amap_cap) * (1 + spec.dim * spec.dim) * sizeof(double);
         if (hipMalloc(reinterpret_cast<void**>(&f->d_amap), bytes) != hipSuccess)
             return fail(FFC_E_NOMEM, "hipMalloc failed for the geometry workspace");
-        const size_t lds = ffc::contract_lds_bytes(spec.dim, spec.kind, f->tile_cells, rt.n_alpha, f->kpad,
-                                                   desc->precision != FFC_FP64);
-        if (lds > 160 * 1024) return fail(FFC_E_UNSUPPORTED, "tile does not fit the 160 KiB LDS of a CU");
+        // default launch shape: the largest cell tile whose output rows can be staged in LDS
+        // (contiguous full-line writes), 16 waves for 16-cell tiles, 8 otherwise; with no
+        // staging possible, 64-cell tiles with direct stores.
+        const bool bf = desc->precision != FFC_FP64;
+        if (f->tile_cells == 0) {
+            f->tile_cells = 64;
+            for (int ct : {64, 32, 16}) {
+                ffc::LdsPlan p = ffc::plan_lds(spec.dim, spec.kind, ct, rt.n_I, rt.n_alpha, f->kpad, bf, ffc::kLdsBudget);
+                if (p.staged && p.total <= (ct == 16 ? ffc::kLdsBudget : ffc::kLdsBudget / 2 + 8192)) {
+                    f->tile_cells = ct;
+                    break;
+                }
+            }
+        }
+        if (f->waves == 0) f->waves = f->tile_cells == 16 ? 16 : 8;
+        const size_t lds = ffc::contract_lds_bytes(spec.dim, spec.kind, f->tile_cells, rt.n_I, rt.n_alpha, f->kpad, bf);
+        if (lds > ffc::kLdsBudget) return fail(FFC_E_UNSUPPORTED, "tile does not fit the 160 KiB LDS of a CU");
     }
     *out = f.release();
     return FFC_OK;
@@ -199,6 +260,10 @@ int ffc_form_get_info(const ffc_form* f, ffc_form_info* info) {
     info->mfma_k_per_tile = f->mfma_k;
     info->n_tiles = f->n_tiles;
     info->quad_points = f->quad_npts;
+    info->persistent_waves = f->pwaves;
+    info->persistent_kmax = f->pkmax;
+    info->tile_cells = f->tile_cells;
+    info->waves = f->waves;
     return FFC_OK;
 }
 
@@ -215,6 +280,56 @@ int ffc_compute_geometry(int32_t dim, int64_t cells, const double* coords, doubl
     hipError_t e = ffc::launch_geometry(dim, cells, coords, cells, affine_map, cells, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "geometry kernel launch");
     return FFC_OK;
+}
+
+namespace {
+// contraction of cells [0, n) whose affine map sits at amap with row stride astride
+int contract_chunk(const ffc_form* f, int64_t n, const double* amap, int64_t astride, const double* coeffs,
+                   int64_t cstride, void* out) {
+    const auto& rt = f->rt;
+    const bool bf16 = f->desc.precision != FFC_FP64;
+    ffc::ContractArgs a{};
+    a.cells = n;
+    a.amap = amap;
+    a.astride = astride;
+    a.coeffs = coeffs;
+    a.cstride = cstride;
+    a.out = out;
+    a.n_I = rt.n_I;
+    a.n_alpha = rt.n_alpha;
+    a.n_tiles = f->n_tiles;
+    a.lambda = f->desc.lambda;
+    a.mu = f->desc.mu;
+    a.koff = f->d_koff;
+    a.apack = f->d_apack;
+    a.entry = f->d_entry;
+    a.b = f->d_b;
+    a.bb = f->d_bb;
+    a.nonzero = f->d_nz;
+    a.kpad = f->kpad;
+    a.n_seg = f->n_seg;
+    std::copy(f->gpiece, f->gpiece + 6, a.gpiece);
+    hipError_t e = hipErrorInvalidValue;
+    if (f->pwaves > 0) {
+        ffc::PersistArgs p{f->d_woff, f->d_step_kstep, f->d_step_end, f->d_zero, f->n_zero};
+        e = ffc::launch_contract_persistent(f->desc.dim, f->desc.kind, f->pkmax, f->pwaves, f->pgrid, a, p, f->stream);
+    }
+    if (e == hipErrorInvalidValue)
+        e = ffc::launch_contract(f->desc.dim, f->desc.kind, bf16, f->tile_cells, f->waves, a, f->stream);
+    if (e != hipSuccess) return hip_fail(e, "contraction kernel launch");
+    return FFC_OK;
+}
+}  // namespace
+
+int ffc_tabulate_tensor_affine(const ffc_form* f, int64_t cells, const double* affine_map, const double* coeffs,
+                               void* out) {
+    if (!f) return fail(FFC_E_INVALID, "form is NULL");
+    if (f->desc.kernel != FFC_KERNEL_TENSOR) return fail(FFC_E_INVALID, "not a tensor-kernel form");
+    if (cells < 0) return fail(FFC_E_INVALID, "cells < 0");
+    if (cells == 0) return FFC_OK;
+    if (!affine_map || !out) return fail(FFC_E_INVALID, "affine_map / out is NULL");
+    if (f->rt.n_coeff > 0 && !coeffs) return fail(FFC_E_INVALID, "this form needs coefficients (coeffs is NULL)");
+    return contract_chunk(f, cells, affine_map, cells, coeffs, cells, out);
 }
 
 int ffc_tabulate_tensor(const ffc_form* f, int64_t cells, const double* coords, const double* coeffs, void* out) {
@@ -255,29 +370,9 @@ int ffc_tabulate_tensor(const ffc_form* f, int64_t cells, const double* coords, 
         const int64_t n = std::min(f->amap_cap, cells - c0);
         hipError_t e = ffc::launch_geometry(d, n, coords + c0, cells, f->d_amap, f->amap_cap, f->stream);
         if (e != hipSuccess) return hip_fail(e, "geometry kernel launch");
-        ffc::ContractArgs a{};
-        a.cells = n;
-        a.amap = f->d_amap;
-        a.astride = f->amap_cap;
-        a.coeffs = coeffs ? coeffs + c0 : nullptr;
-        a.cstride = cells;
-        a.out = static_cast<char*>(out) + static_cast<size_t>(c0) * rt.n_I * obytes;
-        a.n_I = rt.n_I;
-        a.n_alpha = rt.n_alpha;
-        a.n_tiles = f->n_tiles;
-        a.lambda = f->desc.lambda;
-        a.mu = f->desc.mu;
-        a.koff = f->d_koff;
-        a.alpha = f->d_alpha;
-        a.b = f->d_b;
-        a.bb = f->d_bb;
-        a.nonzero = f->d_nz;
-        a.kpad = f->kpad;
-        a.n_seg = f->n_seg;
-        std::copy(f->gpiece, f->gpiece + 6, a.gpiece);
-        e = bf16 ? ffc::launch_contract_bf16(d, kind, f->tile_cells, f->waves, a, f->stream)
-                 : ffc::launch_contract_f64(d, kind, f->tile_cells, f->waves, a, f->stream);
-        if (e != hipSuccess) return hip_fail(e, "contraction kernel launch");
+        int rc = contract_chunk(f, n, f->d_amap, f->amap_cap, coeffs ? coeffs + c0 : nullptr, cells,
+                                static_cast<char*>(out) + static_cast<size_t>(c0) * rt.n_I * obytes);
+        if (rc) return rc;
     }
     return FFC_OK;
 }
@@ -291,7 +386,7 @@ struct ffc_batch {
     int64_t total_cells = 0, total_units = 0;
     int grid = 0;
     bool bf16 = false;
-    size_t lds = 0;
+    size_t lds = 0, stage_cap = 0;
     hipStream_t stream = nullptr;
     ~ffc_batch() {
         if (d_items) (void)hipFree(d_items);
@@ -334,28 +429,37 @@ int ffc_batch_create(int32_t n, const ffc_form* const* forms, const int64_t* cel
         it.n_seg = f->n_seg;
         it.n_coeff = f->rt.n_coeff;
         it.koff = f->d_koff;
-        it.alpha = f->d_alpha;
+        it.apack = f->d_apack;
+        it.entry = f->d_entry;
         it.b = f->d_b;
         it.bb = f->d_bb;
         it.nonzero = f->d_nz;
         std::copy(f->gpiece, f->gpiece + 6, it.gpiece);
-        units += (cells[i] + 63) / 64;
+        units += (cells[i] + ffc::kBatchCT - 1) / ffc::kBatchCT;
         b->total_cells += cells[i];
         max_alpha = std::max(max_alpha, f->rt.n_alpha);
         max_kpad = std::max(max_kpad, f->kpad);
         b->items.push_back(it);
     }
     b->total_units = units;
-    b->lds = ffc::batch_lds_bytes(max_alpha, max_kpad, b->bf16);
-    if (b->lds > 160 * 1024) return fail(FFC_E_UNSUPPORTED, "batch tile does not fit LDS");
+    // stage the outputs of every item whose 16 rows fit next to the largest G tile
+    int stage_nI = 0;
+    for (const auto& it : b->items)
+        if (ffc::batch_lds_bytes(max_alpha, max_kpad, it.n_I, b->bf16) <= ffc::kLdsBudget)
+            stage_nI = std::max(stage_nI, static_cast<int>(it.n_I));
+    b->lds = ffc::batch_lds_bytes(max_alpha, max_kpad, stage_nI, b->bf16);
+    b->stage_cap = ffc::batch_lds_bytes(max_alpha, max_kpad, stage_nI, b->bf16) -
+                   ffc::batch_lds_bytes(max_alpha, max_kpad, 0, b->bf16);
+    if (b->lds > ffc::kLdsBudget) return fail(FFC_E_UNSUPPORTED, "batch tile does not fit LDS");
     int dev;
     int rc = check_device(&dev);
     if (rc) return rc;
     hipDeviceProp_t prop;
     HIP_TRY(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
-    const int per_cu = std::max(1, std::min(4, static_cast<int>((160 * 1024) / std::max<size_t>(b->lds, 1))));
+    const int per_cu = std::max(1, std::min(2, static_cast<int>((160 * 1024) / std::max<size_t>(b->lds, 1))));
+    const int64_t claims = (units + ffc::kBatchChunk - 1) / ffc::kBatchChunk;
     b->grid = static_cast<int>(std::min<int64_t>(static_cast<int64_t>(prop.multiProcessorCount) * per_cu,
-                                                 std::max<int64_t>(units, 1)));
+                                                 std::max<int64_t>(claims, 1)));
     if (hipMalloc(reinterpret_cast<void**>(&b->d_items), n * sizeof(ffc::BatchItem)) != hipSuccess ||
         hipMalloc(reinterpret_cast<void**>(&b->d_counter), 2 * sizeof(int)) != hipSuccess)
         return fail(FFC_E_NOMEM, "hipMalloc failed for the batch work list");
@@ -371,7 +475,7 @@ int ffc_batch_run(ffc_batch* b) {
     if (!b) return fail(FFC_E_INVALID, "batch is NULL");
     if (b->total_units == 0) return FFC_OK;
     hipError_t e = ffc::launch_batch(b->d_items, static_cast<int>(b->items.size()), b->total_units, b->d_counter,
-                                     b->grid, b->bf16, b->lds, b->stream);
+                                     b->grid, b->bf16, b->lds, b->stage_cap, b->stream);
     if (e != hipSuccess) return hip_fail(e, "batch kernel launch");
     return FFC_OK;
 }

@@ -24,6 +24,9 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 enum { K_MASS = 0, K_LAPLACE = 1, K_WLAPLACE = 2, K_ELASTICITY = 3, K_NS = 4 };
 
@@ -199,19 +202,70 @@ __device__ __forceinline__ void stage_tile_from_coords(const double* __restrict_
     }
 }
 
+// ------------------------------------------------------ LDS plan and output write ---
+// LDS of a contraction workgroup, in order (each part 16-byte aligned):
+//   st   [CT][n_I] output values (double, or float in split modes) -- staged plans only
+//   am   [1 + D*D][CT] affine map,  cf [n_coeff][CT] coefficients
+//   G    FP64: [CT][n_alpha | 1] doubles;  split: [CT][kpad + 8] BF16 pieces
+// A staged workgroup writes its whole output region -- CT consecutive cells, i.e. one
+// contiguous run of CT * n_I values -- with 16-byte stores once every tile is done, so the
+// HBM sees full aligned lines in streaming order whatever the order of the tiles.
+
+__host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
+
+__host__ __device__ inline int n_coeff_of(int dim, int kind) {
+    return kind == K_WLAPLACE ? dim + 1 : kind == K_NS ? dim * (dim + 1) : 0;
+}
+
+LdsPlan plan_lds(int dim, int kind, int tile_cells, int n_I, int n_alpha, int kpad, bool bf16, size_t budget) {
+    LdsPlan p{};
+    const size_t ob = bf16 ? sizeof(float) : sizeof(double);
+    p.stage_bytes = align16(static_cast<size_t>(tile_cells) * n_I * ob);
+    const size_t head = align16(static_cast<size_t>(1 + dim * dim + n_coeff_of(dim, kind)) * tile_cells * sizeof(double));
+    const size_t g = bf16 ? static_cast<size_t>(tile_cells) * (kpad + 8) * sizeof(uint16_t)
+                          : static_cast<size_t>(tile_cells) * (n_alpha | 1) * sizeof(double);
+    p.head_bytes = head;
+    p.g_bytes = align16(g);
+    p.staged = p.stage_bytes + head + p.g_bytes <= budget;
+    if (!p.staged) p.stage_bytes = 0;
+    p.total = p.stage_bytes + head + p.g_bytes;
+    return p;
+}
+
+size_t contract_lds_bytes(int dim, int kind, int tile_cells, int n_I, int n_alpha, int kpad, bool bf16) {
+    return plan_lds(dim, kind, tile_cells, n_I, n_alpha, kpad, bf16, kLdsBudget).total;
+}
+
+// Flat copy of n staged values to global memory (out 16-byte aligned) with 16-byte stores.
+template <typename T>
+__device__ __forceinline__ void write_region(const T* __restrict__ st, T* __restrict__ out, int64_t n) {
+    constexpr int V = 16 / sizeof(T);
+    typedef T vec __attribute__((ext_vector_type(V)));
+    const int64_t nv = n / V;
+    const vec* s = reinterpret_cast<const vec*>(st);
+    vec* o = reinterpret_cast<vec*>(out);
+    for (int64_t i = threadIdx.x; i < nv; i += blockDim.x) o[i] = s[i];
+    for (int64_t i = nv * V + threadIdx.x; i < n; i += blockDim.x) out[i] = st[i];
+}
+
 // ----------------------------------------------------------- FP64 contraction ---
 // One cell tile of CT = 16*MT cells: G tile into LDS (row stride GS = n_alpha | 1, odd,
 // so the 16 lanes reading one alpha column hit distinct banks), then every 16-entry output
-// tile on the wave that owns it (tile t on wave t mod waves).
+// tile on the wave that owns it (tile t on wave t mod waves; tile loops are wave-uniform).
 // MFMA operands: lane = 16*kq + r holds A[r][kq] = G[cell r][alpha of k row kq] and
-// B[kq][r] = A^0[entry r][that alpha]; the 4 results of lane 16*kq + r are rows
+// B[kq][r] = A^0[entry of column r][that alpha]; the 4 results of lane 16*kq + r are rows
 // kq, kq + 4, kq + 8, kq + 12 of column r (the FP64 16x16x4 result layout on gfx950,
 // which interleaves rows unlike the BF16 instruction below).
+// Per k step: one scalar load of the 4 packed alpha indices and one 8-byte B load per
+// lane, both fetched one step ahead; the MT LDS reads are issued before the MT MFMAs.
+// Results go to the staging rows st (then one contiguous write of the whole tile), or
+// straight to global memory when the tile's output does not fit in LDS (st == nullptr).
 
 template <int D, int KIND, int MT>
-__device__ __forceinline__ void contract_tile_f64(const double* am, const double* cf, double* Gs, int64_t c0,
-                                                  int64_t cells, int nI, int n_tiles, const int32_t* __restrict__ koff,
-                                                  const int32_t* __restrict__ alpha, const double* __restrict__ bvals,
+__device__ __forceinline__ void contract_tile_f64(const double* am, const double* cf, double* Gs, double* st,
+                                                  int64_t c0, int64_t cells, int nI, int n_tiles,
+                                                  const int32_t* __restrict__ koff, const uint32_t* __restrict__ apack,
+                                                  const int32_t* __restrict__ entry, const double* __restrict__ bvals,
                                                   double* __restrict__ out) {
     using FT = FormTraits<KIND, D>;
     constexpr int CT = 16 * MT;
@@ -223,60 +277,80 @@ __device__ __forceinline__ void contract_tile_f64(const double* am, const double
     }
     __syncthreads();
     const int waves = blockDim.x >> 6;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     const int lr = lane & 15, lk = lane >> 4;
+    const double* grow = Gs + lr * GS;
     for (int t = wave; t < n_tiles; t += waves) {
         d4 acc[MT];
 #pragma unroll
         for (int m = 0; m < MT; ++m) acc[m] = d4{0.0, 0.0, 0.0, 0.0};
-        const int k0 = koff[t], k1 = koff[t + 1];
-        for (int k = k0; k < k1; k += 4) {
-            const int al = alpha[k + lk];
-            const double bv = bvals[static_cast<int64_t>(k + lk) * 16 + lr];
-#pragma unroll
-            for (int m = 0; m < MT; ++m)
-                acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(Gs[(m * 16 + lr) * GS + al], bv, acc[m], 0, 0, 0);
-        }
-        const int e = t * 16 + lr;
-        if (e < nI) {
-#pragma unroll
-            for (int m = 0; m < MT; ++m)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int64_t cell = c0 + m * 16 + i * 4 + lk;
-                    if (cell < cells) __builtin_nontemporal_store(acc[m][i], &out[cell * nI + e]);
+        const int k0 = koff[t];
+        const int nk = (koff[t + 1] - k0) >> 2;
+        const int e = entry[t * 16 + lr];
+        if (nk > 0) {
+            const uint32_t* ap = apack + (k0 >> 2);
+            const double* bp = bvals + static_cast<int64_t>(k0 + lk) * 16 + lr;
+            double bnext = bp[0];
+            uint32_t wnext = ap[0];
+            for (int kk = 0; kk < nk; ++kk) {
+                const double bcur = bnext;
+                const uint32_t w = wnext;
+                if (kk + 1 < nk) {
+                    bnext = bp[(kk + 1) * 64];
+                    wnext = ap[kk + 1];
                 }
+                const int al = (w >> (8 * lk)) & 0xff;
+                double av[MT];
+#pragma unroll
+                for (int m = 0; m < MT; ++m) av[m] = grow[m * 16 * GS + al];
+#pragma unroll
+                for (int m = 0; m < MT; ++m) acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[m], bcur, acc[m], 0, 0, 0);
+            }
         }
+        if (e >= 0) {
+            if (st) {
+#pragma unroll
+                for (int m = 0; m < MT; ++m)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) st[(m * 16 + i * 4 + lk) * nI + e] = acc[m][i];
+            } else {
+#pragma unroll
+                for (int m = 0; m < MT; ++m)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int64_t cell = c0 + m * 16 + i * 4 + lk;
+                        if (cell < cells) out[cell * nI + e] = acc[m][i];
+                    }
+            }
+        }
+    }
+    if (st) {
+        __syncthreads();
+        const int64_t nc = cells - c0 < CT ? cells - c0 : CT;
+        write_region(st, out + c0 * nI, nc * nI);
     }
 }
 
 template <int D, int KIND, int MT>
-__global__ __launch_bounds__(512) void contract_f64_kernel(ContractArgs A) {
+__global__ __launch_bounds__(1024) void contract_f64_kernel(ContractArgs A) {
     using FT = FormTraits<KIND, D>;
     constexpr int CT = 16 * MT;
     constexpr int NC = FT::n_coeff;
-    extern __shared__ double smem[];
-    double* am = smem;
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    double* st = A.staged ? reinterpret_cast<double*>(smem_raw) : nullptr;
+    double* am = reinterpret_cast<double*>(smem_raw + A.stage_bytes);
     double* cf = am + (1 + D * D) * CT;
-    double* Gs = cf + NC * CT;
+    double* Gs = reinterpret_cast<double*>(smem_raw + A.stage_bytes + A.head_bytes);
     const int64_t c0 = static_cast<int64_t>(blockIdx.x) * CT;
     stage_tile<D, NC>(A, c0, CT, am, cf);
     __syncthreads();
-    contract_tile_f64<D, KIND, MT>(am, cf, Gs, c0, A.cells, A.n_I, A.n_tiles, A.koff, A.alpha, A.b,
+    contract_tile_f64<D, KIND, MT>(am, cf, Gs, st, c0, A.cells, A.n_I, A.n_tiles, A.koff, A.apack, A.entry, A.b,
                                    static_cast<double*>(A.out));
 }
 
-size_t contract_lds_bytes(int dim, int kind, int tile_cells, int n_alpha, int kpad, bool bf16) {
-    const int nc = kind == K_WLAPLACE ? dim + 1 : kind == K_NS ? dim * (dim + 1) : 0;
-    size_t head = static_cast<size_t>((1 + dim * dim) + nc) * tile_cells * sizeof(double);
-    if (!bf16) return head + static_cast<size_t>(tile_cells) * (n_alpha | 1) * sizeof(double);
-    return head + static_cast<size_t>(tile_cells) * (kpad + 8) * sizeof(uint16_t);
-}
-
 template <int D, int KIND>
-static hipError_t launch_f64_mt(int tile_cells, int waves, const ContractArgs& a, hipStream_t s) {
-    const int nA = FormTraits<KIND, D>::n_alpha;
-    const size_t lds = contract_lds_bytes(D, KIND, tile_cells, nA, 0, false);
+static hipError_t launch_f64_mt(int tile_cells, int waves, size_t lds, const ContractArgs& a, hipStream_t s) {
     const unsigned grid = static_cast<unsigned>((a.cells + tile_cells - 1) / tile_cells);
     const unsigned block = 64u * waves;
     switch (tile_cells) {
@@ -287,21 +361,14 @@ static hipError_t launch_f64_mt(int tile_cells, int waves, const ContractArgs& a
 }
 
 template <int D>
-static hipError_t launch_f64_d(int kind, int tile_cells, int waves, const ContractArgs& a, hipStream_t s) {
+static hipError_t launch_f64_d(int kind, int tile_cells, int waves, size_t lds, const ContractArgs& a, hipStream_t s) {
     switch (kind) {
-    case K_MASS: return launch_f64_mt<D, K_MASS>(tile_cells, waves, a, s);
-    case K_LAPLACE: return launch_f64_mt<D, K_LAPLACE>(tile_cells, waves, a, s);
-    case K_WLAPLACE: return launch_f64_mt<D, K_WLAPLACE>(tile_cells, waves, a, s);
-    case K_ELASTICITY: return launch_f64_mt<D, K_ELASTICITY>(tile_cells, waves, a, s);
-    default: return launch_f64_mt<D, K_NS>(tile_cells, waves, a, s);
+    case K_MASS: return launch_f64_mt<D, K_MASS>(tile_cells, waves, lds, a, s);
+    case K_LAPLACE: return launch_f64_mt<D, K_LAPLACE>(tile_cells, waves, lds, a, s);
+    case K_WLAPLACE: return launch_f64_mt<D, K_WLAPLACE>(tile_cells, waves, lds, a, s);
+    case K_ELASTICITY: return launch_f64_mt<D, K_ELASTICITY>(tile_cells, waves, lds, a, s);
+    default: return launch_f64_mt<D, K_NS>(tile_cells, waves, lds, a, s);
     }
-}
-
-hipError_t launch_contract_f64(int dim, int kind, int tile_cells, int waves, const ContractArgs& a,
-                               hipStream_t stream) {
-    if (a.cells <= 0) return hipSuccess;
-    return dim == 2 ? launch_f64_d<2>(kind, tile_cells, waves, a, stream)
-                    : launch_f64_d<3>(kind, tile_cells, waves, a, stream);
 }
 
 // ----------------------------------------------------------- BF16 contraction ---
@@ -326,9 +393,9 @@ __device__ __forceinline__ unsigned short bf16_of(double representable) {
 // the G tile (A) and of column r of the A^0 tile (B); the same K order on both sides.
 // The 4 results of lane 16*kq + r are rows 4*kq .. 4*kq + 3 of column r.
 template <int D, int KIND, int MT, int NSEG>
-__device__ __forceinline__ void contract_tile_bf16(const double* am, const double* cf, unsigned short* Gp, int64_t c0,
-                                                   int64_t cells, int nI, int n_tiles, int kpad, const int* gpiece,
-                                                   const uint16_t* __restrict__ bb,
+__device__ __forceinline__ void contract_tile_bf16(const double* am, const double* cf, unsigned short* Gp, float* st,
+                                                   int64_t c0, int64_t cells, int nI, int n_tiles, int kpad,
+                                                   const int* gpiece, const uint16_t* __restrict__ bb,
                                                    const uint8_t* __restrict__ nonzero, float* __restrict__ out) {
     using FT = FormTraits<KIND, D>;
     constexpr int CT = 16 * MT;
@@ -351,57 +418,73 @@ __device__ __forceinline__ void contract_tile_bf16(const double* am, const doubl
     }
     __syncthreads();
     const int waves = blockDim.x >> 6;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     const int lr = lane & 15, lk = lane >> 4;
     const int kchunks = kpad / 32;
+    const unsigned short* grow = Gp + lr * KS + lk * 8;
     for (int t = wave; t < n_tiles; t += waves) {
         f4 acc[MT];
 #pragma unroll
         for (int m = 0; m < MT; ++m) acc[m] = f4{0.f, 0.f, 0.f, 0.f};
         if (nonzero[t]) {
-            const u16x8* bt = reinterpret_cast<const u16x8*>(bb) + static_cast<int64_t>(t) * (kpad / 8) * 16;
+            const u16x8* bt = reinterpret_cast<const u16x8*>(bb) + static_cast<int64_t>(t) * (kpad / 8) * 16 + lk * 16 + lr;
+            u16x8 bnext = bt[0];
             for (int kc = 0; kc < kchunks; ++kc) {
-                const bf8 bv = __builtin_bit_cast(bf8, bt[(kc * 4 + lk) * 16 + lr]);
+                const bf8 bv = __builtin_bit_cast(bf8, bnext);
+                if (kc + 1 < kchunks) bnext = bt[(kc + 1) * 64];
+                u16x8 av[MT];
 #pragma unroll
-                for (int m = 0; m < MT; ++m) {
-                    const u16x8 av = *reinterpret_cast<const u16x8*>(&Gp[(m * 16 + lr) * KS + kc * 32 + lk * 8]);
-                    acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, av), bv, acc[m], 0, 0, 0);
-                }
+                for (int m = 0; m < MT; ++m) av[m] = *reinterpret_cast<const u16x8*>(grow + m * 16 * KS + kc * 32);
+#pragma unroll
+                for (int m = 0; m < MT; ++m)
+                    acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, av[m]), bv, acc[m], 0, 0, 0);
             }
         }
         const int e = t * 16 + lr;
         if (e < nI) {
+            if (st) {
 #pragma unroll
-            for (int m = 0; m < MT; ++m)
+                for (int m = 0; m < MT; ++m)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int64_t cell = c0 + m * 16 + lk * 4 + i;
-                    if (cell < cells) __builtin_nontemporal_store(acc[m][i], &out[cell * nI + e]);
-                }
+                    for (int i = 0; i < 4; ++i) st[(m * 16 + lk * 4 + i) * nI + e] = acc[m][i];
+            } else {
+#pragma unroll
+                for (int m = 0; m < MT; ++m)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int64_t cell = c0 + m * 16 + lk * 4 + i;
+                        if (cell < cells) out[cell * nI + e] = acc[m][i];
+                    }
+            }
         }
+    }
+    if (st) {
+        __syncthreads();
+        const int64_t nc = cells - c0 < CT ? cells - c0 : CT;
+        write_region(st, out + c0 * nI, nc * nI);
     }
 }
 
 template <int D, int KIND, int MT, int NSEG>
-__global__ __launch_bounds__(512) void contract_bf16_kernel(ContractArgs A) {
+__global__ __launch_bounds__(1024) void contract_bf16_kernel(ContractArgs A) {
     using FT = FormTraits<KIND, D>;
     constexpr int CT = 16 * MT;
     constexpr int NC = FT::n_coeff;
-    extern __shared__ double smem[];
-    double* am = smem;
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    float* st = A.staged ? reinterpret_cast<float*>(smem_raw) : nullptr;
+    double* am = reinterpret_cast<double*>(smem_raw + A.stage_bytes);
     double* cf = am + (1 + D * D) * CT;
-    unsigned short* Gp = reinterpret_cast<unsigned short*>(cf + NC * CT);
+    unsigned short* Gp = reinterpret_cast<unsigned short*>(smem_raw + A.stage_bytes + A.head_bytes);
     const int64_t c0 = static_cast<int64_t>(blockIdx.x) * CT;
     stage_tile<D, NC>(A, c0, CT, am, cf);
     __syncthreads();
-    contract_tile_bf16<D, KIND, MT, NSEG>(am, cf, Gp, c0, A.cells, A.n_I, A.n_tiles, A.kpad, A.gpiece, A.bb, A.nonzero,
-                                          static_cast<float*>(A.out));
+    contract_tile_bf16<D, KIND, MT, NSEG>(am, cf, Gp, st, c0, A.cells, A.n_I, A.n_tiles, A.kpad, A.gpiece, A.bb,
+                                          A.nonzero, static_cast<float*>(A.out));
 }
 
 template <int D, int KIND, int NSEG>
-static hipError_t launch_bf16_mt(int tile_cells, int waves, const ContractArgs& a, hipStream_t s) {
-    const int nA = FormTraits<KIND, D>::n_alpha;
-    const size_t lds = contract_lds_bytes(D, KIND, tile_cells, nA, a.kpad, true);
+static hipError_t launch_bf16_mt(int tile_cells, int waves, size_t lds, const ContractArgs& a, hipStream_t s) {
     const unsigned grid = static_cast<unsigned>((a.cells + tile_cells - 1) / tile_cells);
     const unsigned block = 64u * waves;
     switch (tile_cells) {
@@ -412,106 +495,333 @@ static hipError_t launch_bf16_mt(int tile_cells, int waves, const ContractArgs& 
 }
 
 template <int D, int NSEG>
-static hipError_t launch_bf16_d(int kind, int tile_cells, int waves, const ContractArgs& a, hipStream_t s) {
+static hipError_t launch_bf16_d(int kind, int tile_cells, int waves, size_t lds, const ContractArgs& a, hipStream_t s) {
     switch (kind) {
-    case K_MASS: return launch_bf16_mt<D, K_MASS, NSEG>(tile_cells, waves, a, s);
-    case K_LAPLACE: return launch_bf16_mt<D, K_LAPLACE, NSEG>(tile_cells, waves, a, s);
-    case K_WLAPLACE: return launch_bf16_mt<D, K_WLAPLACE, NSEG>(tile_cells, waves, a, s);
-    case K_ELASTICITY: return launch_bf16_mt<D, K_ELASTICITY, NSEG>(tile_cells, waves, a, s);
-    default: return launch_bf16_mt<D, K_NS, NSEG>(tile_cells, waves, a, s);
+    case K_MASS: return launch_bf16_mt<D, K_MASS, NSEG>(tile_cells, waves, lds, a, s);
+    case K_LAPLACE: return launch_bf16_mt<D, K_LAPLACE, NSEG>(tile_cells, waves, lds, a, s);
+    case K_WLAPLACE: return launch_bf16_mt<D, K_WLAPLACE, NSEG>(tile_cells, waves, lds, a, s);
+    case K_ELASTICITY: return launch_bf16_mt<D, K_ELASTICITY, NSEG>(tile_cells, waves, lds, a, s);
+    default: return launch_bf16_mt<D, K_NS, NSEG>(tile_cells, waves, lds, a, s);
     }
 }
 
-hipError_t launch_contract_bf16(int dim, int kind, int tile_cells, int waves, const ContractArgs& a,
-                                hipStream_t stream) {
+// Plans the LDS of the launch (staging the output when it fits and `out` is 16-byte
+// aligned) and launches the FP64 or split-BF16 contraction.
+hipError_t launch_contract(int dim, int kind, bool bf16, int tile_cells, int waves, ContractArgs a,
+                           hipStream_t stream) {
     if (a.cells <= 0) return hipSuccess;
+    LdsPlan p = plan_lds(dim, kind, tile_cells, a.n_I, a.n_alpha, a.kpad, bf16, kLdsBudget);
+    if (p.staged && (reinterpret_cast<uintptr_t>(a.out) & 15u) != 0) {
+        p = plan_lds(dim, kind, tile_cells, a.n_I, a.n_alpha, a.kpad, bf16, 0);  // unaligned output: direct stores
+        p.total = p.head_bytes + p.g_bytes;
+    }
+    a.staged = p.staged ? 1 : 0;
+    a.stage_bytes = p.stage_bytes;
+    a.head_bytes = p.head_bytes;
+    if (!bf16) return dim == 2 ? launch_f64_d<2>(kind, tile_cells, waves, p.total, a, stream)
+                               : launch_f64_d<3>(kind, tile_cells, waves, p.total, a, stream);
     if (a.n_seg == 3)
-        return dim == 2 ? launch_bf16_d<2, 3>(kind, tile_cells, waves, a, stream)
-                        : launch_bf16_d<3, 3>(kind, tile_cells, waves, a, stream);
-    return dim == 2 ? launch_bf16_d<2, 6>(kind, tile_cells, waves, a, stream)
-                    : launch_bf16_d<3, 6>(kind, tile_cells, waves, a, stream);
+        return dim == 2 ? launch_bf16_d<2, 3>(kind, tile_cells, waves, p.total, a, stream)
+                        : launch_bf16_d<3, 3>(kind, tile_cells, waves, p.total, a, stream);
+    return dim == 2 ? launch_bf16_d<2, 6>(kind, tile_cells, waves, p.total, a, stream)
+                    : launch_bf16_d<3, 6>(kind, tile_cells, waves, p.total, a, stream);
+}
+
+// ------------------------------------------------------ persistent FP64 contraction ---
+// Every 16-cell tile of a mesh runs the same contraction, so a persistent workgroup keeps
+// it in registers: wave w owns a fixed set of the A^0 tiles (balanced by k steps on the
+// host) and holds, per k step s, its B fragment breg[s] and one packed word preg[s] = LDS
+// column of its alpha | (output entry of its column + 1) << 8 (the entry only at the last
+// step of a tile, which bit s of the wave-uniform endmask flags).
+// Per cell tile: affine map (prefetched one tile ahead in registers) -> LDS, G tile and the
+// zero entries, then the MFMA chain straight from LDS and registers into the staged output
+// rows, then one contiguous write of the 16 rows.
+
+// Barrier for LDS traffic only: waits for this wave's LDS operations, then s_barrier.
+// Unlike __syncthreads() it leaves global stores in flight, so the write-out of one cell
+// tile overlaps the contraction of the next.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0); vmcnt and expcnt left at their maxima
+    __builtin_amdgcn_s_barrier();
+}
+
+template <int D, int KIND, int KMAX, int MAXT, int IOS>
+__global__ __launch_bounds__(MAXT) void contract_f64_persistent(ContractArgs A, PersistArgs P) {
+    using FT = FormTraits<KIND, D>;
+    constexpr int CT = 16;
+    constexpr int NA = FT::n_alpha;
+    constexpr int NC = FT::n_coeff;
+    constexpr int GS = NA | 1;
+    constexpr int ROWS = 1 + D * D + NC;
+    // One register file, two uses (the compiler cannot see that a wave only ever takes one
+    // role, so separate arrays would both count): a compute lane keeps the B fragment of
+    // step s in R[2s], R[2s+1] and its packed word in R[2*KMAX + s]; an I/O lane keeps
+    // 16-byte slot j of a staged tile in R[4j .. 4j+3].
+    constexpr int NR = (3 * KMAX > 4 * IOS) ? 3 * KMAX : 4 * IOS;
+    // Wave roles: the first blockDim/64 - kIoWaves waves ("compute waves") prefetch the next
+    // tile's affine map and coefficients and run the MFMA steps; the last kIoWaves waves
+    // move the staged output to global memory and nothing else.  A wave that has stores in
+    // flight must wait for them before reusing their source registers, so keeping stores
+    // out of the compute waves lets the write-out of one tile overlap the next contraction.
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    double* st = reinterpret_cast<double*>(smem_raw);
+    double* am = reinterpret_cast<double*>(smem_raw + A.stage_bytes);  // [ROWS][CT]: map rows, then coefficients
+    double* cf = am + (1 + D * D) * CT;
+    double* Gs = reinterpret_cast<double*>(smem_raw + A.stage_bytes + A.head_bytes);
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int nI = A.n_I;
+    const int io_begin = blockDim.x - 64 * kIoWaves;
+    const int io_lane = tid - io_begin;
+    const int n_compute = (blockDim.x >> 6) - kIoWaves;
+    const int s0 = wave < n_compute ? P.woff[wave] : 0;
+    const int ns = wave < n_compute ? P.woff[wave + 1] - s0 : 0;
+
+    uint32_t R[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) R[r] = 0;
+    uint32_t endmask = 0;
+#pragma unroll
+    for (int s = 0; s < KMAX; ++s) {
+        if (s < ns) {
+            const int ks = P.step_kstep[s0 + s];
+            const u32x2 bw = __builtin_bit_cast(u32x2, A.b[(static_cast<int64_t>(ks) * 4 + lk) * 16 + lr]);
+            R[2 * s] = bw[0];
+            R[2 * s + 1] = bw[1];
+            uint32_t word = (A.apack[ks] >> (8 * lk)) & 0xffu;
+            const int t = P.step_end[s0 + s];
+            if (t >= 0) {
+                endmask |= 1u << s;
+                word |= static_cast<uint32_t>(A.entry[t * 16 + lr] + 1) << 8;
+            }
+            R[2 * KMAX + s] = word;
+        }
+    }
+    endmask = __builtin_amdgcn_readfirstlane(endmask);
+
+    const int64_t ntiles = (A.cells + CT - 1) / CT;
+    // thread r*CT + c (r < ROWS) fetches row r of cell c: affine map, then coefficients
+    auto fetch = [&](int64_t ct) -> double {
+        const int r = tid / CT, c = tid - (tid / CT) * CT;
+        const int64_t cell = ct * CT + c;
+        if (cell >= A.cells) return r == 0 ? 1.0 : 0.0;
+        return r < 1 + D * D ? A.amap[r * A.astride + cell] : A.coeffs[(r - 1 - D * D) * A.cstride + cell];
+    };
+    double pre = 0.0;
+    int64_t ct = blockIdx.x;
+    if (tid < ROWS * CT && ct < ntiles) pre = fetch(ct);
+    const double* grow = Gs + lr * GS;
+    int64_t io_c0 = -1, io_n = 0;
+    // I/O lanes: store the tile held in R (slot j -> 16-byte pair io_lane + j * 64 * kIoWaves;
+    // an odd last value rides in the last slot of lane 0, which the host keeps unused)
+    auto io_store = [&]() {
+        double* o = static_cast<double*>(A.out) + io_c0 * nI;
+        const int64_t nv = io_n / 2;
+        const int jn = nv > io_lane ? static_cast<int>((nv - io_lane + 64 * kIoWaves - 1) / (64 * kIoWaves)) : 0;
+        d2v* ov = reinterpret_cast<d2v*>(o) + io_lane;
+#pragma unroll
+        for (int j = 0; j < IOS; ++j) {
+            if (j < jn) *ov = __builtin_bit_cast(d2v, u32x4{R[4 * j], R[4 * j + 1], R[4 * j + 2], R[4 * j + 3]});
+            ov += 64 * kIoWaves;
+        }
+        if ((io_n & 1) && io_lane == 0)
+            o[io_n - 1] = __builtin_bit_cast(double, u32x2{R[4 * (IOS - 1)], R[4 * (IOS - 1) + 1]});
+    };
+    for (; ct < ntiles; ct += gridDim.x) {
+        const int64_t c0 = ct * CT;
+        if (tid < ROWS * CT) {
+            am[tid] = pre;
+            if (ct + gridDim.x < ntiles) pre = fetch(ct + gridDim.x);
+        }
+        lds_barrier();
+        for (int i = tid; i < CT * NA; i += blockDim.x) {
+            const int c = i / NA, al = i - c * NA;
+            Gs[c * GS + al] = g_entry<KIND, D>(am, cf, CT, c, al);
+        }
+        for (int i = tid; i < CT * P.n_zero && tid < io_begin; i += io_begin) {
+            const int c = i / P.n_zero;
+            st[c * nI + P.zero_entries[i - c * P.n_zero]] = 0.0;
+        }
+        lds_barrier();
+        if (tid >= io_begin) {
+            if (io_c0 >= 0) io_store();  // the previous tile, during this tile's MFMA phase
+        } else {
+            // compiler-only barrier (emits no instruction) on the row stride: keeps the
+            // staging addresses of the steps from being precomputed outside the cell-tile
+            // loop, which would cost 4 registers a step
+            int nIs = nI;
+            asm volatile("" : "+s"(nIs));
+            d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s = 0; s < KMAX; ++s) {
+                if (s < ns) {
+                    const uint32_t word = R[2 * KMAX + s];
+                    const double bv = __builtin_bit_cast(double, u32x2{R[2 * s], R[2 * s + 1]});
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(grow[word & 0xffu], bv, acc, 0, 0, 0);
+                    if ((endmask >> s) & 1u) {
+                        const int e = static_cast<int>(word >> 8) - 1;
+                        if (e >= 0) {
+#pragma unroll
+                            for (int i = 0; i < 4; ++i) st[(i * 4 + lk) * nIs + e] = acc[i];
+                        }
+                        acc = d4{0.0, 0.0, 0.0, 0.0};
+                        // keeps the reset inside this branch (no select on every step that
+                        // would wait for each MFMA's result)
+                        asm volatile("" : "+v"(acc));
+                    }
+                }
+            }
+        }
+        lds_barrier();
+        if (tid >= io_begin) {  // take this tile's rows into registers; st is free after the next barrier
+            const int64_t nc = A.cells - c0 < CT ? A.cells - c0 : CT;
+            io_c0 = c0;
+            io_n = nc * nI;
+            const int64_t nv = io_n / 2;
+            const int jn = nv > io_lane ? static_cast<int>((nv - io_lane + 64 * kIoWaves - 1) / (64 * kIoWaves)) : 0;
+            const d2v* sv = reinterpret_cast<const d2v*>(st) + io_lane;
+#pragma unroll
+            for (int j = 0; j < IOS; ++j) {
+                if (j < jn) {
+                    const u32x4 w = __builtin_bit_cast(u32x4, *sv);
+                    R[4 * j] = w[0];
+                    R[4 * j + 1] = w[1];
+                    R[4 * j + 2] = w[2];
+                    R[4 * j + 3] = w[3];
+                }
+                sv += 64 * kIoWaves;
+            }
+            if ((io_n & 1) && io_lane == 0) {
+                const u32x2 w = __builtin_bit_cast(u32x2, st[io_n - 1]);
+                R[4 * (IOS - 1)] = w[0];
+                R[4 * (IOS - 1) + 1] = w[1];
+            }
+        }
+    }
+    if (tid >= io_begin && io_c0 >= 0) io_store();  // the last tile
+}
+
+template <int D, int KIND>
+static hipError_t launch_persistent_k(int kmax, int waves, int grid, size_t lds, const ContractArgs& a,
+                                      const PersistArgs& p, hipStream_t s) {
+    const unsigned block = 64u * waves;
+    if (kmax <= 8) return launch_lds(contract_f64_persistent<D, KIND, 8, 1024, kIoSlots>, grid, block, lds, s, a, p);
+    if (kmax <= 16) return launch_lds(contract_f64_persistent<D, KIND, 16, 1024, kIoSlots>, grid, block, lds, s, a, p);
+    return launch_lds(contract_f64_persistent<D, KIND, 24, 1024, kIoSlots>, grid, block, lds, s, a, p);
+}
+
+template <int D>
+static hipError_t launch_persistent_d(int kind, int kmax, int waves, int grid, size_t lds, const ContractArgs& a,
+                                      const PersistArgs& p, hipStream_t s) {
+    switch (kind) {
+    case K_MASS: return launch_persistent_k<D, K_MASS>(kmax, waves, grid, lds, a, p, s);
+    case K_LAPLACE: return launch_persistent_k<D, K_LAPLACE>(kmax, waves, grid, lds, a, p, s);
+    case K_WLAPLACE: return launch_persistent_k<D, K_WLAPLACE>(kmax, waves, grid, lds, a, p, s);
+    case K_ELASTICITY: return launch_persistent_k<D, K_ELASTICITY>(kmax, waves, grid, lds, a, p, s);
+    default: return launch_persistent_k<D, K_NS>(kmax, waves, grid, lds, a, p, s);
+    }
+}
+
+hipError_t launch_contract_persistent(int dim, int kind, int kmax, int waves, int grid, ContractArgs a,
+                                      const PersistArgs& p, hipStream_t stream) {
+    if (a.cells <= 0) return hipSuccess;
+    if (kmax > 24 || waves != 16 || (reinterpret_cast<uintptr_t>(a.out) & 15u) != 0) return hipErrorInvalidValue;
+    // the staged rows of one tile must fit the I/O lanes' register slots, with lane 0's
+    // last slot free for an odd tail
+    const int64_t pairs = (16 * static_cast<int64_t>(a.n_I)) / 2;
+    if (pairs > static_cast<int64_t>(kIoSlots) * 64 * kIoWaves - 64 * kIoWaves) return hipErrorInvalidValue;
+    const LdsPlan pl = plan_lds(dim, kind, 16, a.n_I, a.n_alpha, 0, false, kLdsBudget);
+    if (!pl.staged || (1 + dim * dim + n_coeff_of(dim, kind)) * 16 > 64 * (waves - kIoWaves)) return hipErrorInvalidValue;
+    a.staged = 1;
+    a.stage_bytes = pl.stage_bytes;
+    a.head_bytes = pl.head_bytes;
+    const int64_t ntiles = (a.cells + 15) / 16;
+    if (grid > ntiles) grid = static_cast<int>(ntiles);
+    return dim == 2 ? launch_persistent_d<2>(kind, kmax, waves, grid, pl.total, a, p, stream)
+                    : launch_persistent_d<3>(kind, kmax, waves, grid, pl.total, a, p, stream);
 }
 
 // ------------------------------------------------------- persistent mixed batch ---
-// Work unit = (item, 64-cell tile).  Each workgroup takes units from one atomic counter
-// until the queue is empty; the last workgroup to leave resets the counters, so the
-// launch can be replayed (for example from a captured graph) with no separate reset.
-// Geometry is computed in place, one lane per cell.
+// Work unit = (item, 16-cell tile).  Each workgroup claims kBatchChunk consecutive units
+// per atomic from one queue counter until the queue is empty; the last workgroup to leave
+// resets the counters, so the launch can be replayed (for example from a captured graph)
+// with no separate reset.  Geometry is computed in place, one lane per cell; outputs are
+// staged in LDS for items whose 16 rows fit the launch's LDS.
 
-constexpr int kBatchMT = 4;
-constexpr int kBatchCT = 16 * kBatchMT;
-constexpr int kBatchMaxCoeff = 12;
-
-size_t batch_lds_bytes(int max_alpha, int max_kpad, bool bf16) {
-    size_t head = static_cast<size_t>((1 + 9) + kBatchMaxCoeff) * kBatchCT * sizeof(double);
-    if (!bf16) return head + static_cast<size_t>(kBatchCT) * (max_alpha | 1) * sizeof(double);
-    return head + static_cast<size_t>(kBatchCT) * (max_kpad + 8) * sizeof(uint16_t);
+size_t batch_lds_bytes(int max_alpha, int max_kpad, int max_stage_nI, bool bf16) {
+    const size_t head = align16(static_cast<size_t>(1 + 9 + kBatchMaxCoeff) * kBatchCT * sizeof(double));
+    const size_t g = align16(bf16 ? static_cast<size_t>(kBatchCT) * (max_kpad + 8) * sizeof(uint16_t)
+                                  : static_cast<size_t>(kBatchCT) * (max_alpha | 1) * sizeof(double));
+    const size_t stage = align16(static_cast<size_t>(kBatchCT) * max_stage_nI * (bf16 ? sizeof(float) : sizeof(double)));
+    return stage + head + g;
 }
 
 template <int D, int KIND, bool BF16>
-__device__ __forceinline__ void batch_unit(const BatchItem& it, int64_t c0, double* smem) {
+__device__ __forceinline__ void batch_unit(const BatchItem& it, int64_t c0, unsigned char* smem, size_t stage_cap) {
     constexpr int NC = FormTraits<KIND, D>::n_coeff;
-    double* am = smem;
+    constexpr size_t head = (1 + 9 + kBatchMaxCoeff) * kBatchCT * sizeof(double);
+    double* am = reinterpret_cast<double*>(smem + stage_cap);
     double* cf = am + (1 + D * D) * kBatchCT;
-    double* G = cf + NC * kBatchCT;
+    unsigned char* g = smem + stage_cap + align16(head);
+    const size_t ob = BF16 ? sizeof(float) : sizeof(double);
+    const bool staged = static_cast<size_t>(kBatchCT) * it.n_I * ob <= stage_cap &&
+                        (reinterpret_cast<uintptr_t>(it.out) & 15u) == 0;
     stage_tile_from_coords<D, NC>(it.coords, it.coeffs, it.cells, c0, kBatchCT, am, cf);
     __syncthreads();
     if constexpr (BF16) {
+        float* st = staged ? reinterpret_cast<float*>(smem) : nullptr;
         if (it.n_seg == 3)
-            contract_tile_bf16<D, KIND, kBatchMT, 3>(am, cf, reinterpret_cast<unsigned short*>(G), c0, it.cells, it.n_I,
-                                                     it.n_tiles, it.kpad, it.gpiece, it.bb, it.nonzero,
-                                                     static_cast<float*>(it.out));
+            contract_tile_bf16<D, KIND, 1, 3>(am, cf, reinterpret_cast<unsigned short*>(g), st, c0, it.cells, it.n_I,
+                                              it.n_tiles, it.kpad, it.gpiece, it.bb, it.nonzero, static_cast<float*>(it.out));
         else
-            contract_tile_bf16<D, KIND, kBatchMT, 6>(am, cf, reinterpret_cast<unsigned short*>(G), c0, it.cells, it.n_I,
-                                                     it.n_tiles, it.kpad, it.gpiece, it.bb, it.nonzero,
-                                                     static_cast<float*>(it.out));
+            contract_tile_bf16<D, KIND, 1, 6>(am, cf, reinterpret_cast<unsigned short*>(g), st, c0, it.cells, it.n_I,
+                                              it.n_tiles, it.kpad, it.gpiece, it.bb, it.nonzero, static_cast<float*>(it.out));
     } else {
-        contract_tile_f64<D, KIND, kBatchMT>(am, cf, G, c0, it.cells, it.n_I, it.n_tiles, it.koff, it.alpha, it.b,
-                                             static_cast<double*>(it.out));
+        double* st = staged ? reinterpret_cast<double*>(smem) : nullptr;
+        contract_tile_f64<D, KIND, 1>(am, cf, reinterpret_cast<double*>(g), st, c0, it.cells, it.n_I, it.n_tiles,
+                                      it.koff, it.apack, it.entry, it.b, static_cast<double*>(it.out));
     }
 }
 
 template <bool BF16>
-__global__ __launch_bounds__(256) void batch_kernel(const BatchItem* __restrict__ items, int n_items,
-                                                    int64_t total_units, int* counters) {
-    extern __shared__ double smem[];
-    __shared__ int64_t s_unit;
-    __shared__ int s_item;
+__global__ __launch_bounds__(1024) void batch_kernel(const BatchItem* __restrict__ items, int n_items,
+                                                     int64_t total_units, int* counters, size_t stage_cap) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    __shared__ int s_unit;
     for (;;) {
-        if (threadIdx.x == 0) {
-            const int64_t u = atomicAdd(&counters[0], 1);
-            int lo = 0;
-            if (u < total_units) {
-                int hi = n_items - 1;
-                while (lo < hi) {  // last item with unit_begin <= u
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (items[mid].unit_begin <= u)
-                        lo = mid;
-                    else
-                        hi = mid - 1;
-                }
-            }
-            s_unit = u;
-            s_item = lo;
-        }
+        if (threadIdx.x == 0) s_unit = atomicAdd(&counters[0], kBatchChunk);
         __syncthreads();
-        const int64_t u = s_unit;
-        if (u >= total_units) break;
-        const BatchItem& it = items[s_item];
-        const int64_t c0 = (u - it.unit_begin) * kBatchCT;
-        switch (it.dim * 8 + it.kind) {
-        case 16 + K_MASS: batch_unit<2, K_MASS, BF16>(it, c0, smem); break;
-        case 16 + K_LAPLACE: batch_unit<2, K_LAPLACE, BF16>(it, c0, smem); break;
-        case 16 + K_WLAPLACE: batch_unit<2, K_WLAPLACE, BF16>(it, c0, smem); break;
-        case 16 + K_ELASTICITY: batch_unit<2, K_ELASTICITY, BF16>(it, c0, smem); break;
-        case 16 + K_NS: batch_unit<2, K_NS, BF16>(it, c0, smem); break;
-        case 24 + K_MASS: batch_unit<3, K_MASS, BF16>(it, c0, smem); break;
-        case 24 + K_LAPLACE: batch_unit<3, K_LAPLACE, BF16>(it, c0, smem); break;
-        case 24 + K_WLAPLACE: batch_unit<3, K_WLAPLACE, BF16>(it, c0, smem); break;
-        case 24 + K_ELASTICITY: batch_unit<3, K_ELASTICITY, BF16>(it, c0, smem); break;
-        default: batch_unit<3, K_NS, BF16>(it, c0, smem); break;
+        const int64_t u0 = s_unit;
+        __syncthreads();  // s_unit is rewritten on the next claim
+        if (u0 >= total_units) break;
+        const int64_t u1 = u0 + kBatchChunk < total_units ? u0 + kBatchChunk : total_units;
+        for (int64_t u = u0; u < u1; ++u) {
+            int lo = 0, hi = n_items - 1;
+            while (lo < hi) {  // last item with unit_begin <= u (same answer on every lane)
+                const int mid = (lo + hi + 1) >> 1;
+                if (items[mid].unit_begin <= u)
+                    lo = mid;
+                else
+                    hi = mid - 1;
+            }
+            const BatchItem& it = items[lo];
+            const int64_t c0 = (u - it.unit_begin) * kBatchCT;
+            switch (it.dim * 8 + it.kind) {
+            case 16 + K_MASS: batch_unit<2, K_MASS, BF16>(it, c0, smem_raw, stage_cap); break;
+            case 16 + K_LAPLACE: batch_unit<2, K_LAPLACE, BF16>(it, c0, smem_raw, stage_cap); break;
+            case 16 + K_WLAPLACE: batch_unit<2, K_WLAPLACE, BF16>(it, c0, smem_raw, stage_cap); break;
+            case 16 + K_ELASTICITY: batch_unit<2, K_ELASTICITY, BF16>(it, c0, smem_raw, stage_cap); break;
+            case 16 + K_NS: batch_unit<2, K_NS, BF16>(it, c0, smem_raw, stage_cap); break;
+            case 24 + K_MASS: batch_unit<3, K_MASS, BF16>(it, c0, smem_raw, stage_cap); break;
+            case 24 + K_LAPLACE: batch_unit<3, K_LAPLACE, BF16>(it, c0, smem_raw, stage_cap); break;
+            case 24 + K_WLAPLACE: batch_unit<3, K_WLAPLACE, BF16>(it, c0, smem_raw, stage_cap); break;
+            case 24 + K_ELASTICITY: batch_unit<3, K_ELASTICITY, BF16>(it, c0, smem_raw, stage_cap); break;
+            default: batch_unit<3, K_NS, BF16>(it, c0, smem_raw, stage_cap); break;
+            }
+            __syncthreads();  // LDS is reused by the next unit
         }
-        __syncthreads();  // LDS and s_unit are reused by the next unit
     }
     if (threadIdx.x == 0) {
         __threadfence();
@@ -524,10 +834,13 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchItem* __restrict_
 }
 
 hipError_t launch_batch(const BatchItem* items_dev, int n_items, int64_t total_units, int* counter_dev, int grid,
-                        bool bf16, size_t lds, hipStream_t stream) {
+                        bool bf16, size_t lds, size_t stage_cap, hipStream_t stream) {
     if (total_units <= 0) return hipSuccess;
-    if (bf16) return launch_lds(batch_kernel<true>, grid, 256, lds, stream, items_dev, n_items, total_units, counter_dev);
-    return launch_lds(batch_kernel<false>, grid, 256, lds, stream, items_dev, n_items, total_units, counter_dev);
+    if (bf16)
+        return launch_lds(batch_kernel<true>, grid, 64 * kBatchWaves, lds, stream, items_dev, n_items, total_units,
+                          counter_dev, stage_cap);
+    return launch_lds(batch_kernel<false>, grid, 64 * kBatchWaves, lds, stream, items_dev, n_items, total_units,
+                      counter_dev, stage_cap);
 }
 
 // ------------------------------------------------------------------ quadrature ---

@@ -351,35 +351,138 @@ bool build_reference_tensor(const FormSpec& s, ReferenceTensor* rt, std::string*
 
 // ------------------------------------------------------------ MFMA tiles -------
 
-TilesF64 make_tiles_f64(const ReferenceTensor& rt) {
+namespace {
+
+using Mask = std::array<uint64_t, 2>;  // nonzero alpha columns of a row (n_alpha <= 128)
+
+int popcount(const Mask& m) { return __builtin_popcountll(m[0]) + __builtin_popcountll(m[1]); }
+
+// Greedy clustering of `rows` into groups of at most 16: seed = remaining row with the most
+// nonzero columns, then repeatedly add the row that grows the union least (ties: the row
+// that shares most columns with the union, then the lower row index).
+std::vector<std::vector<int>> cluster_rows(const std::vector<int>& rows, const std::vector<Mask>& mask) {
+    std::vector<std::vector<int>> groups;
+    std::vector<int> rem(rows);
+    while (!rem.empty()) {
+        size_t seed = 0;
+        for (size_t i = 1; i < rem.size(); ++i)
+            if (popcount(mask[rem[i]]) > popcount(mask[rem[seed]])) seed = i;
+        std::vector<int> g{rem[seed]};
+        Mask u = mask[rem[seed]];
+        rem.erase(rem.begin() + seed);
+        while (g.size() < 16 && !rem.empty()) {
+            size_t best = 0;
+            int best_inc = 1 << 30, best_ov = -1;
+            for (size_t i = 0; i < rem.size(); ++i) {
+                const Mask& m = mask[rem[i]];
+                const Mask inc{m[0] & ~u[0], m[1] & ~u[1]};
+                const Mask ov{m[0] & u[0], m[1] & u[1]};
+                const int ci = popcount(inc), co = popcount(ov);
+                if (ci < best_inc || (ci == best_inc && co > best_ov)) {
+                    best = i;
+                    best_inc = ci;
+                    best_ov = co;
+                }
+            }
+            const Mask& m = mask[rem[best]];
+            u[0] |= m[0];
+            u[1] |= m[1];
+            g.push_back(rem[best]);
+            rem.erase(rem.begin() + best);
+        }
+        std::sort(g.begin(), g.end());
+        groups.push_back(g);
+    }
+    return groups;
+}
+
+}  // namespace
+
+TilesF64 make_tiles_f64(const ReferenceTensor& rt, int window) {
     TilesF64 T;
     const int nI = rt.n_I, na = rt.n_alpha;
-    T.n_tiles = (nI + 15) / 16;
-    T.koff.assign(T.n_tiles + 1, 0);
-    for (int t = 0; t < T.n_tiles; ++t) {
-        std::vector<int> cols;
-        for (int a = 0; a < na; ++a) {
-            bool nz = false;
-            for (int e = 0; e < 16 && !nz; ++e) {
-                int row = t * 16 + e;
-                if (row < nI && rt.A0[static_cast<size_t>(row) * na + a] != 0) nz = true;
-            }
-            if (nz) cols.push_back(a);
+    T.window = window;
+    std::vector<Mask> mask(nI, Mask{0, 0});
+    for (int r = 0; r < nI; ++r)
+        for (int a = 0; a < na; ++a)
+            if (rt.A0[static_cast<size_t>(r) * na + a] != 0) mask[r][a >> 6] |= uint64_t(1) << (a & 63);
+    std::vector<std::vector<int>> groups;
+    const int W = window <= 0 ? nI : window;
+    for (int w0 = 0; w0 < nI; w0 += W) {
+        std::vector<int> rows;
+        for (int r = w0; r < std::min(nI, w0 + W); ++r) rows.push_back(r);
+        if (W == 16) {
+            groups.push_back(rows);
+        } else {
+            auto g = cluster_rows(rows, mask);
+            groups.insert(groups.end(), g.begin(), g.end());
         }
-        int kpad = (static_cast<int>(cols.size()) + 3) / 4 * 4;
+    }
+    T.n_tiles = static_cast<int>(groups.size());
+    T.koff.assign(T.n_tiles + 1, 0);
+    T.entry.assign(static_cast<size_t>(T.n_tiles) * 16, -1);
+    for (int t = 0; t < T.n_tiles; ++t) {
+        const auto& g = groups[t];
+        Mask u{0, 0};
+        for (size_t e = 0; e < g.size(); ++e) {
+            T.entry[static_cast<size_t>(t) * 16 + e] = g[e];
+            u[0] |= mask[g[e]][0];
+            u[1] |= mask[g[e]][1];
+        }
+        std::vector<int> cols;
+        for (int a = 0; a < na; ++a)
+            if (u[a >> 6] >> (a & 63) & 1) cols.push_back(a);
+        const int kpad = (static_cast<int>(cols.size()) + 3) / 4 * 4;
         for (int k = 0; k < kpad; ++k) {
-            bool real = k < static_cast<int>(cols.size());
-            int a = real ? cols[k] : (cols.empty() ? 0 : cols[0]);
-            T.alpha.push_back(a);
+            const bool real = k < static_cast<int>(cols.size());
+            const int a = real ? cols[k] : (cols.empty() ? 0 : cols[0]);
+            if (k % 4 == 0) T.apack.push_back(0);
+            T.apack.back() |= static_cast<uint32_t>(a) << (8 * (k % 4));
             for (int e = 0; e < 16; ++e) {
-                int row = t * 16 + e;
-                double v = (real && row < nI) ? rt.A0[static_cast<size_t>(row) * na + a] : 0.0;
-                T.b.push_back(v);
+                const int row = T.entry[static_cast<size_t>(t) * 16 + e];
+                T.b.push_back((real && row >= 0) ? rt.A0[static_cast<size_t>(row) * na + a] : 0.0);
             }
         }
         T.koff[t + 1] = T.koff[t] + kpad;
     }
     return T;
+}
+
+WaveSchedule make_wave_schedule(const TilesF64& T, int waves) {
+    WaveSchedule S;
+    S.waves = waves;
+    std::vector<int> tiles;
+    for (int t = 0; t < T.n_tiles; ++t) {
+        if (T.koff[t + 1] > T.koff[t])
+            tiles.push_back(t);
+        else
+            for (int e = 0; e < 16; ++e)
+                if (T.entry[static_cast<size_t>(t) * 16 + e] >= 0) S.zero_entries.push_back(T.entry[t * 16 + e]);
+    }
+    std::stable_sort(tiles.begin(), tiles.end(), [&](int a, int b) {
+        return (T.koff[a + 1] - T.koff[a]) > (T.koff[b + 1] - T.koff[b]);
+    });
+    std::vector<std::vector<int>> own(waves);
+    std::vector<int> load(waves, 0);
+    for (int t : tiles) {
+        int w = static_cast<int>(std::min_element(load.begin(), load.end()) - load.begin());
+        own[w].push_back(t);
+        load[w] += (T.koff[t + 1] - T.koff[t]) / 4;
+    }
+    S.woff.assign(waves + 1, 0);
+    for (int w = 0; w < waves; ++w) {
+        std::sort(own[w].begin(), own[w].end());
+        for (int t : own[w]) {
+            const int k0 = T.koff[t] / 4, k1 = T.koff[t + 1] / 4;
+            for (int k = k0; k < k1; ++k) {
+                S.step_kstep.push_back(k);
+                S.step_end.push_back(k == k1 - 1 ? t : -1);
+            }
+        }
+        S.woff[w + 1] = static_cast<int>(S.step_kstep.size());
+        S.max_steps = std::max(S.max_steps, S.woff[w + 1] - S.woff[w]);
+    }
+    return S;
 }
 
 double round_bf16(double x) {

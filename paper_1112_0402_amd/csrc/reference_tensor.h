@@ -36,14 +36,19 @@ struct ReferenceTensor {
     std::vector<double> A0;  // [n_I][n_alpha]
 };
 
-// Contraction tiles for 16 x 16 x 4 FP64 MFMA: output entries are cut into tiles of 16
-// consecutive entries; each tile keeps only the alpha columns that are nonzero in one of
-// its rows (padded to a multiple of 4 with zero B values).
+// Contraction tiles for 16 x 16 x 4 FP64 MFMA.  The n_I output entries are grouped into
+// tiles of 16 (the MFMA N dimension); each tile keeps only the alpha columns that are
+// nonzero in one of its rows (zeros of A^0 are skipped), padded to a multiple of 4 (the
+// MFMA K step) with zero B values.  Grouping: within windows of `window` consecutive
+// entries, rows are clustered greedily so that each tile's union of nonzero columns
+// stays small; window == 16 keeps tiles contiguous, window <= 0 clusters over all rows.
 struct TilesF64 {
     int n_tiles = 0;
-    std::vector<int32_t> koff;   // [n_tiles + 1], in k rows
-    std::vector<int32_t> alpha;  // [koff[n_tiles]] alpha index of each k row
-    std::vector<double> b;       // [koff[n_tiles]][16] A^0 values, 0 beyond n_I / padding
+    int window = 16;
+    std::vector<int32_t> koff;    // [n_tiles + 1], in k rows (multiples of 4)
+    std::vector<uint32_t> apack;  // [koff[n_tiles] / 4]: the 4 alpha indices of a k step, one byte each
+    std::vector<double> b;        // [koff[n_tiles]][16] A^0 values, 0 for padding
+    std::vector<int32_t> entry;   // [n_tiles][16] output entry of each tile column, -1 = padding
 };
 
 // Split-BF16 contraction: concatenated K = n_seg segments of n_alpha, segment s pairs
@@ -70,7 +75,21 @@ bool supported(const FormSpec& s, std::string* why);
 
 LagrangeBasis make_basis(int dim, int degree);
 bool build_reference_tensor(const FormSpec& s, ReferenceTensor* out, std::string* err);
-TilesF64 make_tiles_f64(const ReferenceTensor& rt);
+TilesF64 make_tiles_f64(const ReferenceTensor& rt, int window);
+
+// Static schedule of the FP64 tiles over the waves of a persistent workgroup: the tiles
+// with a nonzero contraction are dealt to `waves` waves, longest first onto the least
+// loaded wave (balancing k steps); each wave's steps are listed in order.  Entries whose
+// rows of A^0 are all zero are listed apart (they are written as zeros).
+struct WaveSchedule {
+    int waves = 0;
+    int max_steps = 0;                  // largest number of k steps of one wave
+    std::vector<int32_t> woff;          // [waves + 1] step range of each wave
+    std::vector<int32_t> step_kstep;    // [steps] k step (index into apack, and into b in units of 4 k rows)
+    std::vector<int32_t> step_end;      // [steps] the tile if the step is its last, else -1
+    std::vector<int32_t> zero_entries;  // entries whose A^0 row is zero
+};
+WaveSchedule make_wave_schedule(const TilesF64& T, int waves);
 TilesBF16 make_tiles_bf16(const ReferenceTensor& rt, int products /* 3 or 6 */);
 QuadTables make_quad_tables(const FormSpec& s);
 

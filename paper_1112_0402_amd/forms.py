@@ -34,12 +34,12 @@ class Form:
     """A compiled form on the current device (compile step + upload happen here)."""
 
     def __init__(self, kind, dim, degree, precision="fp64", kernel="tensor", tile_cells=0, waves=0,
-                 lam=1.0, mu=1.0, stream=None):
+                 lam=1.0, mu=1.0, stream=None, tile_window=0, persistent=0):
         self.kind, self.dim, self.degree = kind, dim, degree
         self.precision, self.kernel = precision, kernel
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self._desc = capi.make_desc(kind, dim, degree, precision, kernel, tile_cells, waves, lam, mu,
-                                    _stream_handle(self.stream))
+                                    _stream_handle(self.stream), tile_window, persistent)
         h = ctypes.c_void_p()
         capi.check(capi.lib().ffc_form_create(ctypes.byref(self._desc), ctypes.byref(h)))
         self._h = h
@@ -75,6 +75,26 @@ class Form:
         if out.numel() != cells * self.n_I:
             raise ValueError("out has the wrong number of entries")
         capi.check(capi.lib().ffc_tabulate_tensor(self._h, cells, _ptr(coords), _ptr(coeffs), _ptr(out)))
+        return out
+
+    def tabulate_affine(self, affine_map: torch.Tensor, coeffs: torch.Tensor | None = None,
+                        out: torch.Tensor | None = None) -> torch.Tensor:
+        """Contraction only, from an affine map [1 + d*d, cells] of compute_geometry()."""
+        d = self.dim
+        _check_tensor("affine_map", affine_map, torch.float64)
+        if affine_map.dim() != 2 or affine_map.shape[0] != 1 + d * d:
+            raise ValueError(f"affine_map must be [{1 + d * d}, cells]")
+        cells = affine_map.shape[1]
+        if self.info["n_coeffs"]:
+            if coeffs is None:
+                raise ValueError(f"form {self.kind} needs coefficients")
+            _check_tensor("coeffs", coeffs, torch.float64, (self.info["n_coeffs"], cells))
+        if out is None:
+            out = self.empty_out(cells)
+        _check_tensor("out", out, self.out_dtype)
+        if out.numel() != cells * self.n_I:
+            raise ValueError("out has the wrong number of entries")
+        capi.check(capi.lib().ffc_tabulate_tensor_affine(self._h, cells, _ptr(affine_map), _ptr(coeffs), _ptr(out)))
         return out
 
     def close(self):

@@ -266,3 +266,21 @@ def test_batch_graph_replay():
         torch.cuda.synchronize()
         for o, e in zip(outs, eager):
             assert torch.equal(o, e), rep
+
+
+def test_contraction_from_shared_geometry():
+    """ffc_tabulate_tensor_affine on the output of ffc_compute_geometry equals
+    ffc_tabulate_tensor, for two forms sharing one geometry pass."""
+    require_gpu()
+    wl = _small("wlaplace", 3, 2)
+    X, C = to_dev(wl.coords), to_dev(wl.coeffs)
+    am = compute_geometry(X, 3)
+    for kind, coeffs in (("wlaplace", C), ("laplace", None)):
+        f = Form(kind, 3, 2)
+        a = f.tabulate(X, coeffs)
+        b = f.tabulate_affine(am, coeffs)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b)
+    qf = Form("laplace", 3, 2, kernel="quadrature")
+    assert capi.lib().ffc_tabulate_tensor_affine(qf.handle, wl.cells, am.data_ptr(), None,
+                                                 qf.empty_out(wl.cells).data_ptr()) == capi.FFC_E_INVALID
