@@ -1,13 +1,19 @@
 #!/usr/bin/env python3
 """Element tensors/s of the tensor-representation path on one MI355X.
 
-Workload (default): 3D linear elasticity int sigma(u):eps(v) with lambda = mu = 1, vector
-P2 tetrahedra (30 dofs), 6 * 50^3 = 750,000 cells of a jittered unit cube (seed 2), FP64.
-A step is one pass of the hot path over the mesh, inputs resident in HBM:
-  geometry kernel (coords -> det J, J^{-1}, one lane per cell)
-  + contraction kernel (G_K tile in LDS, A^0 tiles on FP64 MFMA, 900 x 81 per cell).
-The plain GPU quadrature kernel is timed beside it on the same mesh, and the FP64 oracle
-is timed on the host cores on a bounded sample of the same mesh.
+Default workload (--workload elasticity): 3D linear elasticity int sigma(u):eps(v) with
+lambda = mu = 1, vector P2 tetrahedra (30 dofs), 6 * 50^3 = 750,000 cells of a jittered unit
+cube (seed 2), FP64.  A step is one pass of the hot path over the mesh, inputs resident in
+HBM: geometry kernel (coords -> det J, J^{-1}, one lane per cell) + contraction kernel
+(G_K tile in LDS, A^0 tiles on FP64 MFMA, 900 x 81 per cell).  The plain GPU quadrature
+kernel is timed beside it on the same mesh, and the FP64 oracle is timed on the host
+cores on a bounded sample of the same mesh.
+
+Other workloads (same JSON line layout):
+  poisson2d   2D Poisson, P1 triangles, 8192 cells (launch-latency bound), FP64
+  wlaplace    3D weighted Laplacian, P3 tets, w in P1, 1,500,282 cells, split BF16 (x3 / x6)
+  batch       64 meshes of 1e3..5e5 cells, 16 form variants, one persistent launch replayed
+              from a captured graph (FP64 or split BF16)
 
 Prints one JSON line.  Options: --gpus (1 only), --steps, --warmup.
 """
@@ -23,11 +29,11 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
-FP64_MFMA_PEAK_TF = 78.6   # MI355X dense FP64 matrix
+HBM_PEAK_GBS = 8000.0       # MI355X HBM3E
+FP64_MFMA_PEAK_TF = 78.6    # MI355X dense FP64 matrix
 BF16_MFMA_PEAK_TF = 2500.0  # MI355X dense BF16 matrix
 METRIC = "element tensors/s + %HBM/MFMA peak, tensor-rep vs quadrature kernel, rel err≤1e-12"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "contract_f64_elasticity3d_p2_750k_traffic.txt")
+PROFILES = os.path.join(ROOT, "profiles")
 
 
 def kernel_source_hash() -> str:
@@ -38,13 +44,14 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(cells: int):
+def load_traffic(workload: str, cells: int):
     """HBM bytes per launch of the contraction kernel from the committed rocprofv3 PMC
-    summary, if it was taken on the current kernel source; else None."""
-    if not os.path.exists(TRAFFIC_FILE):
+    summary of this workload, if it was taken on the current kernel source; else None."""
+    path = os.path.join(PROFILES, f"contract_{workload}_traffic.txt")
+    if not os.path.exists(path):
         return None
     kv = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
@@ -56,11 +63,264 @@ def load_traffic(cells: int):
         return None
 
 
+def timed(fn, steps, stream, torch):
+    """Mean milliseconds of fn() over `steps` launches, HIP events on the launch stream."""
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in ev:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    return float(sum(a.elapsed_time(b) for a, b in ev) / steps)
+
+
+def cpu_baseline(wl, out_fn, seconds, np):
+    """The oracle on the host cores over a bounded prefix of the same mesh."""
+    import oracle
+
+    threads = oracle.max_threads()
+    calib = min(500, wl.cells)
+
+    def coeffs(n):
+        return None if wl.coeffs is None else np.ascontiguousarray(wl.coeffs[:, :n])
+
+    t = time.perf_counter()
+    oracle.tabulate(wl.kind, wl.dim, wl.degree, wl.coords[:, :calib], coeffs(calib))
+    dt = time.perf_counter() - t
+    sample = int(min(65536, wl.cells, max(calib, calib * seconds / max(dt, 1e-6))))
+    sub = np.ascontiguousarray(wl.coords[:, :sample])
+    t = time.perf_counter()
+    ref = oracle.tabulate(wl.kind, wl.dim, wl.degree, sub, coeffs(sample))
+    dt = time.perf_counter() - t
+    got = out_fn(sample).reshape(sample, -1).astype(np.float64)
+    r = ref.reshape(sample, -1)
+    err = np.linalg.norm(got - r, axis=1) / np.linalg.norm(r, axis=1)
+    base = {
+        "value": sample / dt,
+        "unit": "element tensors/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"first {sample} cells of the same {wl.cells}-cell mesh, FP64 quadrature on the physical "
+                  f"cell, OpenMP over cells ({threads} threads), {dt:.1f} s wall",
+    }
+    return base, {"max": float(err.max()), "median": float(np.median(err)), "cells": sample}
+
+
+def bench_single(args, torch, np):
+    from paper_1112_0402_amd import meshgen
+    from paper_1112_0402_amd.forms import Form, compute_geometry
+
+    if args.workload == "elasticity":
+        wl, precision, name = meshgen.config2(), "fp64", "elasticity3d_p2_750k"
+        desc = "int sigma(u):eps(v), lambda=mu=1, vector P2 tetrahedra, 6*50^3 cells of the unit cube"
+    elif args.workload == "poisson2d":
+        wl, precision, name = meshgen.config1(), "fp64", "poisson2d_p1_8192"
+        desc = "int grad u . grad v, P1 triangles, 64x64 squares of the unit square"
+    else:
+        wl, precision = meshgen.config3(), args.precision
+        name = "wlaplace3d_p3_1.5M"
+        desc = "int w grad u . grad v, w in P1 ~ U(0.5,2), P3 tetrahedra, 6*63^3 cells of the unit cube"
+    cells, d = wl.cells, wl.dim
+    X = torch.from_numpy(wl.coords).cuda()
+    C = None if wl.coeffs is None else torch.from_numpy(wl.coeffs).cuda()
+    form = Form(wl.kind, d, wl.degree, precision=precision, tile_cells=args.tile_cells, waves=args.waves,
+                tile_window=args.tile_window, persistent=args.persistent)
+    info = form.info
+    amap = torch.empty((1 + d * d, cells), dtype=torch.float64, device="cuda")
+    out = form.empty_out(cells)
+    stream = torch.cuda.current_stream()
+    bf16 = precision != "fp64"
+
+    for _ in range(args.warmup):
+        compute_geometry(X, d, out=amap)
+        form.tabulate_affine(amap, C, out=out)
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev[k][0].record(stream)
+        compute_geometry(X, d, out=amap)
+        ev[k][1].record(stream)
+        form.tabulate_affine(amap, C, out=out)
+        ev[k][2].record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    geo_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+    con_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+
+    n_I, n_alpha, nnz = info["n_entries"], info["n_alpha"], info["nnz_a0"]
+    nco = info["n_coeffs"]
+    ob = info["out_bytes"]
+    ncoord = (d + 1) * d
+    con_bytes = cells * ((1 + d * d) * 8 + nco * 8 + n_I * ob)  # affine map + coefficients in, tensors out
+    geo_bytes = cells * (ncoord * 8 + (1 + d * d) * 8)          # coords in, affine map out
+    path_bytes = cells * (ncoord * 8 + nco * 8 + n_I * ob)      # coords + coefficients in, tensors out
+    alg_flops = cells * 2 * nnz                                  # zeros of A^0 skipped
+    mfma_flops = cells * info["mfma_k_per_tile"] * 32            # executed on the matrix cores
+    con_gbs = con_bytes / (con_ms * 1e-3) / 1e9
+    kname = "contract_f64_persistent" if info["persistent_waves"] else (
+        "contract_bf16_kernel" if bf16 else "contract_f64_kernel")
+    mpeak = BF16_MFMA_PEAK_TF if bf16 else FP64_MFMA_PEAK_TF
+
+    result = {
+        "metric": METRIC,
+        "value": cells / (ms_step * 1e-3),
+        "unit": "element tensors/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if not bf16 else precision + "->f32",
+        "data": "synthetic",
+        "config": {
+            "workload": name,
+            "form": desc,
+            "cells": cells,
+            "n_entries": n_I,
+            "n_alpha": n_alpha,
+            "precision": precision,
+            "mesh_seed": {"elasticity": 2, "poisson2d": 1, "wlaplace": 3}[args.workload],
+            "tile_cells": info["tile_cells"],
+            "waves": info["persistent_waves"] or info["waves"],
+            "persistent": bool(info["persistent_waves"]),
+            "mfma_tiles": info["n_tiles"],
+        },
+        "roofline": {
+            "kernel": kname,
+            "bound": "hbm",
+            "achieved": con_gbs,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": con_gbs / HBM_PEAK_GBS,
+            "traffic": load_traffic(name, cells),
+            "algorithmic_bytes_per_launch": con_bytes,
+            "ms_per_launch": con_ms,
+        },
+        "mfma": {
+            "kernel": kname,
+            "dtype": "bf16" if bf16 else "f64",
+            "executed_tflops": mfma_flops / (con_ms * 1e-3) / 1e12,
+            "peak_tflops": mpeak,
+            "frac": mfma_flops / (con_ms * 1e-3) / 1e12 / mpeak,
+            "algorithmic_tflops": alg_flops / (con_ms * 1e-3) / 1e12,
+            "executed_flops_per_cell": info["mfma_k_per_tile"] * 32,
+            "algorithmic_flops_per_cell": 2 * nnz,
+        },
+        "geometry_kernel": {
+            "ms_per_launch": geo_ms,
+            "achieved_gbs": geo_bytes / (geo_ms * 1e-3) / 1e9,
+            "frac": geo_bytes / (geo_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "algorithmic_bytes_per_launch": geo_bytes,
+        },
+        "path": {
+            "algorithmic_bytes_per_step": path_bytes,
+            "achieved_gbs": path_bytes / (ms_step * 1e-3) / 1e9,
+            "hbm_lower_bound_ms": path_bytes / (HBM_PEAK_GBS * 1e9) * 1e3,
+        },
+    }
+
+    if not args.no_quadrature:
+        qform = Form(wl.kind, d, wl.degree, kernel="quadrature")
+        qout = qform.empty_out(cells)
+        for _ in range(max(1, args.warmup)):
+            qform.tabulate(X, C, out=qout)
+        torch.cuda.synchronize()
+        q_ms = timed(lambda: qform.tabulate(X, C, out=qout), args.steps, stream, torch)
+        result["quadrature_kernel"] = {
+            "value": cells / (q_ms * 1e-3),
+            "unit": "element tensors/s",
+            "dtype": "f64",
+            "ms_per_launch": q_ms,
+            "quad_points": qform.info["quad_points"],
+            "speedup_tensor_over_quadrature": q_ms / ms_step,
+            "achieved_gbs": cells * (ncoord * 8 + nco * 8 + n_I * 8) / (q_ms * 1e-3) / 1e9,
+        }
+        del qout, qform
+
+    if not args.no_cpu_baseline:
+        base, err = cpu_baseline(wl, lambda n: out[:n].cpu().numpy(), args.cpu_seconds, np)
+        result["cpu_baseline"] = base
+        err["tol"] = 1e-12 if not bf16 else (1e-6 if precision == "bf16x6" else None)
+        result["rel_err_vs_oracle"] = err
+    return result
+
+
+def bench_batch(args, torch, np):
+    from paper_1112_0402_amd import meshgen
+    from paper_1112_0402_amd.forms import Batch, Form
+
+    precision = args.precision
+    wls = meshgen.config4()
+    forms = {}
+    for w in wls:
+        key = (w.kind, w.dim, w.degree)
+        if key not in forms:
+            forms[key] = Form(w.kind, w.dim, w.degree, precision=precision)
+    fl = [forms[(w.kind, w.dim, w.degree)] for w in wls]
+    X = [torch.from_numpy(w.coords).cuda() for w in wls]
+    C = [None if w.coeffs is None else torch.from_numpy(w.coeffs).cuda() for w in wls]
+    outs = [f.empty_out(w.cells) for f, w in zip(fl, wls)]
+    s = torch.cuda.Stream()
+    b = Batch(fl, X, C, outs, stream=s)
+    cells = b.total_cells
+    with torch.cuda.stream(s):
+        for _ in range(max(1, args.warmup)):
+            b.run()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        b.run()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        for _ in range(args.warmup):
+            g.replay()
+        torch.cuda.synchronize()
+        ms = timed(g.replay, args.steps, s, torch)
+    byt = sum(w.cells * ((w.dim + 1) * w.dim * 8 + (0 if w.coeffs is None else w.coeffs.shape[0] * 8)
+                         + f.n_I * f.info["out_bytes"]) for w, f in zip(wls, fl))
+    # the same meshes as one geometry + contraction launch pair per mesh, for comparison
+    stream = torch.cuda.current_stream()
+    for f, x, c, o in zip(fl, X, C, outs):
+        f.tabulate(x, c, out=o)
+    torch.cuda.synchronize()
+    ms_single = timed(lambda: [f.tabulate(x, c, out=o) for f, x, c, o in zip(fl, X, C, outs)], args.steps,
+                      stream, torch)
+    gbs = byt / (ms * 1e-3) / 1e9
+    return {
+        "metric": METRIC,
+        "value": cells / (ms * 1e-3),
+        "unit": "element tensors/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if precision == "fp64" else precision + "->f32",
+        "data": "synthetic",
+        "config": {"workload": "batch64_mixed", "meshes": len(wls), "cells": cells, "precision": precision,
+                   "variants": len(forms), "work_units": b.work_units, "grid": b.grid},
+        "roofline": {"kernel": "batch_kernel", "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes_per_launch": byt,
+                     "ms_per_launch": ms},
+        "per_mesh_launches": {"ms": ms_single, "value": cells / (ms_single * 1e-3),
+                              "speedup_batch_over_per_mesh": ms_single / ms},
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="elasticity", choices=["elasticity", "poisson2d", "wlaplace", "batch"])
+    ap.add_argument("--precision", default="bf16x3", choices=["fp64", "bf16x3", "bf16x6"],
+                    help="contraction arithmetic of the wlaplace and batch workloads")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target wall time of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-quadrature", action="store_true")
@@ -81,9 +341,6 @@ def main() -> int:
     import numpy as np
     import torch
 
-    from paper_1112_0402_amd import meshgen
-    from paper_1112_0402_amd.forms import Form, compute_geometry
-
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU"}))
         return 1
@@ -96,162 +353,7 @@ def main() -> int:
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_read": src.numel() * 8, "bytes_written": dst.numel() * 8}))
         return 0
-    wl = meshgen.config2()
-    cells = wl.cells
-    X = torch.from_numpy(wl.coords).cuda()
-    form = Form("elasticity", 3, 2, tile_cells=args.tile_cells, waves=args.waves, tile_window=args.tile_window,
-                persistent=args.persistent)
-    info = form.info
-    amap = torch.empty((10, cells), dtype=torch.float64, device="cuda")
-    out = form.empty_out(cells)
-    stream = torch.cuda.current_stream()
-
-    def step():
-        compute_geometry(X, 3, out=amap)
-        form.tabulate_affine(amap, out=out)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    # timed region: K steps, each bracketed by HIP events on the launch stream
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        ev[k][0].record(stream)
-        compute_geometry(X, 3, out=amap)
-        ev[k][1].record(stream)
-        form.tabulate_affine(amap, out=out)
-        ev[k][2].record(stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    geo_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
-    con_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
-    value = cells / (ms_step * 1e-3)
-
-    # algorithmic bytes / flops per cell
-    n_I, n_alpha, nnz = info["n_entries"], info["n_alpha"], info["nnz_a0"]
-    con_bytes = cells * ((1 + 9) * 8 + n_I * 8)            # affine map in + element tensor out
-    geo_bytes = cells * (12 * 8 + (1 + 9) * 8)              # coords in + affine map out
-    path_bytes = cells * (12 * 8 + n_I * 8)                 # coords in + element tensor out
-    alg_flops = cells * 2 * nnz                              # zeros of A^0 skipped
-    mfma_flops = cells * info["mfma_k_per_tile"] * 32        # executed on the matrix cores
-    con_gbs = con_bytes / (con_ms * 1e-3) / 1e9
-    traffic = load_traffic(cells)
-
-    result = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "element tensors/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {
-            "workload": "elasticity3d_p2_750k",
-            "form": "int sigma(u):eps(v), lambda=mu=1, vector P2 tetrahedra",
-            "cells": cells,
-            "n_entries": n_I,
-            "n_alpha": n_alpha,
-            "mesh": "6*50^3 Kuhn tetrahedra of the unit cube, interior vertices jittered U(+-0.2h), seed 2",
-            "tile_cells": info["tile_cells"],
-            "waves": info["persistent_waves"] or info["waves"],
-            "persistent": bool(info["persistent_waves"]),
-            "tile_window": args.tile_window,
-            "mfma_tiles": info["n_tiles"],
-        },
-        "roofline": {
-            "kernel": "contract_f64_kernel",
-            "bound": "hbm",
-            "achieved": con_gbs,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": con_gbs / HBM_PEAK_GBS,
-            "traffic": traffic,
-            "algorithmic_bytes_per_launch": con_bytes,
-            "ms_per_launch": con_ms,
-        },
-        "mfma": {
-            "kernel": "contract_f64_kernel",
-            "executed_tflops": mfma_flops / (con_ms * 1e-3) / 1e12,
-            "peak_tflops": FP64_MFMA_PEAK_TF,
-            "frac": mfma_flops / (con_ms * 1e-3) / 1e12 / FP64_MFMA_PEAK_TF,
-            "algorithmic_tflops": alg_flops / (con_ms * 1e-3) / 1e12,
-            "executed_flops_per_cell": info["mfma_k_per_tile"] * 32,
-            "algorithmic_flops_per_cell": 2 * nnz,
-        },
-        "geometry_kernel": {
-            "ms_per_launch": geo_ms,
-            "achieved_gbs": geo_bytes / (geo_ms * 1e-3) / 1e9,
-            "frac": geo_bytes / (geo_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-            "algorithmic_bytes_per_launch": geo_bytes,
-        },
-        "path": {
-            "algorithmic_bytes_per_step": path_bytes,
-            "achieved_gbs": path_bytes / (ms_step * 1e-3) / 1e9,
-            "hbm_lower_bound_ms": path_bytes / (HBM_PEAK_GBS * 1e9) * 1e3,
-        },
-    }
-
-    if not args.no_quadrature:
-        qform = Form("elasticity", 3, 2, kernel="quadrature")
-        qout = qform.empty_out(cells)
-        for _ in range(max(1, args.warmup)):
-            qform.tabulate(X, out=qout)
-        torch.cuda.synchronize()
-        qe = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-        for a, b in qe:
-            a.record(stream)
-            qform.tabulate(X, out=qout)
-            b.record(stream)
-        torch.cuda.synchronize()
-        q_ms = float(np.mean([a.elapsed_time(b) for a, b in qe]))
-        npts = qform.info["quad_points"]
-        q_flops = cells * n_I * npts * (2 + 2 * 3 + 1)  # n^2 N (n_f + n_D d + 1)-style count
-        result["quadrature_kernel"] = {
-            "value": cells / (q_ms * 1e-3),
-            "unit": "element tensors/s",
-            "ms_per_launch": q_ms,
-            "quad_points": npts,
-            "speedup_tensor_over_quadrature": (cells / (ms_step * 1e-3)) / (cells / (q_ms * 1e-3)),
-            "achieved_gbs": path_bytes / (q_ms * 1e-3) / 1e9,
-            "approx_fp64_tflops": q_flops / (q_ms * 1e-3) / 1e12,
-        }
-        del qout, qform
-
-    if not args.no_cpu_baseline:
-        import oracle
-
-        threads = oracle.max_threads()
-        calib = 500
-        t = time.perf_counter()
-        oracle.tabulate("elasticity", 3, 2, wl.coords[:, :calib])
-        dt = time.perf_counter() - t
-        sample = int(min(65536, max(calib, calib * args.cpu_seconds / max(dt, 1e-6))))
-        sub = np.ascontiguousarray(wl.coords[:, :sample])
-        t = time.perf_counter()
-        ref = oracle.tabulate("elasticity", 3, 2, sub)
-        dt = time.perf_counter() - t
-        got = out[:sample].cpu().numpy().reshape(sample, -1)
-        r = ref.reshape(sample, -1)
-        err = np.linalg.norm(got - r, axis=1) / np.linalg.norm(r, axis=1)
-        result["cpu_baseline"] = {
-            "value": sample / dt,
-            "unit": "element tensors/s",
-            "cores": threads,
-            "kind": "oracle",
-            "sample": f"first {sample} cells of the same 750,000-cell mesh, FP64 quadrature on the "
-                      f"physical cell, OpenMP over cells ({threads} threads), {dt:.1f} s wall",
-        }
-        result["rel_err_vs_oracle"] = {"max": float(err.max()), "median": float(np.median(err)),
-                                       "cells": sample, "tol": 1e-12}
-
+    result = bench_batch(args, torch, np) if args.workload == "batch" else bench_single(args, torch, np)
     print(json.dumps(result), flush=True)
     return 0
 

@@ -47,17 +47,13 @@ def unit_square(n: int, seed: int, jitter: float = JITTER):
     rng = np.random.Generator(np.random.PCG64(seed))
     verts, _ = _grid_vertices(n, 2, rng, jitter)
 
-    def vid(i, j):
-        return i * (n + 1) + j
-
+    i, j = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    i, j = i.reshape(-1), j.reshape(-1)
+    v00, v10 = i * (n + 1) + j, (i + 1) * (n + 1) + j
+    v01, v11 = v00 + 1, v10 + 1
     cells = np.empty((2 * n * n, 3), dtype=np.int64)
-    k = 0
-    for i in range(n):
-        for j in range(n):
-            v00, v10, v01, v11 = vid(i, j), vid(i + 1, j), vid(i, j + 1), vid(i + 1, j + 1)
-            cells[k] = (v00, v10, v11)
-            cells[k + 1] = (v00, v11, v01)
-            k += 2
+    cells[0::2] = np.stack([v00, v10, v11], axis=1)
+    cells[1::2] = np.stack([v00, v11, v01], axis=1)
     return verts, cells
 
 
