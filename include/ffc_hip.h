@@ -175,6 +175,33 @@ int ffc_batch_run(ffc_batch* batch);
 int ffc_batch_info(const ffc_batch* batch, int64_t* total_cells, int64_t* work_units, int32_t* grid);
 void ffc_batch_destroy(ffc_batch* batch);
 
+/* Kernel selector network.  A multilayer perceptron that predicts the log run time of each
+ * candidate launch (tensor or quadrature kernel, launch shape) of a tabulation from its
+ * features (form rank, degree, |i|, |alpha|, dimension, cells); the candidate with the
+ * smallest prediction is chosen -- the automatic choice between tensor representation
+ * and quadrature that Sec. 4.4 leaves to future work.  It is trained on the GPU with these
+ * kernels (FP32):
+ *   y = relu(relu(x W1 + b1) W2 + b2) W3 + b3,
+ * parameters in one flat array: W1 [n_in][n_hidden], b1 [n_hidden], W2 [n_hidden][n_hidden],
+ * b2 [n_hidden], W3 [n_hidden][n_out], b3 [n_out] (ffc_mlp_param_count floats).
+ * All pointers are device pointers, caller-owned; calls are asynchronous on `stream`. */
+int64_t ffc_mlp_param_count(int32_t n_in, int32_t n_hidden, int32_t n_out);
+/* x [batch][n_in] -> y [batch][n_out]; act (workspace, 2*batch*n_hidden floats) keeps the two
+ * hidden activations for the backward pass. */
+int ffc_mlp_forward(int32_t n_in, int32_t n_hidden, int32_t n_out, int64_t batch, const float* params,
+                    const float* x, float* act, float* y, void* stream);
+/* Gradient of a loss with dL/dy = dy [batch][n_out] w.r.t. the parameters, written to grad
+ * (ffc_mlp_param_count floats); act from the forward pass; work: 2*batch*n_hidden floats. */
+int ffc_mlp_backward(int32_t n_in, int32_t n_hidden, int32_t n_out, int64_t batch, const float* params,
+                     const float* x, const float* act, const float* dy, float* grad, float* work, void* stream);
+/* Masked mean squared error over n values: loss[0] = sum m (y - t)^2 / sum m,
+ * dy = 2 m (y - t) / sum m. */
+int ffc_mlp_mse(int64_t n, const float* y, const float* target, const float* mask, float* dy, float* loss,
+                void* stream);
+/* One Adam step (bias-corrected, step >= 1) on n parameters with gradient g and moments m, v. */
+int ffc_adam_step(int64_t n, float* params, const float* grad, float* m, float* v, float lr, float beta1,
+                  float beta2, float eps, int32_t step, void* stream);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char* ffc_last_error(void);
 

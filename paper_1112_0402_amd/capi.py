@@ -86,6 +86,15 @@ def lib():
     L.ffc_batch_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i32)]
     L.ffc_batch_destroy.argtypes = [vp]
     L.ffc_batch_destroy.restype = None
+    fp = ctypes.c_float
+    L.ffc_mlp_param_count.argtypes = [i32, i32, i32]
+    L.ffc_mlp_param_count.restype = i64
+    L.ffc_mlp_forward.argtypes = [i32, i32, i32, i64, vp, vp, vp, vp, vp]
+    L.ffc_mlp_backward.argtypes = [i32, i32, i32, i64, vp, vp, vp, vp, vp, vp, vp]
+    L.ffc_mlp_mse.argtypes = [i64, vp, vp, vp, vp, vp, vp]
+    L.ffc_adam_step.argtypes = [i64, vp, vp, vp, vp, fp, fp, fp, fp, i32, vp]
+    for name in ("ffc_mlp_forward", "ffc_mlp_backward", "ffc_mlp_mse", "ffc_adam_step"):
+        getattr(L, name).restype = ctypes.c_int
     for name in ("ffc_compile_reference_tensor", "ffc_form_create", "ffc_form_get_info", "ffc_tabulate_tensor",
                  "ffc_tabulate_tensor_affine",
                  "ffc_compute_geometry", "ffc_batch_create", "ffc_batch_run", "ffc_batch_info"):

@@ -10,6 +10,7 @@
 
 #include "../../include/ffc_hip.h"
 #include "kernels.h"
+#include "mlp.h"
 #include "reference_tensor.h"
 
 namespace {
@@ -58,8 +59,10 @@ int upload(const std::vector<T>& host, T** dev) {
 
 bool valid_tile(int t) { return t == 16 || t == 32 || t == 64; }
 
-// default grouping of output entries into FP64 MFMA tiles: greedy clustering over all rows
-constexpr int kDefaultTileWindow = -1;
+// Element tensors with at least this many entries use the persistent FP64 kernel by
+// default; below it a 16-cell tile carries too little output to pay for the per-tile
+// pipeline (measured: persistent wins at 900 entries, loses at 400 and below).
+constexpr int kPersistentMinEntries = 576;
 bool valid_waves(int w) { return w == 1 || w == 2 || w == 4 || w == 8 || w == 16; }
 
 int check_desc(const ffc_form_desc* d, ffc::FormSpec* spec) {
@@ -175,7 +178,9 @@ int ffc_form_create(const ffc_form_desc* desc, ffc_form** out) {
             (rc = upload(qt.dphi, &f->d_dphi)))
             return rc;
     } else if (desc->precision == FFC_FP64) {
-        f->tile_window = desc->tile_window ? desc->tile_window : kDefaultTileWindow;
+        // default grouping: greedy clustering over all rows for large element tensors (the
+        // persistent kernel), consecutive rows for small ones (64-cell tiles)
+        f->tile_window = desc->tile_window ? desc->tile_window : (rt.n_I >= kPersistentMinEntries ? -1 : 16);
         ffc::TilesF64 t = ffc::make_tiles_f64(rt, f->tile_window);
         f->n_tiles = t.n_tiles;
         f->mfma_k = t.koff.back();
@@ -185,7 +190,9 @@ int ffc_form_create(const ffc_form_desc* desc, ffc_form** out) {
         // persistent workgroups: 16 waves with up to 16 register-resident k steps each, or
         // 8 waves with up to 32; the 16-cell output rows must be stageable in LDS
         const ffc::LdsPlan pl = ffc::plan_lds(spec.dim, spec.kind, 16, rt.n_I, rt.n_alpha, 0, false, ffc::kLdsBudget);
-        if (desc->persistent >= 0 && pl.staged && (desc->tile_cells == 0 || desc->tile_cells == 16)) {
+        const bool want_persistent =
+            desc->persistent == 1 || (desc->persistent == 0 && rt.n_I >= kPersistentMinEntries);
+        if (want_persistent && pl.staged && (desc->tile_cells == 0 || desc->tile_cells == 16)) {
             ffc::WaveSchedule ws;
             for (int w : {16}) {
                 if (desc->waves != 0 && desc->waves != w) continue;
@@ -224,21 +231,25 @@ int ffc_form_create(const ffc_form_desc* desc, ffc_form** out) {
         const size_t bytes = static_cast<size_t>(f->amap_cap) * (1 + spec.dim * spec.dim) * sizeof(double);
         if (hipMalloc(reinterpret_cast<void**>(&f->d_amap), bytes) != hipSuccess)
             return fail(FFC_E_NOMEM, "hipMalloc failed for the geometry workspace");
-        // default launch shape: the largest cell tile whose output rows can be staged in LDS
-        // (contiguous full-line writes), 16 waves for 16-cell tiles, 8 otherwise; with no
-        // staging possible, 64-cell tiles with direct stores.
+        // default launch shape when the persistent kernel does not apply (no staging fits, or
+        // the launch falls back): see the tile-size choice below; 16 waves for 16-cell
+        // tiles, 8 for split-mode tiles, 4 for 64-cell FP64 tiles.
         const bool bf = desc->precision != FFC_FP64;
         if (f->tile_cells == 0) {
+            // FP64: 64-cell tiles (staged when they fit), except that large tensors without
+            // the persistent kernel stage 16-cell tiles; split modes: the largest stageable
+            // tile among 64 / 32 / 16 cells
             f->tile_cells = 64;
-            for (int ct : {64, 32, 16}) {
-                ffc::LdsPlan p = ffc::plan_lds(spec.dim, spec.kind, ct, rt.n_I, rt.n_alpha, f->kpad, bf, ffc::kLdsBudget);
-                if (p.staged && p.total <= (ct == 16 ? ffc::kLdsBudget : ffc::kLdsBudget / 2 + 8192)) {
-                    f->tile_cells = ct;
-                    break;
+            if (bf || rt.n_I >= kPersistentMinEntries)
+                for (int ct : {64, 32, 16}) {
+                    ffc::LdsPlan p = ffc::plan_lds(spec.dim, spec.kind, ct, rt.n_I, rt.n_alpha, f->kpad, bf, ffc::kLdsBudget);
+                    if (p.staged && p.total <= (ct == 16 ? ffc::kLdsBudget : ffc::kLdsBudget / 2 + 8192)) {
+                        f->tile_cells = ct;
+                        break;
+                    }
                 }
-            }
         }
-        if (f->waves == 0) f->waves = f->tile_cells == 16 ? 16 : 8;
+        if (f->waves == 0) f->waves = f->tile_cells == 16 ? 16 : bf ? 8 : 4;
         const size_t lds = ffc::contract_lds_bytes(spec.dim, spec.kind, f->tile_cells, rt.n_I, rt.n_alpha, f->kpad, bf);
         if (lds > ffc::kLdsBudget) return fail(FFC_E_UNSUPPORTED, "tile does not fit the 160 KiB LDS of a CU");
     }
@@ -489,5 +500,44 @@ int ffc_batch_info(const ffc_batch* b, int64_t* total_cells, int64_t* work_units
 }
 
 void ffc_batch_destroy(ffc_batch* b) { delete b; }
+
+// ------------------------------------------------------------- selector network ----
+
+int64_t ffc_mlp_param_count(int32_t n_in, int32_t n_hidden, int32_t n_out) {
+    if (n_in <= 0 || n_hidden <= 0 || n_out <= 0) return fail(FFC_E_INVALID, "MLP sizes must be positive");
+    return ffc::mlp_param_count(n_in, n_hidden, n_out);
+}
+
+int ffc_mlp_forward(int32_t n_in, int32_t n_hidden, int32_t n_out, int64_t batch, const float* params,
+                    const float* x, float* act, float* y, void* stream) {
+    if (n_in <= 0 || n_hidden <= 0 || n_out <= 0 || batch < 0) return fail(FFC_E_INVALID, "bad MLP sizes");
+    if (batch == 0) return FFC_OK;
+    if (!params || !x || !act || !y) return fail(FFC_E_INVALID, "NULL MLP buffer");
+    hipError_t e = ffc::mlp_forward(n_in, n_hidden, n_out, batch, params, x, act, y, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? FFC_OK : hip_fail(e, "MLP forward launch");
+}
+
+int ffc_mlp_backward(int32_t n_in, int32_t n_hidden, int32_t n_out, int64_t batch, const float* params,
+                     const float* x, const float* act, const float* dy, float* grad, float* work, void* stream) {
+    if (n_in <= 0 || n_hidden <= 0 || n_out <= 0 || batch <= 0) return fail(FFC_E_INVALID, "bad MLP sizes");
+    if (!params || !x || !act || !dy || !grad || !work) return fail(FFC_E_INVALID, "NULL MLP buffer");
+    hipError_t e = ffc::mlp_backward(n_in, n_hidden, n_out, batch, params, x, act, dy, grad, work,
+                                     static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? FFC_OK : hip_fail(e, "MLP backward launch");
+}
+
+int ffc_mlp_mse(int64_t n, const float* y, const float* target, const float* mask, float* dy, float* loss,
+                void* stream) {
+    if (n <= 0 || !y || !target || !mask || !dy || !loss) return fail(FFC_E_INVALID, "bad MSE arguments");
+    hipError_t e = ffc::mlp_mse(n, y, target, mask, dy, loss, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? FFC_OK : hip_fail(e, "MSE launch");
+}
+
+int ffc_adam_step(int64_t n, float* params, const float* grad, float* m, float* v, float lr, float beta1,
+                  float beta2, float eps, int32_t step, void* stream) {
+    if (n <= 0 || !params || !grad || !m || !v || step < 1) return fail(FFC_E_INVALID, "bad Adam arguments");
+    hipError_t e = ffc::adam_step(n, params, grad, m, v, lr, beta1, beta2, eps, step, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? FFC_OK : hip_fail(e, "Adam launch");
+}
 
 }  // extern "C"

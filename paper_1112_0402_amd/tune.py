@@ -1,0 +1,181 @@
+"""Autotuner for the tabulation launches.
+
+For one (form, dim, degree, precision, mesh) it times every candidate launch -- the tensor
+kernel in its launch shapes and, in FP64, the quadrature kernel -- with HIP events on the
+launch stream, and keeps the fastest.  Results go to a JSON tuning database keyed by form
+and log2(cells); sweeps over many shapes are appended to a JSON-lines file and resume
+where an interrupted sweep stopped.  The exhaustive search is also the judge of the learned
+selector's choices (its regret is measured against it).
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+
+import numpy as np
+
+# Candidate launches.  Index order is part of the sweep-file format (the selector's outputs).
+CANDIDATES_FP64 = (
+    {"kernel": "tensor", "tile_cells": 0, "waves": 0, "persistent": 0, "tile_window": 0},      # library default
+    {"kernel": "tensor", "tile_cells": 16, "waves": 16, "persistent": -1, "tile_window": -1},  # staged, clustered
+    {"kernel": "tensor", "tile_cells": 64, "waves": 8, "persistent": -1, "tile_window": -1},
+    {"kernel": "tensor", "tile_cells": 64, "waves": 4, "persistent": -1, "tile_window": 16},   # consecutive rows
+    {"kernel": "tensor", "tile_cells": 32, "waves": 8, "persistent": -1, "tile_window": 16},
+    {"kernel": "quadrature"},
+)
+CANDIDATES_SPLIT = (
+    {"kernel": "tensor", "tile_cells": 0, "waves": 0},
+    {"kernel": "tensor", "tile_cells": 64, "waves": 4},
+    {"kernel": "tensor", "tile_cells": 32, "waves": 8},
+    {"kernel": "tensor", "tile_cells": 16, "waves": 8},
+)
+
+
+def candidates(precision: str):
+    return CANDIDATES_FP64 if precision == "fp64" else CANDIDATES_SPLIT
+
+
+def make_form(kind, dim, degree, precision, cand):
+    from .forms import Form
+
+    return Form(kind, dim, degree, precision=precision if cand["kernel"] == "tensor" else "fp64",
+                kernel=cand["kernel"], tile_cells=cand.get("tile_cells", 0), waves=cand.get("waves", 0),
+                persistent=cand.get("persistent", 0), tile_window=cand.get("tile_window", 0))
+
+
+def measure(form, X, C, reps: int = 5, warmup: int = 2) -> float:
+    """Median milliseconds of one tabulation (geometry + contraction, or quadrature)."""
+    import torch
+
+    out = form.empty_out(X.shape[1])
+    stream = form.stream
+    for _ in range(warmup):
+        form.tabulate(X, C, out=out)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        form.tabulate(X, C, out=out)
+        b.record(stream)
+        b.synchronize()
+        times.append(a.elapsed_time(b))
+    return float(np.median(times))
+
+
+def shape_key(kind, dim, degree, precision, cells) -> str:
+    return f"{kind}/{dim}/{degree}/{precision}/{int(round(math.log2(max(cells, 1))))}"
+
+
+class TuneDB:
+    """JSON map shape key -> {"candidate": index, "config": ..., "ms": ...}."""
+
+    def __init__(self, path: str | None = None):
+        self.path = path or os.environ.get("FFC_TUNE_DB", "")
+        self.db = {}
+        if self.path and os.path.exists(self.path):
+            with open(self.path) as f:
+                self.db = json.load(f)
+
+    def put(self, key, entry):
+        self.db[key] = entry
+        if self.path:
+            tmp = self.path + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(self.db, f, indent=1, sort_keys=True)
+            os.replace(tmp, self.path)
+
+    def lookup(self, kind, dim, degree, precision, cells):
+        """Entry of the nearest cell-count bucket for this form, or None."""
+        best, dist = None, None
+        lc = math.log2(max(cells, 1))
+        prefix = f"{kind}/{dim}/{degree}/{precision}/"
+        for k, v in self.db.items():
+            if k.startswith(prefix):
+                d = abs(int(k.rsplit("/", 1)[1]) - lc)
+                if dist is None or d < dist:
+                    best, dist = v, d
+        return best
+
+
+def autotune(kind, dim, degree, precision, X, C, db: TuneDB | None = None, reps: int = 5):
+    """Time every candidate on this mesh; return (index, config, ms list)."""
+    times = []
+    for cand in candidates(precision):
+        form = make_form(kind, dim, degree, precision, cand)
+        times.append(measure(form, X, C, reps))
+        form.close()
+    best = int(np.argmin(times))
+    if db is not None:
+        db.put(shape_key(kind, dim, degree, precision, X.shape[1]),
+               {"candidate": best, "config": candidates(precision)[best], "ms": times[best], "all_ms": times})
+    return best, candidates(precision)[best], times
+
+
+def sweep_shapes(variants, cells_list):
+    return [(k, d, q, c) for (k, d, q) in variants for c in cells_list]
+
+
+def sweep(shapes, path: str, precision: str = "fp64", reps: int = 5, seed: int = 5, log=print):
+    """Time every candidate on every shape; one JSON line per shape, appended to `path`;
+    shapes already in the file are skipped (resume)."""
+    import torch
+
+    from . import meshgen
+    from .forms import Form
+
+    done = set()
+    if os.path.exists(path):
+        for line in open(path):
+            r = json.loads(line)
+            done.add((r["kind"], r["dim"], r["degree"], r["precision"], r["cells"]))
+    forms = {}
+    for i, (kind, dim, degree, cells) in enumerate(shapes):
+        if (kind, dim, degree, precision, cells) in done:
+            continue
+        n = math.ceil(math.sqrt(cells / 2.0)) if dim == 2 else math.ceil((cells / 6.0) ** (1.0 / 3.0))
+        wl = meshgen.make_workload(kind, dim, degree, max(n, 1), seed + i, max_cells=cells)
+        X = torch.from_numpy(wl.coords).cuda()
+        C = None if wl.coeffs is None else torch.from_numpy(wl.coeffs).cuda()
+        times = []
+        for j, cand in enumerate(candidates(precision)):
+            key = (kind, dim, degree, j)
+            if key not in forms:
+                forms[key] = make_form(kind, dim, degree, precision, cand)
+            times.append(measure(forms[key], X, C, reps))
+        info = Form(kind, dim, degree, precision=precision).info
+        rec = {"kind": kind, "dim": dim, "degree": degree, "precision": precision, "cells": cells,
+               "n_I": info["n_entries"], "n_alpha": info["n_alpha"], "ms": times, "time": time.time()}
+        with open(path, "a") as f:
+            f.write(json.dumps(rec) + "\n")
+        log(f"sweep {kind} d={dim} q={degree} cells={cells}: best {int(np.argmin(times))} "
+            f"({min(times):.4f} ms) of {[round(t, 4) for t in times]}")
+    return path
+
+
+def load_sweep(path: str):
+    with open(path) as f:
+        return [json.loads(line) for line in f if line.strip()]
+
+
+def default_sweep_shapes():
+    """The mixed-batch form variants plus the two large single-form workloads, each at
+    cell counts 2^10 .. 2^19."""
+    from .meshgen import BATCH_VARIANTS
+
+    variants = list(BATCH_VARIANTS) + [("elasticity", 3, 2), ("wlaplace", 3, 3)]
+    return sweep_shapes(variants, [2 ** k for k in (10, 12, 14, 16, 18, 19)])
+
+
+if __name__ == "__main__":
+    import argparse
+
+    ap = argparse.ArgumentParser(description="time every candidate launch on a sweep of shapes (resumable)")
+    ap.add_argument("--out", required=True, help="JSON-lines file to append to")
+    ap.add_argument("--precision", default="fp64")
+    ap.add_argument("--reps", type=int, default=5)
+    args = ap.parse_args()
+    sweep(default_sweep_shapes(), args.out, precision=args.precision, reps=args.reps,
+          log=lambda s: print(s, flush=True))

@@ -1,0 +1,69 @@
+"""CPU checks of the selector's reference network, heuristic, regret and tuning DB."""
+import math
+
+import numpy as np
+
+from paper_1112_0402_amd import selector, tune
+
+
+def _rand_params(n_in, h, n_out, seed=0):
+    rng = np.random.default_rng(seed)
+    n = n_in * h + h + h * h + h + h * n_out + n_out
+    return rng.normal(0, 0.5, size=n)
+
+
+def test_reference_backward_matches_finite_differences():
+    n_in, h, n_out = 6, 8, 5
+    p = _rand_params(n_in, h, n_out)
+    rng = np.random.default_rng(1)
+    x = rng.normal(size=(7, n_in))
+    dy = rng.normal(size=(7, n_out))
+    g = selector.ref_backward(p, x, dy, n_in, h, n_out)
+    eps = 1e-6
+    for k in rng.choice(p.size, size=40, replace=False):
+        e = np.zeros_like(p)
+        e[k] = eps
+        fp = (selector.ref_forward(p + e, x, n_in, h, n_out)[0] * dy).sum()
+        fm = (selector.ref_forward(p - e, x, n_in, h, n_out)[0] * dy).sum()
+        assert abs((fp - fm) / (2 * eps) - g[k]) < 1e-6 * (1 + abs(g[k]))
+
+
+def test_reference_mse():
+    y = np.array([[1.0, 2.0], [3.0, 5.0]])
+    t = np.array([[0.0, 2.0], [3.0, 1.0]])
+    m = np.array([[1.0, 1.0], [0.0, 1.0]])
+    loss, dy = selector.ref_mse(y, t, m)
+    assert math.isclose(loss, (1 + 0 + 16) / 3)
+    assert np.allclose(dy, 2 * (y - t) * m / 3)
+
+
+def test_heuristic_follows_paper_complexity_model():
+    # mass: speedup (2q)^d > 1 -> tensor representation for every q >= 1
+    for d in (2, 3):
+        for q in (1, 2, 3):
+            assert selector.heuristic_choice("mass", d, q) == 0
+    assert selector.heuristic_choice("laplace", 3, 2) == 0
+
+
+def test_regret_and_features():
+    recs = [{"ms": [2.0, 1.0, 4.0, 1.0, 1.0, 3.0]}, {"ms": [1.0, 2.0, 2.0, 2.0, 2.0, 0.5]}]
+    r = selector.regret(recs, [0, 5])
+    assert np.allclose(r, [1.0, 0.0])
+    f = selector.features("laplace", 3, 2, 1024, 100, 9)
+    assert f.shape == (selector.N_FEATURES,) and f[-1] == 10
+
+
+def test_tune_db_roundtrip(tmp_path):
+    db = tune.TuneDB(str(tmp_path / "db.json"))
+    db.put(tune.shape_key("laplace", 3, 2, "fp64", 1 << 14), {"candidate": 2, "ms": 0.1})
+    db.put(tune.shape_key("laplace", 3, 2, "fp64", 1 << 18), {"candidate": 0, "ms": 0.5})
+    db2 = tune.TuneDB(str(tmp_path / "db.json"))
+    assert db2.lookup("laplace", 3, 2, "fp64", 20000)["candidate"] == 2
+    assert db2.lookup("laplace", 3, 2, "fp64", 300000)["candidate"] == 0
+    assert db2.lookup("mass", 3, 2, "fp64", 300000) is None
+
+
+def test_candidate_lists():
+    assert tune.CANDIDATES_FP64[-1]["kernel"] == "quadrature"
+    assert all(c["kernel"] == "tensor" for c in tune.CANDIDATES_SPLIT)
+    assert len(tune.default_sweep_shapes()) == 18 * 6

@@ -1,0 +1,116 @@
+"""GPU tests of the selector network kernels (against the FP64 NumPy statement), of the
+autotuner, and of what the trained selector gains over choosing without it."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1112_0402_amd import meshgen, selector, tune
+from tests.gpu_util import rel_fro, require_gpu, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+SWEEP = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1112_0402_amd", "data",
+                     "sweep_mi355x_fp64.jsonl")
+
+
+def test_mlp_kernels_match_fp64_reference():
+    require_gpu()
+    net = selector.MLP(n_in=6, n_hidden=32, n_out=6, seed=3)
+    rng = np.random.default_rng(0)
+    X = rng.normal(size=(300, 6))
+    x = torch.tensor(X, dtype=torch.float32, device="cuda")
+    y, act = net.forward(x)
+    p = net.params.cpu().numpy().astype(np.float64)
+    yref, _ = selector.ref_forward(p, x.cpu().numpy().astype(np.float64), 6, 32, 6)
+    assert np.allclose(y.cpu().numpy(), yref, rtol=1e-4, atol=1e-4)
+    T = rng.normal(size=(300, 6))
+    Mk = (rng.uniform(size=(300, 6)) > 0.2).astype(np.float64)
+    t = torch.tensor(T, dtype=torch.float32, device="cuda")
+    m = torch.tensor(Mk, dtype=torch.float32, device="cuda")
+    loss, dy = net.mse(y, t, m)
+    lref, dyref = selector.ref_mse(yref, T, Mk)
+    assert abs(float(loss.item()) - lref) < 1e-4 * max(1.0, lref)
+    assert np.allclose(dy.cpu().numpy(), dyref, rtol=1e-3, atol=1e-6)
+    g = net.backward(x, act, dy).cpu().numpy()
+    gref = selector.ref_backward(p, x.cpu().numpy().astype(np.float64), dy.cpu().numpy().astype(np.float64), 6, 32, 6)
+    err = np.abs(g - gref).max() / np.abs(gref).max()
+    say(f"[mlp] max rel gradient error vs FP64 reference {err:.2e}")
+    assert err < 1e-4
+    # one Adam step vs its definition
+    m0 = np.zeros_like(p)
+    v0 = np.zeros_like(p)
+    net.adam(lr=1e-2)
+    torch.cuda.synchronize()
+    m1 = 0.1 * g
+    v1 = 0.001 * g * g
+    pref = p - 1e-2 * (m1 / 0.1) / (np.sqrt(v1 / 0.001) + 1e-8)
+    assert np.allclose(net.params.cpu().numpy(), pref, rtol=1e-4, atol=1e-6)
+    assert np.all(m0 == 0) and np.all(v0 == 0)
+
+
+def test_autotuner_picks_fastest_and_is_exact():
+    require_gpu()
+    wl = meshgen.make_workload("laplace", 3, 2, 12, 21)  # 10,368 cells
+    X, C = to_dev(wl.coords), None
+    db = tune.TuneDB()
+    best, cfg, times = tune.autotune("laplace", 3, 2, "fp64", X, C, db=db, reps=3)
+    say(f"[tune] laplace P2 3D 10k cells: best {best} {cfg} times {[round(t, 4) for t in times]}")
+    assert times[best] == min(times)
+    assert db.lookup("laplace", 3, 2, "fp64", wl.cells)["candidate"] == best
+    out = tune.make_form("laplace", 3, 2, "fp64", cfg).tabulate(X, C)
+    torch.cuda.synchronize()
+    ref = oracle.tabulate("laplace", 3, 2, wl.coords)
+    assert rel_fro(out.cpu().numpy(), ref)[0] <= 1e-12
+
+
+def test_selector_beats_choosing_without_it():
+    """Train on two thirds of the stored sweep (every shape whose index is not 0 mod 3),
+    evaluate on the held-out third: mean regret against the exhaustive autotuner must be
+    lower than always taking the library default launch and lower than the paper's
+    analytic tensor-vs-quadrature rule."""
+    require_gpu()
+    if not os.path.exists(SWEEP):
+        pytest.skip("no stored sweep")
+    recs = tune.load_sweep(SWEEP)
+    train = [r for i, r in enumerate(recs) if i % 3 != 0]
+    test = [r for i, r in enumerate(recs) if i % 3 == 0]
+    sel = selector.Selector(n_hidden=64, seed=0)
+    loss = sel.fit(train, epochs=3000, lr=3e-3)
+    choice = sel.choose(test)
+    r_mlp = selector.regret(test, choice)
+    r_fixed = selector.regret(test, [0] * len(test))
+    r_heur = selector.regret(test, [selector.heuristic_choice(r["kind"], r["dim"], r["degree"]) for r in test])
+    t_best = sum(min(r["ms"]) for r in test)
+    t_mlp = sum(r["ms"][c] for r, c in zip(test, choice))
+    t_fixed = sum(r["ms"][0] for r in test)
+    say(f"[selector] train loss {loss:.4f}; held-out mean regret: mlp {r_mlp.mean():.3f} "
+        f"fixed {r_fixed.mean():.3f} heuristic {r_heur.mean():.3f}; total ms best {t_best:.3f} "
+        f"mlp {t_mlp:.3f} fixed {t_fixed:.3f}")
+    assert r_mlp.mean() < r_fixed.mean()
+    assert r_mlp.mean() < r_heur.mean()
+
+
+def test_selected_launch_is_exact():
+    """Whatever the selector picks, the element tensors are the oracle's."""
+    require_gpu()
+    if not os.path.exists(SWEEP):
+        pytest.skip("no stored sweep")
+    recs = tune.load_sweep(SWEEP)
+    sel = selector.Selector(seed=1)
+    sel.fit(recs, epochs=1500)
+    for kind, dim, q, n in (("laplace", 2, 1, 8), ("mass", 3, 2, 4), ("ns", 3, 2, 3)):
+        wl = meshgen.make_workload(kind, dim, q, n, 31)
+        from paper_1112_0402_amd.forms import Form
+
+        info = Form(kind, dim, q).info
+        rec = {"kind": kind, "dim": dim, "degree": q, "cells": wl.cells, "n_I": info["n_entries"],
+               "n_alpha": info["n_alpha"], "ms": [1.0] * len(tune.CANDIDATES_FP64)}
+        c = sel.choose([rec])[0]
+        out = tune.make_form(kind, dim, q, "fp64", tune.CANDIDATES_FP64[c]).tabulate(to_dev(wl.coords),
+                                                                                       to_dev(wl.coeffs))
+        torch.cuda.synchronize()
+        ref = oracle.tabulate(kind, dim, q, wl.coords, wl.coeffs)
+        assert rel_fro(out.cpu().numpy(), ref)[0] <= 1e-12, (kind, c)
