@@ -304,8 +304,8 @@ def bench_batch(args, torch, np):
         "dtype": "f64" if precision == "fp64" else precision + "->f32",
         "data": "synthetic",
         "config": {"workload": "batch64_mixed", "meshes": len(wls), "cells": cells, "precision": precision,
-                   "variants": len(forms), "work_units": b.work_units, "grid": b.grid},
-        "roofline": {"kernel": "batch_kernel", "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                   "variants": len(forms), "work_units": b.work_units, "launches": b.launches},
+        "roofline": {"kernel": "batch_persistent_kernel + batch_tiles_kernel", "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gbs / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes_per_launch": byt,
                      "ms_per_launch": ms},
         "per_mesh_launches": {"ms": ms_single, "value": cells / (ms_single * 1e-3),

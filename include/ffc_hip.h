@@ -162,17 +162,26 @@ int ffc_tabulate_tensor_affine(const ffc_form* form, int64_t cells, const double
  * default). */
 int ffc_compute_geometry(int32_t dim, int64_t cells, const double* coords, double* affine_map, void* stream);
 
-/* Mixed batches (many meshes, mixed forms, one persistent launch).  A batch is built
- * from `n` (form, cells, coords, coeffs, out) items; all forms must share one precision
- * and use the tensor kernel.  ffc_batch_run enqueues the whole batch as one launch of a
- * persistent kernel whose workgroups pull (item, cell-tile) work units from an atomic
- * queue.  The arrays are copied; the device pointers must stay valid while the batch
- * exists.  The batch owns its device-side work list. */
+/* Mixed batches (many meshes of uneven size, mixed forms and degrees; the level-3 BLAS
+ * batching of Sec. 4.5 taken across meshes).  A batch is built from `n` (form, cells,
+ * coords, coeffs, out) items; all forms must share one precision and use the tensor
+ * kernel.  ffc_batch_run enqueues a fixed, short sequence of launches on `stream` (fit
+ * for graph capture; no memset, no allocation):
+ *   - FP64 items whose form uses the persistent contraction: one geometry pass each into
+ *     a batch-owned workspace, then one persistent launch per (dim, form kind, register
+ *     schedule depth) whose workgroups claim chunks of 16-cell tiles of any of its items
+ *     from an atomic queue (the queue counters reset themselves at the end of every run);
+ *   - every other item: one launch per group of items sharing a workgroup size and an LDS
+ *     size class, one workgroup per cell tile, geometry computed in place.
+ * Results equal those of ffc_tabulate_tensor on each item.  The arrays are copied; the
+ * device pointers must stay valid while the batch exists; runs of one batch must not
+ * overlap (they share the queue counters).  ffc_batch_info: total cells, work units
+ * (tiles plus claims) and the number of kernel launches one run enqueues. */
 typedef struct ffc_batch ffc_batch;
 int ffc_batch_create(int32_t n, const ffc_form* const* forms, const int64_t* cells, const double* const* coords,
                      const double* const* coeffs, void* const* outs, void* stream, ffc_batch** batch);
 int ffc_batch_run(ffc_batch* batch);
-int ffc_batch_info(const ffc_batch* batch, int64_t* total_cells, int64_t* work_units, int32_t* grid);
+int ffc_batch_info(const ffc_batch* batch, int64_t* total_cells, int64_t* work_units, int32_t* launches);
 void ffc_batch_destroy(ffc_batch* batch);
 
 /* Kernel selector network.  A multilayer perceptron that predicts the log run time of each

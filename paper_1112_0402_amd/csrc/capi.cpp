@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <string>
 #include <vector>
@@ -231,25 +232,40 @@ int ffc_form_create(const ffc_form_desc* desc, ffc_form** out) {
         const size_t bytes = static_cast<size_t>(f->amap_cap) * (1 + spec.dim * spec.dim) * sizeof(double);
         if (hipMalloc(reinterpret_cast<void**>(&f->d_amap), bytes) != hipSuccess)
             return fail(FFC_E_NOMEM, "hipMalloc failed for the geometry workspace");
-        // default launch shape when the persistent kernel does not apply (no staging fits, or
-        // the launch falls back): see the tile-size choice below; 16 waves for 16-cell
-        // tiles, 8 for split-mode tiles, 4 for 64-cell FP64 tiles.
+        // default launch shape when the persistent kernel does not apply
         const bool bf = desc->precision != FFC_FP64;
+        auto plan = [&](int ct) {
+            return ffc::plan_lds(spec.dim, spec.kind, ct, rt.n_I, rt.n_alpha, f->kpad, bf, ffc::kLdsBudget);
+        };
+        int dw = 0;  // default waves
         if (f->tile_cells == 0) {
-            // FP64: 64-cell tiles (staged when they fit), except that large tensors without
-            // the persistent kernel stage 16-cell tiles; split modes: the largest stageable
-            // tile among 64 / 32 / 16 cells
-            f->tile_cells = 64;
-            if (bf || rt.n_I >= kPersistentMinEntries)
+            if (!bf && rt.n_I < kPersistentMinEntries) {
+                // small FP64 tensors (measured on MI355X): 64-cell tiles staged in at most
+                // 40 KiB of LDS (several workgroups per CU); else 32-cell tiles staged in at
+                // most 80 KiB (two per CU); else 64-cell tiles written directly (consecutive
+                // output rows per MFMA tile keep those writes in whole 128-byte runs)
+                const ffc::LdsPlan p64 = plan(64), p32 = plan(32);
+                if (p64.staged && p64.total <= 40 * 1024) {
+                    f->tile_cells = 64, dw = 4;
+                } else if (p32.staged && p32.total <= 80 * 1024) {
+                    f->tile_cells = 32, dw = 8;
+                } else {
+                    f->tile_cells = 64, dw = 4;
+                }
+            } else {
+                // large FP64 tensors without the persistent kernel, and the split modes: the
+                // largest stageable tile among 64 / 32 / 16 cells
+                f->tile_cells = 64;
                 for (int ct : {64, 32, 16}) {
-                    ffc::LdsPlan p = ffc::plan_lds(spec.dim, spec.kind, ct, rt.n_I, rt.n_alpha, f->kpad, bf, ffc::kLdsBudget);
+                    const ffc::LdsPlan p = plan(ct);
                     if (p.staged && p.total <= (ct == 16 ? ffc::kLdsBudget : ffc::kLdsBudget / 2 + 8192)) {
                         f->tile_cells = ct;
                         break;
                     }
                 }
+            }
         }
-        if (f->waves == 0) f->waves = f->tile_cells == 16 ? 16 : bf ? 8 : 4;
+        if (f->waves == 0) f->waves = dw ? dw : f->tile_cells == 16 ? 16 : bf ? 8 : 4;
         const size_t lds = ffc::contract_lds_bytes(spec.dim, spec.kind, f->tile_cells, rt.n_I, rt.n_alpha, f->kpad, bf);
         if (lds > ffc::kLdsBudget) return fail(FFC_E_UNSUPPORTED, "tile does not fit the 160 KiB LDS of a CU");
     }
@@ -390,48 +406,88 @@ int ffc_tabulate_tensor(const ffc_form* f, int64_t cells, const double* coords, 
 
 // ------------------------------------------------------------------ batches ----
 
-struct ffc_batch {
+// One launch of a batch: a tile launch over a group of items, or the persistent launch of
+// one form's items.  Each launch has its own device copy of its items' descriptors.
+struct BatchLaunch {
+    bool persistent = false;
+    int dim = 0, kind = 0, kmax = 0;  // persistent launches
     std::vector<ffc::BatchItem> items;
     ffc::BatchItem* d_items = nullptr;
-    int* d_counter = nullptr;
+    int32_t* d_unit_item = nullptr;  // tile launches: [units] item of each tile
+    int64_t units = 0;               // tiles
+    int waves = 16, mt = 1, grid = 0;  // tile launches: workgroup size and tile size 16*mt
+    size_t lds = 0, stage_cap = 0, head_cap = 0;
+};
+
+struct ffc_batch {
+    std::vector<BatchLaunch> launches;
+    struct Geo {
+        int dim;
+        int64_t cells;
+        const double* coords;
+        double* amap;
+    };
+    std::vector<Geo> geometry;  // geometry passes of the persistent items
+    double* d_amap = nullptr;
     int64_t total_cells = 0, total_units = 0;
-    int grid = 0;
-    bool bf16 = false;
-    size_t lds = 0, stage_cap = 0;
+    int nseg = 0;
     hipStream_t stream = nullptr;
     ~ffc_batch() {
-        if (d_items) (void)hipFree(d_items);
-        if (d_counter) (void)hipFree(d_counter);
+        for (auto& l : launches) {
+            if (l.d_unit_item) (void)hipFree(l.d_unit_item);
+            if (l.d_items) (void)hipFree(l.d_items);
+        }
+        if (d_amap) (void)hipFree(d_amap);
     }
 };
+
+namespace {
+// Tile launches are grouped by workgroup size, tile size and LDS size class, so that each
+// kernel has the register count of its own tile and small-LDS items keep several
+// workgroups per CU.
+int lds_class(size_t bytes) { return bytes <= 40 * 1024 ? 0 : bytes <= 80 * 1024 ? 1 : 2; }
+}  // namespace
 
 int ffc_batch_create(int32_t n, const ffc_form* const* forms, const int64_t* cells, const double* const* coords,
                      const double* const* coeffs, void* const* outs, void* stream, ffc_batch** out) {
     if (!out) return fail(FFC_E_INVALID, "batch output pointer is NULL");
     *out = nullptr;
     if (n <= 0 || !forms || !cells || !coords || !outs) return fail(FFC_E_INVALID, "empty batch or NULL array");
+    int dev;
+    int rc = check_device(&dev);
+    if (rc) return rc;
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
     std::unique_ptr<ffc_batch> b(new ffc_batch());
     b->stream = static_cast<hipStream_t>(stream);
-    int max_alpha = 1, max_kpad = 0;
-    int64_t units = 0;
+    bool bf16 = false;
+    std::map<const ffc_form*, std::vector<ffc::BatchItem>> pgroups;  // persistent launches, per form
+    std::map<int, std::vector<ffc::BatchItem>> tgroups;              // tile launches
+    int64_t amap_doubles = 0;
     for (int i = 0; i < n; ++i) {
         const ffc_form* f = forms[i];
         if (!f) return fail(FFC_E_INVALID, "NULL form in batch");
         if (f->desc.kernel != FFC_KERNEL_TENSOR) return fail(FFC_E_UNSUPPORTED, "batches use the tensor kernel only");
         const bool bf = f->desc.precision != FFC_FP64;
-        if (i == 0) b->bf16 = bf;
-        if (bf != b->bf16) return fail(FFC_E_INVALID, "all forms of a batch must share one precision");
+        if (i == 0) {
+            bf16 = bf;
+            b->nseg = bf ? f->n_seg : 0;
+        }
+        if (bf != bf16 || (bf && f->n_seg != b->nseg))
+            return fail(FFC_E_INVALID, "all forms of a batch must share one precision");
         if (cells[i] < 0) return fail(FFC_E_INVALID, "cells < 0");
         if (cells[i] > 0 && (!coords[i] || !outs[i])) return fail(FFC_E_INVALID, "NULL coords / out in batch");
         if (cells[i] > 0 && f->rt.n_coeff > 0 && (!coeffs || !coeffs[i]))
             return fail(FFC_E_INVALID, "batch item needs coefficients");
+        b->total_cells += cells[i];
+        if (cells[i] == 0) continue;
+        const int d = f->desc.dim;
         ffc::BatchItem it{};
         it.cells = cells[i];
-        it.unit_begin = units;
         it.coords = coords[i];
         it.coeffs = coeffs ? coeffs[i] : nullptr;
         it.out = outs[i];
-        it.dim = f->desc.dim;
+        it.dim = d;
         it.kind = f->desc.kind;
         it.n_I = f->rt.n_I;
         it.n_alpha = f->rt.n_alpha;
@@ -446,56 +502,108 @@ int ffc_batch_create(int32_t n, const ffc_form* const* forms, const int64_t* cel
         it.bb = f->d_bb;
         it.nonzero = f->d_nz;
         std::copy(f->gpiece, f->gpiece + 6, it.gpiece);
-        units += (cells[i] + ffc::kBatchCT - 1) / ffc::kBatchCT;
-        b->total_cells += cells[i];
-        max_alpha = std::max(max_alpha, f->rt.n_alpha);
-        max_kpad = std::max(max_kpad, f->kpad);
-        b->items.push_back(it);
+        const bool aligned = (reinterpret_cast<uintptr_t>(outs[i]) & 15u) == 0;
+        const ffc::LdsPlan p16 = ffc::plan_lds(d, f->desc.kind, 16, f->rt.n_I, f->rt.n_alpha, 0, false, ffc::kLdsBudget);
+        if (!bf && f->pwaves == 16 && aligned && p16.staged &&
+            (1 + d * d + f->rt.n_coeff) * 16 <= 64 * (16 - ffc::kIoWaves)) {
+            it.kmax = f->pkmax;
+            it.p = ffc::PersistArgs{f->d_woff, f->d_step_kstep, f->d_step_end, f->d_zero, f->n_zero};
+            it.stage_bytes = p16.stage_bytes;
+            it.head_bytes = p16.head_bytes;
+            amap_doubles += cells[i] * (1 + d * d);
+            pgroups[f].push_back(it);
+        } else {
+            const int ct = f->tile_cells;
+            it.mt = ct / 16;
+            const ffc::LdsPlan pl = ffc::plan_lds(d, f->desc.kind, ct, f->rt.n_I, f->rt.n_alpha, f->kpad, bf,
+                                                  ffc::kLdsBudget);
+            it.staged = pl.staged && aligned;
+            const size_t lds = (it.staged ? pl.stage_bytes : 0) + pl.head_bytes + pl.g_bytes;
+            tgroups[(f->waves << 8) | (it.mt << 4) | lds_class(lds)].push_back(it);
+        }
     }
-    b->total_units = units;
-    // stage the outputs of every item whose 16 rows fit next to the largest G tile
-    int stage_nI = 0;
-    for (const auto& it : b->items)
-        if (ffc::batch_lds_bytes(max_alpha, max_kpad, it.n_I, b->bf16) <= ffc::kLdsBudget)
-            stage_nI = std::max(stage_nI, static_cast<int>(it.n_I));
-    b->lds = ffc::batch_lds_bytes(max_alpha, max_kpad, stage_nI, b->bf16);
-    b->stage_cap = ffc::batch_lds_bytes(max_alpha, max_kpad, stage_nI, b->bf16) -
-                   ffc::batch_lds_bytes(max_alpha, max_kpad, 0, b->bf16);
-    if (b->lds > ffc::kLdsBudget) return fail(FFC_E_UNSUPPORTED, "batch tile does not fit LDS");
-    int dev;
-    int rc = check_device(&dev);
-    if (rc) return rc;
-    hipDeviceProp_t prop;
-    HIP_TRY(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
-    const int per_cu = std::max(1, std::min(2, static_cast<int>((160 * 1024) / std::max<size_t>(b->lds, 1))));
-    const int64_t claims = (units + ffc::kBatchChunk - 1) / ffc::kBatchChunk;
-    b->grid = static_cast<int>(std::min<int64_t>(static_cast<int64_t>(prop.multiProcessorCount) * per_cu,
-                                                 std::max<int64_t>(claims, 1)));
-    if (hipMalloc(reinterpret_cast<void**>(&b->d_items), n * sizeof(ffc::BatchItem)) != hipSuccess ||
-        hipMalloc(reinterpret_cast<void**>(&b->d_counter), 2 * sizeof(int)) != hipSuccess)
-        return fail(FFC_E_NOMEM, "hipMalloc failed for the batch work list");
-    HIP_TRY(hipMemcpy(b->d_items, b->items.data(), n * sizeof(ffc::BatchItem), hipMemcpyHostToDevice), "hipMemcpy");
-    // queue counters start at zero; every run leaves them at zero again (last workgroup out)
-    const int zeros[2] = {0, 0};
-    HIP_TRY(hipMemcpy(b->d_counter, zeros, sizeof(zeros), hipMemcpyHostToDevice), "hipMemcpy");
+    // geometry workspace of the persistent items
+    if (amap_doubles > 0 &&
+        hipMalloc(reinterpret_cast<void**>(&b->d_amap), static_cast<size_t>(amap_doubles) * sizeof(double)) != hipSuccess)
+        return fail(FFC_E_NOMEM, "hipMalloc failed for the batch geometry workspace");
+    int64_t amap_off = 0;
+    for (auto& kv : pgroups) {
+        BatchLaunch L;
+        L.persistent = true;
+        L.items = kv.second;
+        L.dim = L.items[0].dim;
+        L.kind = L.items[0].kind;
+        L.kmax = L.items[0].kmax;
+        const ffc::LdsPlan p16 = ffc::plan_lds(L.dim, L.kind, 16, L.items[0].n_I, L.items[0].n_alpha, 0, false,
+                                               ffc::kLdsBudget);
+        L.lds = p16.total;
+        for (auto& it : L.items) {
+            it.unit_begin = L.units;
+            L.units += (it.cells + 15) / 16;
+            it.amap = b->d_amap + amap_off;
+            b->geometry.push_back({it.dim, it.cells, it.coords, b->d_amap + amap_off});
+            amap_off += it.cells * (1 + it.dim * it.dim);
+        }
+        const int per_cu = std::max(1, std::min(2, static_cast<int>((160 * 1024) / std::max<size_t>(L.lds, 1))));
+        L.grid = static_cast<int>(std::min<int64_t>(static_cast<int64_t>(prop.multiProcessorCount) * per_cu, L.units));
+        b->launches.push_back(std::move(L));
+    }
+    for (auto& kv : tgroups) {
+        BatchLaunch L;
+        L.waves = kv.first >> 8;
+        L.mt = (kv.first >> 4) & 15;
+        L.items = kv.second;
+        std::vector<int32_t> unit_item;
+        size_t g_cap = 0;
+        for (size_t i = 0; i < L.items.size(); ++i) {
+            ffc::BatchItem& it = L.items[i];
+            const int ct = 16 * it.mt;
+            const ffc::LdsPlan pl = ffc::plan_lds(it.dim, it.kind, ct, it.n_I, it.n_alpha, it.kpad, bf16,
+                                                  ffc::kLdsBudget);
+            if (it.staged) L.stage_cap = std::max(L.stage_cap, pl.stage_bytes);
+            L.head_cap = std::max(L.head_cap, ffc::batch_head_bytes(it.dim, it.kind, ct));
+            g_cap = std::max(g_cap, pl.g_bytes);
+            it.unit_begin = static_cast<int64_t>(unit_item.size());
+            unit_item.insert(unit_item.end(), static_cast<size_t>((it.cells + ct - 1) / ct), static_cast<int32_t>(i));
+        }
+        L.lds = L.stage_cap + L.head_cap + g_cap;
+        if (L.lds > ffc::kLdsBudget) return fail(FFC_E_UNSUPPORTED, "batch tile does not fit LDS");
+        L.units = static_cast<int64_t>(unit_item.size());
+        if (L.units > INT32_MAX) return fail(FFC_E_UNSUPPORTED, "too many tiles in one batch launch");
+        if ((rc = upload(unit_item, &L.d_unit_item))) return rc;
+        b->launches.push_back(std::move(L));
+    }
+    for (auto& L : b->launches) {
+        b->total_units += L.units;
+        if ((rc = upload(L.items, &L.d_items))) return rc;
+    }
     *out = b.release();
     return FFC_OK;
 }
 
 int ffc_batch_run(ffc_batch* b) {
     if (!b) return fail(FFC_E_INVALID, "batch is NULL");
-    if (b->total_units == 0) return FFC_OK;
-    hipError_t e = ffc::launch_batch(b->d_items, static_cast<int>(b->items.size()), b->total_units, b->d_counter,
-                                     b->grid, b->bf16, b->lds, b->stage_cap, b->stream);
-    if (e != hipSuccess) return hip_fail(e, "batch kernel launch");
+    for (const auto& g : b->geometry) {
+        hipError_t e = ffc::launch_geometry(g.dim, g.cells, g.coords, g.cells, g.amap, g.cells, b->stream);
+        if (e != hipSuccess) return hip_fail(e, "batch geometry launch");
+    }
+    for (const auto& L : b->launches) {
+        hipError_t e = L.persistent
+                           ? ffc::launch_batch_persistent(L.dim, L.kind, L.kmax, L.d_items,
+                                                          static_cast<int>(L.items.size()), L.units, L.grid, L.lds,
+                                                          b->stream)
+                           : ffc::launch_batch_tiles(L.d_items, L.d_unit_item, L.units, L.waves, L.mt, b->nseg,
+                                                     L.lds, L.stage_cap, L.head_cap, b->stream);
+        if (e != hipSuccess) return hip_fail(e, "batch kernel launch");
+    }
     return FFC_OK;
 }
 
-int ffc_batch_info(const ffc_batch* b, int64_t* total_cells, int64_t* work_units, int32_t* grid) {
+int ffc_batch_info(const ffc_batch* b, int64_t* total_cells, int64_t* work_units, int32_t* launches) {
     if (!b) return fail(FFC_E_INVALID, "batch is NULL");
     if (total_cells) *total_cells = b->total_cells;
     if (work_units) *work_units = b->total_units;
-    if (grid) *grid = b->grid;
+    if (launches) *launches = static_cast<int32_t>(b->geometry.size() + b->launches.size());
     return FFC_OK;
 }
 

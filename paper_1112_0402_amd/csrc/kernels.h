@@ -82,14 +82,21 @@ hipError_t launch_quadrature(int dim, int kind, const QuadArgs& a, hipStream_t s
 size_t contract_lds_bytes(int dim, int kind, int tile_cells, int n_I, int n_alpha, int kpad, bool bf16);
 int quad_cells_per_block(int dim, int kind, int ns, int npts);
 
-// Persistent mixed-batch kernel: one descriptor per item (a mesh with its form).
+// Mixed batches.  One descriptor per item (a mesh with its form); an item runs either in a
+// tile launch (one workgroup per cell tile of 16*mt cells, geometry computed in place) or in
+// the persistent launch of its form (FP64 forms with a persistent schedule; the 16-cell
+// tiles of all its items form one sequence; affine map from a geometry pass into `amap`).
 struct BatchItem {
     int64_t cells;
-    int64_t unit_begin;     // first work unit of this item (prefix sum)
+    int64_t unit_begin;     // first tile of this item in its launch's tile sequence
     const double* coords;   // SoA [(d+1)*d][cells]
-    const double* coeffs;   // SoA or nullptr
-    void* out;
+    const double* coeffs;   // SoA [n_coeff][cells] or nullptr
+    void* out;              // [cells][n_I]
+    const double* amap;     // persistent items: SoA [1 + d*d][cells]
     int32_t dim, kind, n_I, n_alpha, n_tiles, kpad, n_seg, n_coeff;
+    int32_t mt, staged;     // tile items: cell tile 16*mt, output rows staged in LDS
+    int32_t kmax, reserved; // persistent items: register steps per wave
+    size_t stage_bytes, head_bytes;  // persistent items: LDS plan
     const int32_t* koff;
     const uint32_t* apack;
     const int32_t* entry;
@@ -97,15 +104,19 @@ struct BatchItem {
     const uint16_t* bb;
     const uint8_t* nonzero;
     int32_t gpiece[6];
+    PersistArgs p;
 };
 
-// persistent batch: 16-cell work units claimed kBatchChunk at a time, kBatchWaves waves
-constexpr int kBatchCT = 16;
-constexpr int kBatchChunk = 4;
-constexpr int kBatchWaves = 16;
-constexpr int kBatchMaxCoeff = 12;
-hipError_t launch_batch(const BatchItem* items_dev, int n_items, int64_t total_units, int* counter_dev,
-                        int grid, bool bf16, size_t lds_bytes, size_t stage_cap, hipStream_t stream);
-size_t batch_lds_bytes(int max_alpha, int max_kpad, int max_stage_nI, bool bf16);
+// Tile launch over items of one tile size (16*mt cells): grid = total tiles, unit_item[u] =
+// item of tile u; nseg 0 = FP64, 3 / 6 = split BF16 with that many products; LDS =
+// stage_cap + head_cap + G.
+hipError_t launch_batch_tiles(const BatchItem* items, const int32_t* unit_item, int64_t units, int waves, int mt,
+                              int nseg, size_t lds, size_t stage_cap, size_t head_cap, hipStream_t stream);
+// Persistent launch over the items of one form (items in unit_begin order, `tiles` 16-cell
+// tiles in all): `grid` workgroups of 16 waves, workgroup w runs tiles w, w + grid, ...
+hipError_t launch_batch_persistent(int dim, int kind, int kmax, const BatchItem* items, int n_items, int64_t tiles,
+                                   int grid, size_t lds, hipStream_t stream);
+// head part of a tile launch's LDS: affine map and coefficients of one tile
+size_t batch_head_bytes(int dim, int kind, int tile_cells);
 
 }  // namespace ffc

@@ -44,6 +44,15 @@ static hipError_t launch_lds(Kernel kernel, unsigned grid, unsigned block, size_
     return hipGetLastError();
 }
 
+// Pointers read from a descriptor in memory are generic to the compiler, which then emits
+// flat loads and stores (slower, and counted by lgkmcnt as well, so LDS waits would also
+// wait for them).  Every buffer of this library lives in global memory: say so.
+template <typename T>
+__device__ __forceinline__ T* as_global(T* p) {
+    // through an integer: a cast pair generic -> global -> generic would fold away
+    return (T*)((__attribute__((address_space(1))) T*)reinterpret_cast<uintptr_t>(p));
+}
+
 template <int KIND, int D>
 struct FormTraits {
     static constexpr int n_alpha = KIND == K_MASS ? 1
@@ -545,8 +554,53 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_s_barrier();
 }
 
-template <int D, int KIND, int KMAX, int MAXT, int IOS>
-__global__ __launch_bounds__(MAXT) void contract_f64_persistent(ContractArgs A, PersistArgs P) {
+// A cell tile of the persistent loop as the fetch and store steps see it: the mesh it
+// belongs to (affine map, coefficients, output, cell count) and its index in that mesh.
+struct MeshTile {
+    const double* amap;
+    int64_t astride;
+    const double* coeffs;
+    int64_t cstride;
+    double* out;
+    int64_t cells;
+    int64_t ct;
+};
+
+// Tile source of a single-mesh launch: tile g of the sequence is tile g of the mesh.
+struct OneMesh {
+    const ContractArgs& A;
+    __device__ __forceinline__ MeshTile at(int64_t g) const {
+        return MeshTile{A.amap, A.astride, A.coeffs, A.cstride, static_cast<double*>(A.out), A.cells, g};
+    }
+};
+
+// Tile source of a batch launch: the tiles of items[0], then of items[1], ... (items in
+// unit_begin order); queried with increasing g, so a cursor advances over the items.
+struct ItemCursor {
+    const BatchItem* items;
+    int n, idx;
+    int64_t begin, end;
+    MeshTile base;
+    __device__ __forceinline__ MeshTile at(int64_t g) {
+        while (g >= end && idx + 1 < n) {
+            ++idx;
+            const BatchItem& it = items[idx];
+            begin = it.unit_begin;
+            end = begin + (it.cells + 15) / 16;
+            base = MeshTile{as_global(it.amap), it.cells, as_global(it.coeffs), it.cells,
+                            as_global(static_cast<double*>(it.out)), it.cells, 0};
+        }
+        MeshTile t = base;
+        t.ct = g - begin;
+        return t;
+    }
+};
+
+// The tiles g, g + step, ... below g_end of a tile source (one mesh, or the items of a
+// batch that share one form).
+template <int D, int KIND, int KMAX, int IOS, class Src>
+__device__ __forceinline__ void persistent_tiles(const ContractArgs& A, const PersistArgs& P, Src& src, int64_t ct,
+                                                 const int64_t ct_end, const int64_t step, unsigned char* smem_raw) {
     using FT = FormTraits<KIND, D>;
     constexpr int CT = 16;
     constexpr int NA = FT::n_alpha;
@@ -563,7 +617,6 @@ __global__ __launch_bounds__(MAXT) void contract_f64_persistent(ContractArgs A, 
     // move the staged output to global memory and nothing else.  A wave that has stores in
     // flight must wait for them before reusing their source registers, so keeping stores
     // out of the compute waves lets the write-out of one tile overlap the next contraction.
-    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     double* st = reinterpret_cast<double*>(smem_raw);
     double* am = reinterpret_cast<double*>(smem_raw + A.stage_bytes);  // [ROWS][CT]: map rows, then coefficients
     double* cf = am + (1 + D * D) * CT;
@@ -601,23 +654,34 @@ __global__ __launch_bounds__(MAXT) void contract_f64_persistent(ContractArgs A, 
     }
     endmask = __builtin_amdgcn_readfirstlane(endmask);
 
-    const int64_t ntiles = (A.cells + CT - 1) / CT;
     // thread r*CT + c (r < ROWS) fetches row r of cell c: affine map, then coefficients
-    auto fetch = [&](int64_t ct) -> double {
+    auto fetch = [&](const MeshTile& t) -> double {
         const int r = tid / CT, c = tid - (tid / CT) * CT;
-        const int64_t cell = ct * CT + c;
-        if (cell >= A.cells) return r == 0 ? 1.0 : 0.0;
-        return r < 1 + D * D ? A.amap[r * A.astride + cell] : A.coeffs[(r - 1 - D * D) * A.cstride + cell];
+        const int64_t cell = t.ct * CT + c;
+        if (cell >= t.cells) return r == 0 ? 1.0 : 0.0;
+        return r < 1 + D * D ? t.amap[r * t.astride + cell] : t.coeffs[(r - 1 - D * D) * t.cstride + cell];
+    };
+    // output run of a tile: start and length in doubles
+    auto out_run = [&](const MeshTile& t, double*& o, int64_t& n) {
+        const int64_t c0 = t.ct * CT;
+        o = t.out + c0 * nI;
+        n = (t.cells - c0 < CT ? t.cells - c0 : CT) * nI;
     };
     double pre = 0.0;
-    int64_t ct = blockIdx.x;
-    if (tid < ROWS * CT && ct < ntiles) pre = fetch(ct);
+    double* cur_out = nullptr;
+    int64_t cur_n = 0;
+    if (ct < ct_end) {
+        const MeshTile t = src.at(ct);
+        out_run(t, cur_out, cur_n);
+        if (tid < ROWS * CT) pre = fetch(t);
+    }
     const double* grow = Gs + lr * GS;
-    int64_t io_c0 = -1, io_n = 0;
+    double* io_out = nullptr;
+    int64_t io_n = 0;
     // I/O lanes: store the tile held in R (slot j -> 16-byte pair io_lane + j * 64 * kIoWaves;
     // an odd last value rides in the last slot of lane 0, which the host keeps unused)
     auto io_store = [&]() {
-        double* o = static_cast<double*>(A.out) + io_c0 * nI;
+        double* o = io_out;
         const int64_t nv = io_n / 2;
         const int jn = nv > io_lane ? static_cast<int>((nv - io_lane + 64 * kIoWaves - 1) / (64 * kIoWaves)) : 0;
         d2v* ov = reinterpret_cast<d2v*>(o) + io_lane;
@@ -629,11 +693,15 @@ __global__ __launch_bounds__(MAXT) void contract_f64_persistent(ContractArgs A, 
         if ((io_n & 1) && io_lane == 0)
             o[io_n - 1] = __builtin_bit_cast(double, u32x2{R[4 * (IOS - 1)], R[4 * (IOS - 1) + 1]});
     };
-    for (; ct < ntiles; ct += gridDim.x) {
-        const int64_t c0 = ct * CT;
-        if (tid < ROWS * CT) {
-            am[tid] = pre;
-            if (ct + gridDim.x < ntiles) pre = fetch(ct + gridDim.x);
+    for (; ct < ct_end; ct += step) {
+        const bool more = ct + step < ct_end;
+        double* nxt_out = nullptr;
+        int64_t nxt_n = 0;
+        if (tid < ROWS * CT) am[tid] = pre;
+        if (more) {
+            const MeshTile t = src.at(ct + step);
+            out_run(t, nxt_out, nxt_n);
+            if (tid < ROWS * CT) pre = fetch(t);
         }
         lds_barrier();
         for (int i = tid; i < CT * NA; i += blockDim.x) {
@@ -646,7 +714,7 @@ __global__ __launch_bounds__(MAXT) void contract_f64_persistent(ContractArgs A, 
         }
         lds_barrier();
         if (tid >= io_begin) {
-            if (io_c0 >= 0) io_store();  // the previous tile, during this tile's MFMA phase
+            if (io_n > 0) io_store();  // the previous tile, during this tile's MFMA phase
         } else {
             // compiler-only barrier (emits no instruction) on the row stride: keeps the
             // staging addresses of the steps from being precomputed outside the cell-tile
@@ -676,9 +744,8 @@ __global__ __launch_bounds__(MAXT) void contract_f64_persistent(ContractArgs A, 
         }
         lds_barrier();
         if (tid >= io_begin) {  // take this tile's rows into registers; st is free after the next barrier
-            const int64_t nc = A.cells - c0 < CT ? A.cells - c0 : CT;
-            io_c0 = c0;
-            io_n = nc * nI;
+            io_out = cur_out;
+            io_n = cur_n;
             const int64_t nv = io_n / 2;
             const int jn = nv > io_lane ? static_cast<int>((nv - io_lane + 64 * kIoWaves - 1) / (64 * kIoWaves)) : 0;
             const d2v* sv = reinterpret_cast<const d2v*>(st) + io_lane;
@@ -699,8 +766,17 @@ __global__ __launch_bounds__(MAXT) void contract_f64_persistent(ContractArgs A, 
                 R[4 * (IOS - 1) + 1] = w[1];
             }
         }
+        cur_out = nxt_out;
+        cur_n = nxt_n;
     }
-    if (tid >= io_begin && io_c0 >= 0) io_store();  // the last tile
+    if (tid >= io_begin && io_n > 0) io_store();  // the last tile
+}
+
+template <int D, int KIND, int KMAX, int MAXT, int IOS>
+__global__ __launch_bounds__(MAXT) void contract_f64_persistent(ContractArgs A, PersistArgs P) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    OneMesh src{A};
+    persistent_tiles<D, KIND, KMAX, IOS>(A, P, src, blockIdx.x, (A.cells + 15) / 16, gridDim.x, smem_raw);
 }
 
 template <int D, int KIND>
@@ -743,104 +819,136 @@ hipError_t launch_contract_persistent(int dim, int kind, int kmax, int waves, in
                     : launch_persistent_d<3>(kind, kmax, waves, grid, pl.total, a, p, stream);
 }
 
-// ------------------------------------------------------- persistent mixed batch ---
-// Work unit = (item, 16-cell tile).  Each workgroup claims kBatchChunk consecutive units
-// per atomic from one queue counter until the queue is empty; the last workgroup to leave
-// resets the counters, so the launch can be replayed (for example from a captured graph)
-// with no separate reset.  Geometry is computed in place, one lane per cell; outputs are
-// staged in LDS for items whose 16 rows fit the launch's LDS.
+// --------------------------------------------------------------- mixed batches ---
+// Tile launch: workgroup u runs tile u of the launch, cell tile 16*MT of item unit_item[u]
+// (one launch per tile size, so each kernel's register count is that of its own tile),
+// geometry computed in place (one lane per cell), then the FP64 or split-BF16 contraction of
+// the single-mesh kernel.  LDS: staged rows [stage_cap], affine map and coefficients
+// [head_cap], G tile.
 
-size_t batch_lds_bytes(int max_alpha, int max_kpad, int max_stage_nI, bool bf16) {
-    const size_t head = align16(static_cast<size_t>(1 + 9 + kBatchMaxCoeff) * kBatchCT * sizeof(double));
-    const size_t g = align16(bf16 ? static_cast<size_t>(kBatchCT) * (max_kpad + 8) * sizeof(uint16_t)
-                                  : static_cast<size_t>(kBatchCT) * (max_alpha | 1) * sizeof(double));
-    const size_t stage = align16(static_cast<size_t>(kBatchCT) * max_stage_nI * (bf16 ? sizeof(float) : sizeof(double)));
-    return stage + head + g;
+size_t batch_head_bytes(int dim, int kind, int tile_cells) {
+    return align16(static_cast<size_t>(1 + dim * dim + n_coeff_of(dim, kind)) * tile_cells * sizeof(double));
 }
 
-template <int D, int KIND, bool BF16>
-__device__ __forceinline__ void batch_unit(const BatchItem& it, int64_t c0, unsigned char* smem, size_t stage_cap) {
+template <int D, int KIND, int MT, int NSEG>
+__device__ __forceinline__ void batch_tile(const BatchItem& it, int64_t c0, unsigned char* smem, size_t stage_cap,
+                                           size_t head_cap) {
     constexpr int NC = FormTraits<KIND, D>::n_coeff;
-    constexpr size_t head = (1 + 9 + kBatchMaxCoeff) * kBatchCT * sizeof(double);
+    constexpr int CT = 16 * MT;
     double* am = reinterpret_cast<double*>(smem + stage_cap);
-    double* cf = am + (1 + D * D) * kBatchCT;
-    unsigned char* g = smem + stage_cap + align16(head);
-    const size_t ob = BF16 ? sizeof(float) : sizeof(double);
-    const bool staged = static_cast<size_t>(kBatchCT) * it.n_I * ob <= stage_cap &&
-                        (reinterpret_cast<uintptr_t>(it.out) & 15u) == 0;
-    stage_tile_from_coords<D, NC>(it.coords, it.coeffs, it.cells, c0, kBatchCT, am, cf);
+    double* cf = am + (1 + D * D) * CT;
+    unsigned char* g = smem + stage_cap + head_cap;
+    stage_tile_from_coords<D, NC>(as_global(it.coords), as_global(it.coeffs), it.cells, c0, CT, am, cf);
     __syncthreads();
-    if constexpr (BF16) {
-        float* st = staged ? reinterpret_cast<float*>(smem) : nullptr;
-        if (it.n_seg == 3)
-            contract_tile_bf16<D, KIND, 1, 3>(am, cf, reinterpret_cast<unsigned short*>(g), st, c0, it.cells, it.n_I,
-                                              it.n_tiles, it.kpad, it.gpiece, it.bb, it.nonzero, static_cast<float*>(it.out));
-        else
-            contract_tile_bf16<D, KIND, 1, 6>(am, cf, reinterpret_cast<unsigned short*>(g), st, c0, it.cells, it.n_I,
-                                              it.n_tiles, it.kpad, it.gpiece, it.bb, it.nonzero, static_cast<float*>(it.out));
+    if constexpr (NSEG > 0) {
+        contract_tile_bf16<D, KIND, MT, NSEG>(am, cf, reinterpret_cast<unsigned short*>(g),
+                                              it.staged ? reinterpret_cast<float*>(smem) : nullptr, c0, it.cells,
+                                              it.n_I, it.n_tiles, it.kpad, it.gpiece, as_global(it.bb),
+                                              as_global(it.nonzero), as_global(static_cast<float*>(it.out)));
     } else {
-        double* st = staged ? reinterpret_cast<double*>(smem) : nullptr;
-        contract_tile_f64<D, KIND, 1>(am, cf, reinterpret_cast<double*>(g), st, c0, it.cells, it.n_I, it.n_tiles,
-                                      it.koff, it.apack, it.entry, it.b, static_cast<double*>(it.out));
+        contract_tile_f64<D, KIND, MT>(am, cf, reinterpret_cast<double*>(g),
+                                       it.staged ? reinterpret_cast<double*>(smem) : nullptr, c0, it.cells, it.n_I,
+                                       it.n_tiles, as_global(it.koff), as_global(it.apack), as_global(it.entry),
+                                       as_global(it.b), as_global(static_cast<double*>(it.out)));
     }
 }
 
-template <bool BF16>
-__global__ __launch_bounds__(1024) void batch_kernel(const BatchItem* __restrict__ items, int n_items,
-                                                     int64_t total_units, int* counters, size_t stage_cap) {
+template <int NSEG, int MT>
+__global__ __launch_bounds__(1024) void batch_tiles_kernel(const BatchItem* __restrict__ items,
+                                                           const int32_t* __restrict__ unit_item, size_t stage_cap,
+                                                           size_t head_cap) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
-    __shared__ int s_unit;
-    for (;;) {
-        if (threadIdx.x == 0) s_unit = atomicAdd(&counters[0], kBatchChunk);
-        __syncthreads();
-        const int64_t u0 = s_unit;
-        __syncthreads();  // s_unit is rewritten on the next claim
-        if (u0 >= total_units) break;
-        const int64_t u1 = u0 + kBatchChunk < total_units ? u0 + kBatchChunk : total_units;
-        for (int64_t u = u0; u < u1; ++u) {
-            int lo = 0, hi = n_items - 1;
-            while (lo < hi) {  // last item with unit_begin <= u (same answer on every lane)
-                const int mid = (lo + hi + 1) >> 1;
-                if (items[mid].unit_begin <= u)
-                    lo = mid;
-                else
-                    hi = mid - 1;
-            }
-            const BatchItem& it = items[lo];
-            const int64_t c0 = (u - it.unit_begin) * kBatchCT;
-            switch (it.dim * 8 + it.kind) {
-            case 16 + K_MASS: batch_unit<2, K_MASS, BF16>(it, c0, smem_raw, stage_cap); break;
-            case 16 + K_LAPLACE: batch_unit<2, K_LAPLACE, BF16>(it, c0, smem_raw, stage_cap); break;
-            case 16 + K_WLAPLACE: batch_unit<2, K_WLAPLACE, BF16>(it, c0, smem_raw, stage_cap); break;
-            case 16 + K_ELASTICITY: batch_unit<2, K_ELASTICITY, BF16>(it, c0, smem_raw, stage_cap); break;
-            case 16 + K_NS: batch_unit<2, K_NS, BF16>(it, c0, smem_raw, stage_cap); break;
-            case 24 + K_MASS: batch_unit<3, K_MASS, BF16>(it, c0, smem_raw, stage_cap); break;
-            case 24 + K_LAPLACE: batch_unit<3, K_LAPLACE, BF16>(it, c0, smem_raw, stage_cap); break;
-            case 24 + K_WLAPLACE: batch_unit<3, K_WLAPLACE, BF16>(it, c0, smem_raw, stage_cap); break;
-            case 24 + K_ELASTICITY: batch_unit<3, K_ELASTICITY, BF16>(it, c0, smem_raw, stage_cap); break;
-            default: batch_unit<3, K_NS, BF16>(it, c0, smem_raw, stage_cap); break;
-            }
-            __syncthreads();  // LDS is reused by the next unit
-        }
-    }
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const int done = atomicAdd(&counters[1], 1);
-        if (done == static_cast<int>(gridDim.x) - 1) {  // every other workgroup has left the loop
-            atomicExch(&counters[0], 0);
-            atomicExch(&counters[1], 0);
-        }
+    const int64_t u = blockIdx.x;
+    const BatchItem& it = items[__builtin_amdgcn_readfirstlane(unit_item[u])];
+    const int64_t c0 = (u - it.unit_begin) * 16 * MT;
+    switch (it.dim * 8 + it.kind) {
+    case 16 + K_MASS: batch_tile<2, K_MASS, MT, NSEG>(it, c0, smem_raw, stage_cap, head_cap); break;
+    case 16 + K_LAPLACE: batch_tile<2, K_LAPLACE, MT, NSEG>(it, c0, smem_raw, stage_cap, head_cap); break;
+    case 16 + K_WLAPLACE: batch_tile<2, K_WLAPLACE, MT, NSEG>(it, c0, smem_raw, stage_cap, head_cap); break;
+    case 16 + K_ELASTICITY: batch_tile<2, K_ELASTICITY, MT, NSEG>(it, c0, smem_raw, stage_cap, head_cap); break;
+    case 16 + K_NS: batch_tile<2, K_NS, MT, NSEG>(it, c0, smem_raw, stage_cap, head_cap); break;
+    case 24 + K_MASS: batch_tile<3, K_MASS, MT, NSEG>(it, c0, smem_raw, stage_cap, head_cap); break;
+    case 24 + K_LAPLACE: batch_tile<3, K_LAPLACE, MT, NSEG>(it, c0, smem_raw, stage_cap, head_cap); break;
+    case 24 + K_WLAPLACE: batch_tile<3, K_WLAPLACE, MT, NSEG>(it, c0, smem_raw, stage_cap, head_cap); break;
+    case 24 + K_ELASTICITY: batch_tile<3, K_ELASTICITY, MT, NSEG>(it, c0, smem_raw, stage_cap, head_cap); break;
+    default: batch_tile<3, K_NS, MT, NSEG>(it, c0, smem_raw, stage_cap, head_cap); break;
     }
 }
 
-hipError_t launch_batch(const BatchItem* items_dev, int n_items, int64_t total_units, int* counter_dev, int grid,
-                        bool bf16, size_t lds, size_t stage_cap, hipStream_t stream) {
-    if (total_units <= 0) return hipSuccess;
-    if (bf16)
-        return launch_lds(batch_kernel<true>, grid, 64 * kBatchWaves, lds, stream, items_dev, n_items, total_units,
-                          counter_dev, stage_cap);
-    return launch_lds(batch_kernel<false>, grid, 64 * kBatchWaves, lds, stream, items_dev, n_items, total_units,
-                      counter_dev, stage_cap);
+template <int NSEG>
+static hipError_t launch_batch_tiles_n(int mt, unsigned grid, unsigned block, size_t lds, hipStream_t s,
+                                       const BatchItem* items, const int32_t* unit_item, size_t stage_cap,
+                                       size_t head_cap) {
+    switch (mt) {
+    case 1: return launch_lds(batch_tiles_kernel<NSEG, 1>, grid, block, lds, s, items, unit_item, stage_cap, head_cap);
+    case 2: return launch_lds(batch_tiles_kernel<NSEG, 2>, grid, block, lds, s, items, unit_item, stage_cap, head_cap);
+    default:
+        return launch_lds(batch_tiles_kernel<NSEG, 4>, grid, block, lds, s, items, unit_item, stage_cap, head_cap);
+    }
+}
+
+hipError_t launch_batch_tiles(const BatchItem* items, const int32_t* unit_item, int64_t units, int waves, int mt,
+                              int nseg, size_t lds, size_t stage_cap, size_t head_cap, hipStream_t stream) {
+    if (units <= 0) return hipSuccess;
+    const unsigned grid = static_cast<unsigned>(units);
+    const unsigned block = 64u * waves;
+    if (nseg == 3) return launch_batch_tiles_n<3>(mt, grid, block, lds, stream, items, unit_item, stage_cap, head_cap);
+    if (nseg == 6) return launch_batch_tiles_n<6>(mt, grid, block, lds, stream, items, unit_item, stage_cap, head_cap);
+    return launch_batch_tiles_n<0>(mt, grid, block, lds, stream, items, unit_item, stage_cap, head_cap);
+}
+
+// Persistent launch over the items of one form: the 16-cell tiles of all items form one
+// sequence, and workgroup w runs tiles w, w + grid, ... of it with the persistent tile loop
+// above (A^0 fragments loaded once, the pipeline never drained between items; every tile
+// costs the same, so the static split is balanced to one tile).
+
+template <int D, int KIND, int KMAX>
+__global__ __launch_bounds__(1024) void batch_persistent_kernel(const BatchItem* __restrict__ items, int n_items,
+                                                                int64_t total_tiles) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    // every item of the launch has the same form: tables and LDS plan from the first
+    const BatchItem& f = items[0];
+    ContractArgs A{};
+    A.n_I = f.n_I;
+    A.b = as_global(f.b);
+    A.apack = as_global(f.apack);
+    A.entry = as_global(f.entry);
+    A.stage_bytes = f.stage_bytes;
+    A.head_bytes = f.head_bytes;
+    const PersistArgs P{as_global(f.p.woff), as_global(f.p.step_kstep), as_global(f.p.step_end),
+                        as_global(f.p.zero_entries), f.p.n_zero};
+    ItemCursor src{items, n_items, -1, 0, 0, MeshTile{}};
+    persistent_tiles<D, KIND, KMAX, kIoSlots>(A, P, src, blockIdx.x, total_tiles, gridDim.x, smem_raw);
+}
+
+template <int D, int KIND>
+static hipError_t launch_batch_persistent_k(int kmax, const BatchItem* items, int n_items, int64_t tiles, int grid,
+                                            size_t lds, hipStream_t s) {
+    if (kmax <= 8)
+        return launch_lds(batch_persistent_kernel<D, KIND, 8>, grid, 1024u, lds, s, items, n_items, tiles);
+    if (kmax <= 16)
+        return launch_lds(batch_persistent_kernel<D, KIND, 16>, grid, 1024u, lds, s, items, n_items, tiles);
+    return launch_lds(batch_persistent_kernel<D, KIND, 24>, grid, 1024u, lds, s, items, n_items, tiles);
+}
+
+template <int D>
+static hipError_t launch_batch_persistent_d(int kind, int kmax, const BatchItem* items, int n_items, int64_t tiles,
+                                            int grid, size_t lds, hipStream_t s) {
+    switch (kind) {
+    case K_MASS: return launch_batch_persistent_k<D, K_MASS>(kmax, items, n_items, tiles, grid, lds, s);
+    case K_LAPLACE: return launch_batch_persistent_k<D, K_LAPLACE>(kmax, items, n_items, tiles, grid, lds, s);
+    case K_WLAPLACE: return launch_batch_persistent_k<D, K_WLAPLACE>(kmax, items, n_items, tiles, grid, lds, s);
+    case K_ELASTICITY: return launch_batch_persistent_k<D, K_ELASTICITY>(kmax, items, n_items, tiles, grid, lds, s);
+    default: return launch_batch_persistent_k<D, K_NS>(kmax, items, n_items, tiles, grid, lds, s);
+    }
+}
+
+hipError_t launch_batch_persistent(int dim, int kind, int kmax, const BatchItem* items, int n_items, int64_t tiles,
+                                   int grid, size_t lds, hipStream_t stream) {
+    if (tiles <= 0 || n_items <= 0) return hipSuccess;
+    if (grid > tiles) grid = static_cast<int>(tiles);
+    return dim == 2 ? launch_batch_persistent_d<2>(kind, kmax, items, n_items, tiles, grid, lds, stream)
+                    : launch_batch_persistent_d<3>(kind, kmax, items, n_items, tiles, grid, lds, stream);
 }
 
 // ------------------------------------------------------------------ quadrature ---

@@ -121,7 +121,9 @@ def compute_geometry(coords: torch.Tensor, dim: int, out: torch.Tensor | None = 
 
 
 class Batch:
-    """Many (form, mesh) items evaluated by one persistent launch."""
+    """Many (form, mesh) items evaluated by a short fixed sequence of launches: one
+    persistent launch for the large FP64 element tensors (after their geometry passes)
+    and one tile launch per group of the other items."""
 
     def __init__(self, forms, coords, coeffs, outs, stream=None):
         n = len(forms)
@@ -145,7 +147,7 @@ class Batch:
         self._h = h
         tc, wu, gr = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
         capi.check(capi.lib().ffc_batch_info(h, ctypes.byref(tc), ctypes.byref(wu), ctypes.byref(gr)))
-        self.total_cells, self.work_units, self.grid = tc.value, wu.value, gr.value
+        self.total_cells, self.work_units, self.launches = tc.value, wu.value, gr.value
 
     def run(self):
         capi.check(capi.lib().ffc_batch_run(self._h))

@@ -2,6 +2,8 @@
 element, on seeded meshes.  FP64 tensor and quadrature kernels: per-cell relative
 Frobenius error <= 1e-12.  Split-BF16: the measured error is printed per form; the
 6-product split must reach <= 1e-6."""
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -220,7 +222,7 @@ def test_persistent_batch_matches_oracle_and_single_calls(precision):
     C = [to_dev(w.coeffs) for w in wls]
     outs = [f.empty_out(w.cells).zero_() for f, w in zip(fl, wls)]
     b = Batch(fl, X, C, outs)
-    say(f"[batch] {precision}: {len(wls)} meshes, {b.total_cells} cells, {b.work_units} units, grid {b.grid}")
+    say(f"[batch] {precision}: {len(wls)} meshes, {b.total_cells} cells, {b.work_units} units, {b.launches} launches")
     b.run()
     torch.cuda.synchronize()
     first = [o.clone() for o in outs]
@@ -233,11 +235,58 @@ def test_persistent_batch_matches_oracle_and_single_calls(precision):
         assert torch.equal(o, o1)
         single = f.tabulate(x, c)
         torch.cuda.synchronize()
+        # same tiles, same geometry arithmetic and same MFMA order as the single launch
+        assert torch.equal(o, single), w.name
         ref = oracle.tabulate(w.kind, w.dim, w.degree, w.coords, w.coeffs)
         e_b = rel_fro(o.cpu().numpy(), ref)[0]
         e_s = rel_fro(single.cpu().numpy(), ref)[0]
         assert e_b <= tol, (w.name, e_b)
         assert e_s <= tol, (w.name, e_s)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "bf16x6"])
+def test_batch_launch_classes(precision):
+    """Items of every launch class in one batch: two persistent (dim, kind, depth) groups
+    sharing the queue counters, several claims per item, tile items staged and direct,
+    16- and 64-cell tiles, an empty item, a one-cell item, ragged tails.  The batch equals
+    the single-mesh launches bit for bit, and the oracle on sampled cells."""
+    require_gpu()
+    spec = [("ns", 3, 2, 40000), ("elasticity", 3, 2, 9001), ("laplace", 3, 4, 3001), ("mass", 2, 1, 70001),
+            ("wlaplace", 3, 3, 12345), ("laplace", 2, 3, 0), ("ns", 2, 2, 1), ("ns", 3, 2, 17)]
+    wls = []
+    for k, (kind, dim, q, cells) in enumerate(spec):
+        n = max(1, math.ceil(math.sqrt(max(cells, 1) / 2.0)) if dim == 2 else math.ceil((max(cells, 1) / 6.0) ** (1 / 3)))
+        wl = meshgen.make_workload(kind, dim, q, n, 900 + k, max_cells=max(cells, 1))
+        if cells == 0:
+            wl.coords = wl.coords[:, :0].copy()
+            wl.coeffs = None if wl.coeffs is None else wl.coeffs[:, :0].copy()
+        wls.append(wl)
+    forms = {}
+    fl = []
+    for w in wls:
+        key = (w.kind, w.dim, w.degree)
+        if key not in forms:
+            forms[key] = Form(w.kind, w.dim, w.degree, precision=precision)
+        fl.append(forms[key])
+    X = [to_dev(w.coords) for w in wls]
+    C = [to_dev(w.coeffs) for w in wls]
+    outs = [f.empty_out(w.cells).fill_(float("nan")) for f, w in zip(fl, wls)]
+    b = Batch(fl, X, C, outs)
+    say(f"[batch classes] {precision}: {b.total_cells} cells, {b.work_units} units, {b.launches} launches")
+    b.run()
+    torch.cuda.synchronize()
+    tol = FP64_TOL if precision == "fp64" else SPLIT6_TOL
+    for w, f, x, c, o in zip(wls, fl, X, C, outs):
+        if w.cells == 0:
+            continue
+        single = f.tabulate(x, c)
+        torch.cuda.synchronize()
+        assert torch.equal(o, single), w.name
+        idx = np.arange(w.cells) if w.cells <= 80 else _sample(w.cells, 64, 3)
+        ref = oracle.tabulate(w.kind, w.dim, w.degree, np.ascontiguousarray(w.coords[:, idx]),
+                              None if w.coeffs is None else np.ascontiguousarray(w.coeffs[:, idx]))
+        e = rel_fro(o.cpu().numpy()[idx], ref)[0]
+        assert e <= tol, (w.kind, w.dim, w.degree, w.cells, e)
 
 
 def test_batch_graph_replay():
