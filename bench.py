@@ -12,8 +12,13 @@ cores on a bounded sample of the same mesh.
 Other workloads (same JSON line layout):
   poisson2d   2D Poisson, P1 triangles, 8192 cells (launch-latency bound), FP64
   wlaplace    3D weighted Laplacian, P3 tets, w in P1, 1,500,282 cells, split BF16 (x3 / x6)
-  batch       64 meshes of 1e3..5e5 cells, 16 form variants, one persistent launch replayed
-              from a captured graph (FP64 or split BF16)
+  batch       64 meshes of 1e3..5e5 cells, 16 form variants, the batch's fixed launch
+              sequence replayed from a captured graph (FP64 or split BF16)
+
+Forms that do not use the persistent kernel compute the affine map inside the contraction
+(one launch per step) unless --geometry pass is given.  The timed step is the hot path
+captured once in a graph and replayed; per-kernel durations come from eager steps with HIP
+events on the launch stream.
 
 Prints one JSON line.  Options: --gpus (1 only), --steps, --warmup.
 """
@@ -123,44 +128,77 @@ def bench_single(args, torch, np):
     cells, d = wl.cells, wl.dim
     X = torch.from_numpy(wl.coords).cuda()
     C = None if wl.coeffs is None else torch.from_numpy(wl.coeffs).cuda()
+    stream = torch.cuda.Stream()  # the form's launches and every timing event live on this stream
     form = Form(wl.kind, d, wl.degree, precision=precision, tile_cells=args.tile_cells, waves=args.waves,
-                tile_window=args.tile_window, persistent=args.persistent)
+                tile_window=args.tile_window, persistent=args.persistent, geometry=args.geometry, stream=stream)
     info = form.info
-    amap = torch.empty((1 + d * d, cells), dtype=torch.float64, device="cuda")
+    fused = bool(info["fused_geometry"])
+    amap = None if fused else torch.empty((1 + d * d, cells), dtype=torch.float64, device="cuda")
     out = form.empty_out(cells)
-    stream = torch.cuda.current_stream()
     bf16 = precision != "fp64"
 
+    def geometry():
+        compute_geometry(X, d, out=amap, stream=stream)
+
+    def contraction():
+        if fused:
+            form.tabulate(X, C, out=out)  # one launch: affine map computed per cell tile
+        else:
+            form.tabulate_affine(amap, C, out=out)
+
+    def step():
+        if not fused:
+            geometry()
+        contraction()
+
     for _ in range(args.warmup):
-        compute_geometry(X, d, out=amap)
-        form.tabulate_affine(amap, C, out=out)
+        step()
     torch.cuda.synchronize()
+    # eager steps, each kernel bracketed by events on the launch stream
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
     t0 = time.perf_counter()
     for k in range(args.steps):
         ev[k][0].record(stream)
-        compute_geometry(X, d, out=amap)
+        if not fused:
+            geometry()
         ev[k][1].record(stream)
-        form.tabulate_affine(amap, C, out=out)
+        contraction()
         ev[k][2].record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    geo_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+    eager_ms_step = (t1 - t0) * 1e3 / args.steps
+    geo_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev])) if not fused else 0.0
     con_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+    # the timed figure: steps captured in a graph and replayed back to back, so no host
+    # launch overhead is counted; a short step is captured several times per graph so that
+    # the graph launch itself is amortised
+    gsteps = 1 if eager_ms_step > 0.2 else min(100, max(1, int(round(0.5 / eager_ms_step))))
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        for _ in range(gsteps):
+            step()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):  # replay() launches on the current stream
+        for _ in range(max(1, args.warmup)):
+            g.replay()
+        torch.cuda.synchronize()
+        ms_step = timed(g.replay, args.steps, stream, torch) / gsteps
 
     n_I, n_alpha, nnz = info["n_entries"], info["n_alpha"], info["nnz_a0"]
     nco = info["n_coeffs"]
     ob = info["out_bytes"]
     ncoord = (d + 1) * d
-    con_bytes = cells * ((1 + d * d) * 8 + nco * 8 + n_I * ob)  # affine map + coefficients in, tensors out
     geo_bytes = cells * (ncoord * 8 + (1 + d * d) * 8)          # coords in, affine map out
     path_bytes = cells * (ncoord * 8 + nco * 8 + n_I * ob)      # coords + coefficients in, tensors out
+    # contraction launch: affine map + coefficients in, tensors out (fused: the whole path)
+    con_bytes = path_bytes if fused else cells * ((1 + d * d) * 8 + nco * 8 + n_I * ob)
     alg_flops = cells * 2 * nnz                                  # zeros of A^0 skipped
     mfma_flops = cells * info["mfma_k_per_tile"] * 32            # executed on the matrix cores
     con_gbs = con_bytes / (con_ms * 1e-3) / 1e9
-    kname = "contract_f64_persistent" if info["persistent_waves"] else (
-        "contract_bf16_kernel" if bf16 else "contract_f64_kernel")
+    if info["persistent_waves"]:
+        kname = "contract_bf16_persistent" if bf16 else "contract_f64_persistent"
+    else:
+        kname = "contract_bf16_kernel" if bf16 else "contract_f64_kernel"
     mpeak = BF16_MFMA_PEAK_TF if bf16 else FP64_MFMA_PEAK_TF
 
     result = {
@@ -187,8 +225,12 @@ def bench_single(args, torch, np):
             "tile_cells": info["tile_cells"],
             "waves": info["persistent_waves"] or info["waves"],
             "persistent": bool(info["persistent_waves"]),
+            "geometry": "fused into the contraction" if fused else "separate pass",
             "mfma_tiles": info["n_tiles"],
+            "timing": f"{gsteps} step(s) per captured graph, replayed; per-kernel times from eager steps "
+                      "with events on the launch stream",
         },
+        "eager_ms_per_step": eager_ms_step,
         "roofline": {
             "kernel": kname,
             "bound": "hbm",
@@ -215,7 +257,7 @@ def bench_single(args, torch, np):
             "achieved_gbs": geo_bytes / (geo_ms * 1e-3) / 1e9,
             "frac": geo_bytes / (geo_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "algorithmic_bytes_per_launch": geo_bytes,
-        },
+        } if not fused else {"fused": True},
         "path": {
             "algorithmic_bytes_per_step": path_bytes,
             "achieved_gbs": path_bytes / (ms_step * 1e-3) / 1e9,
@@ -224,7 +266,7 @@ def bench_single(args, torch, np):
     }
 
     if not args.no_quadrature:
-        qform = Form(wl.kind, d, wl.degree, kernel="quadrature")
+        qform = Form(wl.kind, d, wl.degree, kernel="quadrature", stream=stream)
         qout = qform.empty_out(cells)
         for _ in range(max(1, args.warmup)):
             qform.tabulate(X, C, out=qout)
@@ -327,6 +369,8 @@ def main() -> int:
     ap.add_argument("--tile-cells", type=int, default=0)
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--persistent", type=int, default=0, help="0 auto, 1 on, -1 off")
+    ap.add_argument("--geometry", default="default", choices=["default", "pass", "fused"],
+                    help="affine map in a separate pass or inside the contraction")
     ap.add_argument("--tile-window", type=int, default=0,
                     help="grouping of output entries into MFMA tiles (0 = library default)")
     ap.add_argument("--copy-calibration", action="store_true",

@@ -79,6 +79,7 @@ typedef enum { FFC_FP64 = 0, FFC_SPLIT_BF16_3 = 1, FFC_SPLIT_BF16_6 = 2 } ffc_pr
 
 /* Which kernel evaluates A^K.  QUADRATURE is FP64 only. */
 typedef enum { FFC_KERNEL_TENSOR = 1, FFC_KERNEL_QUADRATURE = 2 } ffc_kernel;
+typedef enum { FFC_GEOMETRY_PASS = 1, FFC_GEOMETRY_FUSED = 2 } ffc_geometry;
 
 typedef struct {
     int32_t kind;        /* ffc_kind */
@@ -93,10 +94,18 @@ typedef struct {
                             multiple of 16 = rows clustered greedily (smallest union of nonzero
                             A^0 columns) inside windows of that many consecutive entries;
                             -1 = clustered over all entries.  Ignored by the other kernels. */
-    int32_t persistent;  /* FP64 tensor kernel: 0 = auto (persistent workgroups with the A^0
-                            tiles in registers whenever they fit), 1 = the same, -1 = one
-                            workgroup per cell tile */
-    int32_t reserved;    /* must be 0 */
+    int32_t persistent;  /* tensor kernel: 0 = auto (persistent workgroups with the A^0 tiles
+                            in registers for element tensors of at least 576 entries in FP64,
+                            256 in the split modes, when they fit), 1 = persistent whenever
+                            it fits, -1 = one workgroup per cell tile */
+    int32_t geometry;    /* tensor kernel, ffc_tabulate_tensor: where the affine map is
+                            computed.  FFC_GEOMETRY_PASS = a geometry kernel writes it to a
+                            form-owned workspace that the contraction reads;
+                            FFC_GEOMETRY_FUSED = each cell tile computes it in LDS from the
+                            coordinates (one launch, no workspace).  The persistent kernel
+                            always uses the pass.  0 = default: fused for the per-tile
+                            kernels (measured faster on MI355X at every swept shape), the
+                            pass for the persistent kernel. */
     double lambda, mu;   /* Lame parameters (FFC_ELASTICITY only) */
     void* stream;        /* hipStream_t the form's work is enqueued on; NULL = default stream */
 } ffc_form_desc;
@@ -114,10 +123,12 @@ typedef struct {
                                  FP64 MFMA flops (split modes: * 512 BF16 flops) */
     int64_t n_tiles;          /* 16-entry output tiles */
     int64_t quad_points;      /* points of the quadrature kernel's rule */
-    int64_t persistent_waves; /* waves of the persistent FP64 contraction (0 = not used) */
+    int64_t persistent_waves; /* waves of the persistent contraction, FP64 or split BF16 (0 = not used) */
     int64_t persistent_kmax;  /* register-resident k steps per wave of that kernel */
     int64_t tile_cells;       /* cells per workgroup tile of the contraction */
     int64_t waves;            /* waves per workgroup of the (non-persistent) contraction */
+    int64_t fused_geometry;   /* 1: ffc_tabulate_tensor computes the affine map inside the
+                                 contraction (one launch); 0: geometry pass first */
 } ffc_form_info;
 
 /* Compile step only, host only, touches no device: the reference tensor A^0 of the form
@@ -207,9 +218,10 @@ int ffc_mlp_backward(int32_t n_in, int32_t n_hidden, int32_t n_out, int64_t batc
  * dy = 2 m (y - t) / sum m. */
 int ffc_mlp_mse(int64_t n, const float* y, const float* target, const float* mask, float* dy, float* loss,
                 void* stream);
-/* One Adam step (bias-corrected, step >= 1) on n parameters with gradient g and moments m, v. */
+/* One Adam step (bias-corrected, step >= 1) on n parameters with gradient g and moments m, v;
+ * weight_decay adds the L2 term weight_decay * params to the gradient first (0 = plain Adam). */
 int ffc_adam_step(int64_t n, float* params, const float* grad, float* m, float* v, float lr, float beta1,
-                  float beta2, float eps, int32_t step, void* stream);
+                  float beta2, float eps, float weight_decay, int32_t step, void* stream);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* ffc_last_error(void);

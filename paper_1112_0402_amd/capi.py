@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libffc_hip.so")
 KINDS = {"mass": 0, "laplace": 1, "wlaplace": 2, "elasticity": 3, "ns": 4}
 PRECISIONS = {"fp64": 0, "bf16x3": 1, "bf16x6": 2}
 KERNELS = {"tensor": 1, "quadrature": 2}
+GEOMETRY = {"default": 0, "pass": 1, "fused": 2}
 
 FFC_OK = 0
 FFC_E_INVALID = -1
@@ -36,7 +37,7 @@ class FormDesc(ctypes.Structure):
         ("waves", ctypes.c_int32),
         ("tile_window", ctypes.c_int32),
         ("persistent", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("geometry", ctypes.c_int32),
         ("lambda_", ctypes.c_double),
         ("mu", ctypes.c_double),
         ("stream", ctypes.c_void_p),
@@ -47,7 +48,7 @@ class FormInfo(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in (
         "n_dofs", "n_entries", "n_alpha", "nnz_a0", "n_coords", "n_coeffs", "out_bytes",
         "mfma_k_per_tile", "n_tiles", "quad_points", "persistent_waves", "persistent_kmax", "tile_cells",
-        "waves")]
+        "waves", "fused_geometry")]
 
 
 class FFCError(RuntimeError):
@@ -92,7 +93,7 @@ def lib():
     L.ffc_mlp_forward.argtypes = [i32, i32, i32, i64, vp, vp, vp, vp, vp]
     L.ffc_mlp_backward.argtypes = [i32, i32, i32, i64, vp, vp, vp, vp, vp, vp, vp]
     L.ffc_mlp_mse.argtypes = [i64, vp, vp, vp, vp, vp, vp]
-    L.ffc_adam_step.argtypes = [i64, vp, vp, vp, vp, fp, fp, fp, fp, i32, vp]
+    L.ffc_adam_step.argtypes = [i64, vp, vp, vp, vp, fp, fp, fp, fp, fp, i32, vp]
     for name in ("ffc_mlp_forward", "ffc_mlp_backward", "ffc_mlp_mse", "ffc_adam_step"):
         getattr(L, name).restype = ctypes.c_int
     for name in ("ffc_compile_reference_tensor", "ffc_form_create", "ffc_form_get_info", "ffc_tabulate_tensor",
@@ -109,7 +110,7 @@ def check(rc: int) -> None:
 
 
 def make_desc(kind, dim, degree, precision="fp64", kernel="tensor", tile_cells=0, waves=0,
-              lam=1.0, mu=1.0, stream=None, tile_window=0, persistent=0) -> FormDesc:
+              lam=1.0, mu=1.0, stream=None, tile_window=0, persistent=0, geometry=0) -> FormDesc:
     d = FormDesc()
     d.kind = KINDS[kind] if isinstance(kind, str) else int(kind)
     d.dim = dim
@@ -120,7 +121,7 @@ def make_desc(kind, dim, degree, precision="fp64", kernel="tensor", tile_cells=0
     d.waves = waves
     d.tile_window = tile_window
     d.persistent = persistent
-    d.reserved = 0
+    d.geometry = GEOMETRY[geometry] if isinstance(geometry, str) else int(geometry)
     d.lambda_ = lam
     d.mu = mu
     d.stream = stream

@@ -64,6 +64,9 @@ bool valid_tile(int t) { return t == 16 || t == 32 || t == 64; }
 // default; below it a 16-cell tile carries too little output to pay for the per-tile
 // pipeline (measured: persistent wins at 900 entries, loses at 400 and below).
 constexpr int kPersistentMinEntries = 576;
+// The same threshold for the persistent split-BF16 kernel (FP32 output: half the bytes
+// per entry).
+constexpr int kBf16PersistentMinEntries = 256;
 bool valid_waves(int w) { return w == 1 || w == 2 || w == 4 || w == 8 || w == 16; }
 
 int check_desc(const ffc_form_desc* d, ffc::FormSpec* spec) {
@@ -83,7 +86,7 @@ int check_desc(const ffc_form_desc* d, ffc::FormSpec* spec) {
         return fail(FFC_E_UNSUPPORTED, "the quadrature kernel is FP64 only");
     if (d->tile_cells != 0 && !valid_tile(d->tile_cells)) return fail(FFC_E_INVALID, "tile_cells must be 0, 16, 32 or 64");
     if (d->waves != 0 && !valid_waves(d->waves)) return fail(FFC_E_INVALID, "waves must be 0, 1, 2, 4, 8 or 16");
-    if (d->reserved != 0) return fail(FFC_E_INVALID, "reserved must be 0");
+    if (d->geometry < 0 || d->geometry > FFC_GEOMETRY_FUSED) return fail(FFC_E_INVALID, "geometry must be 0, 1 or 2");
     if (d->persistent < -1 || d->persistent > 1) return fail(FFC_E_INVALID, "persistent must be -1, 0 or 1");
     if (d->tile_window != 0 && d->tile_window != -1 && (d->tile_window < 16 || d->tile_window % 16 != 0))
         return fail(FFC_E_INVALID, "tile_window must be 0, -1 or a positive multiple of 16");
@@ -116,9 +119,13 @@ struct ffc_form {
     int64_t amap_cap = 0;
     // persistent FP64 contraction
     int pwaves = 0, pkmax = 0, pgrid = 0, n_zero = 0;
+    bool bpersistent = false;  // split modes: persistent BF16 contraction (pwaves, pkmax, pgrid set)
+    int ptile = 16;            // its cell tile
+    bool fused = false;  // ffc_tabulate_tensor computes the affine map inside the tile kernel
     int32_t* d_woff = nullptr;
-    int32_t* d_step_kstep = nullptr;
-    int32_t* d_step_end = nullptr;
+    double* d_wave_b = nullptr;
+    uint32_t* d_wave_word = nullptr;
+    uint32_t* d_wave_mask = nullptr;
     int32_t* d_zero = nullptr;
 
     ~ffc_form() {
@@ -127,7 +134,7 @@ struct ffc_form {
                         static_cast<void*>(d_bb), static_cast<void*>(d_nz), static_cast<void*>(d_pts),
                         static_cast<void*>(d_wts), static_cast<void*>(d_phi), static_cast<void*>(d_dphi),
                         static_cast<void*>(d_amap), static_cast<void*>(d_woff),
-                        static_cast<void*>(d_step_kstep), static_cast<void*>(d_step_end),
+                        static_cast<void*>(d_wave_b), static_cast<void*>(d_wave_word), static_cast<void*>(d_wave_mask),
                         static_cast<void*>(d_zero)})
             if (p) (void)hipFree(p);
     }
@@ -209,13 +216,33 @@ int ffc_form_create(const ffc_form_desc* desc, ffc_form** out) {
                 f->pwaves = ws.waves;
                 f->pkmax = ws.max_steps <= 8 ? 8 : ws.max_steps <= 16 ? 16 : 24;
                 f->n_zero = static_cast<int>(ws.zero_entries.size());
-                if ((rc = upload(ws.woff, &f->d_woff)) || (rc = upload(ws.step_kstep, &f->d_step_kstep)) ||
-                    (rc = upload(ws.step_end, &f->d_step_end)) || (rc = upload(ws.zero_entries, &f->d_zero)))
+                // each compute wave's register contents, expanded per step and lane so that
+                // the kernel loads them with independent, coalesced loads
+                const int nw = ws.waves - ffc::kIoWaves, km = f->pkmax;
+                std::vector<double> wb(static_cast<size_t>(nw) * km * 64, 0.0);
+                std::vector<uint32_t> wword(static_cast<size_t>(nw) * km * 64, 0u), wmask(nw, 0u);
+                for (int w = 0; w < nw; ++w)
+                    for (int s = 0; s < ws.woff[w + 1] - ws.woff[w]; ++s) {
+                        const int ks = ws.step_kstep[ws.woff[w] + s], te = ws.step_end[ws.woff[w] + s];
+                        if (te >= 0) wmask[w] |= 1u << s;
+                        for (int l = 0; l < 64; ++l) {
+                            const int lk = l / 16, lr = l % 16;
+                            const size_t i = (static_cast<size_t>(w) * km + s) * 64 + l;
+                            wb[i] = t.b[(static_cast<size_t>(ks) * 4 + lk) * 16 + lr];
+                            uint32_t word = (t.apack[ks] >> (8 * lk)) & 0xffu;
+                            if (te >= 0) word |= static_cast<uint32_t>(t.entry[te * 16 + lr] + 1) << 8;
+                            wword[i] = word;
+                        }
+                    }
+                if ((rc = upload(ws.woff, &f->d_woff)) || (rc = upload(wb, &f->d_wave_b)) ||
+                    (rc = upload(wword, &f->d_wave_word)) || (rc = upload(wmask, &f->d_wave_mask)) ||
+                    (rc = upload(ws.zero_entries, &f->d_zero)))
                     return rc;
+                // one 1024-thread workgroup per CU: at ~128 registers per lane two would
+                // not be resident together
                 hipDeviceProp_t prop;
                 HIP_TRY(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
-                const int per_cu = std::max(1, static_cast<int>((160 * 1024) / pl.total));
-                f->pgrid = prop.multiProcessorCount * std::min(per_cu, 2);
+                f->pgrid = prop.multiProcessorCount;
             }
         }
     } else {
@@ -226,11 +253,33 @@ int ffc_form_create(const ffc_form_desc* desc, ffc_form** out) {
         std::copy(t.gpiece, t.gpiece + 6, f->gpiece);
         f->mfma_k = static_cast<int64_t>(t.kpad) * t.n_tiles;
         if ((rc = upload(t.b, &f->d_bb)) || (rc = upload(t.nonzero, &f->d_nz))) return rc;
+        // persistent split-BF16 kernel when the form fits it (B fragments of at most 16
+        // steps per wave in registers, a staged tile in the I/O lanes' registers)
+        // (cell tiles of 32, else 16 cells: the largest that fits)
+        if (desc->kernel == FFC_KERNEL_TENSOR &&
+            (desc->persistent == 1 || (desc->persistent == 0 && rt.n_I >= kBf16PersistentMinEntries)) &&
+            (desc->waves == 0 || desc->waves == 16)) {
+            for (int ct : {32, 16}) {
+                if (desc->tile_cells != 0 && desc->tile_cells != ct) continue;
+                if (!ffc::plan_bf16_persistent(spec.dim, spec.kind, ct, rt.n_I, t.n_tiles, t.kpad, t.n_seg).staged)
+                    continue;
+                hipDeviceProp_t prop;
+                HIP_TRY(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+                f->bpersistent = true;
+                f->ptile = ct;
+                f->pwaves = 16;
+                f->pkmax = ffc::bf16_persistent_steps(t.n_tiles, t.kpad);
+                f->pgrid = prop.multiProcessorCount;
+                break;
+            }
+        }
     }
     if (desc->kernel == FFC_KERNEL_TENSOR) {
+        // geometry workspace (chunks of 2^21 cells), unless every tabulation is fused
         f->amap_cap = int64_t(1) << 21;
         const size_t bytes = static_cast<size_t>(f->amap_cap) * (1 + spec.dim * spec.dim) * sizeof(double);
-        if (hipMalloc(reinterpret_cast<void**>(&f->d_amap), bytes) != hipSuccess)
+        f->fused = desc->geometry != FFC_GEOMETRY_PASS && f->pwaves == 0;
+        if (!f->fused && hipMalloc(reinterpret_cast<void**>(&f->d_amap), bytes) != hipSuccess)
             return fail(FFC_E_NOMEM, "hipMalloc failed for the geometry workspace");
         // default launch shape when the persistent kernel does not apply
         const bool bf = desc->precision != FFC_FP64;
@@ -289,8 +338,9 @@ int ffc_form_get_info(const ffc_form* f, ffc_form_info* info) {
     info->quad_points = f->quad_npts;
     info->persistent_waves = f->pwaves;
     info->persistent_kmax = f->pkmax;
-    info->tile_cells = f->tile_cells;
+    info->tile_cells = f->bpersistent ? f->ptile : f->pwaves ? 16 : f->tile_cells;
     info->waves = f->waves;
+    info->fused_geometry = f->fused ? 1 : 0;
     return FFC_OK;
 }
 
@@ -311,10 +361,9 @@ int ffc_compute_geometry(int32_t dim, int64_t cells, const double* coords, doubl
 
 namespace {
 // contraction of cells [0, n) whose affine map sits at amap with row stride astride
-int contract_chunk(const ffc_form* f, int64_t n, const double* amap, int64_t astride, const double* coeffs,
-                   int64_t cstride, void* out) {
+ffc::ContractArgs contract_args(const ffc_form* f, int64_t n, const double* amap, int64_t astride,
+                                const double* coeffs, int64_t cstride, void* out) {
     const auto& rt = f->rt;
-    const bool bf16 = f->desc.precision != FFC_FP64;
     ffc::ContractArgs a{};
     a.cells = n;
     a.amap = amap;
@@ -336,9 +385,18 @@ int contract_chunk(const ffc_form* f, int64_t n, const double* amap, int64_t ast
     a.kpad = f->kpad;
     a.n_seg = f->n_seg;
     std::copy(f->gpiece, f->gpiece + 6, a.gpiece);
+    return a;
+}
+
+int contract_chunk(const ffc_form* f, int64_t n, const double* amap, int64_t astride, const double* coeffs,
+                   int64_t cstride, void* out) {
+    const bool bf16 = f->desc.precision != FFC_FP64;
+    ffc::ContractArgs a = contract_args(f, n, amap, astride, coeffs, cstride, out);
     hipError_t e = hipErrorInvalidValue;
-    if (f->pwaves > 0) {
-        ffc::PersistArgs p{f->d_woff, f->d_step_kstep, f->d_step_end, f->d_zero, f->n_zero};
+    if (f->bpersistent) {
+        e = ffc::launch_contract_bf16_persistent(f->desc.dim, f->desc.kind, f->ptile, f->pgrid, a, f->stream);
+    } else if (f->pwaves > 0) {
+        ffc::PersistArgs p{f->d_woff, f->d_wave_b, f->d_wave_word, f->d_wave_mask, f->d_zero, f->n_zero};
         e = ffc::launch_contract_persistent(f->desc.dim, f->desc.kind, f->pkmax, f->pwaves, f->pgrid, a, p, f->stream);
     }
     if (e == hipErrorInvalidValue)
@@ -393,6 +451,14 @@ int ffc_tabulate_tensor(const ffc_form* f, int64_t cells, const double* coords, 
     }
     const bool bf16 = f->desc.precision != FFC_FP64;
     const size_t obytes = bf16 ? 4 : 8;
+    if (f->fused) {
+        // one launch: every cell tile computes its affine map from the coordinates
+        ffc::ContractArgs a = contract_args(f, cells, nullptr, 0, coeffs, cells, out);
+        a.coords = coords;
+        hipError_t e = ffc::launch_contract(d, kind, bf16, f->tile_cells, f->waves, a, f->stream);
+        if (e != hipSuccess) return hip_fail(e, "contraction kernel launch");
+        return FFC_OK;
+    }
     for (int64_t c0 = 0; c0 < cells; c0 += f->amap_cap) {
         const int64_t n = std::min(f->amap_cap, cells - c0);
         hipError_t e = ffc::launch_geometry(d, n, coords + c0, cells, f->d_amap, f->amap_cap, f->stream);
@@ -507,7 +573,7 @@ int ffc_batch_create(int32_t n, const ffc_form* const* forms, const int64_t* cel
         if (!bf && f->pwaves == 16 && aligned && p16.staged &&
             (1 + d * d + f->rt.n_coeff) * 16 <= 64 * (16 - ffc::kIoWaves)) {
             it.kmax = f->pkmax;
-            it.p = ffc::PersistArgs{f->d_woff, f->d_step_kstep, f->d_step_end, f->d_zero, f->n_zero};
+            it.p = ffc::PersistArgs{f->d_woff, f->d_wave_b, f->d_wave_word, f->d_wave_mask, f->d_zero, f->n_zero};
             it.stage_bytes = p16.stage_bytes;
             it.head_bytes = p16.head_bytes;
             amap_doubles += cells[i] * (1 + d * d);
@@ -642,9 +708,11 @@ int ffc_mlp_mse(int64_t n, const float* y, const float* target, const float* mas
 }
 
 int ffc_adam_step(int64_t n, float* params, const float* grad, float* m, float* v, float lr, float beta1,
-                  float beta2, float eps, int32_t step, void* stream) {
-    if (n <= 0 || !params || !grad || !m || !v || step < 1) return fail(FFC_E_INVALID, "bad Adam arguments");
-    hipError_t e = ffc::adam_step(n, params, grad, m, v, lr, beta1, beta2, eps, step, static_cast<hipStream_t>(stream));
+                  float beta2, float eps, float weight_decay, int32_t step, void* stream) {
+    if (n <= 0 || !params || !grad || !m || !v || step < 1 || !(weight_decay >= 0.f))
+        return fail(FFC_E_INVALID, "bad Adam arguments");
+    hipError_t e = ffc::adam_step(n, params, grad, m, v, lr, beta1, beta2, eps, weight_decay, step,
+                                  static_cast<hipStream_t>(stream));
     return e == hipSuccess ? FFC_OK : hip_fail(e, "Adam launch");
 }
 

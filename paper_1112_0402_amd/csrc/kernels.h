@@ -13,6 +13,8 @@ struct ContractArgs {
     int64_t astride;
     const double* coeffs;   // SoA [n_coeff][cstride] or nullptr
     int64_t cstride;
+    const double* coords;   // non-null: SoA [(d+1)*d][cells] coordinates, affine map computed
+                            // per tile in LDS (amap unused; tile kernels only)
     void* out;              // [cells][n_I] double or float
     int n_I, n_alpha, n_tiles;
     double lambda, mu;      // unused by the contraction (inside A^0), kept for symmetry
@@ -64,9 +66,11 @@ hipError_t launch_contract(int dim, int kind, bool bf16, int tile_cells, int wav
 // Persistent FP64 contraction: 16-cell tiles, output rows staged in LDS, each wave's share
 // of the A^0 tiles (B fragments and alpha offsets, at most kmax k steps) held in registers.
 struct PersistArgs {
-    const int32_t* woff;          // [waves + 1]
-    const int32_t* step_kstep;    // [steps]
-    const int32_t* step_end;      // [steps]
+    const int32_t* woff;          // [compute waves + 1] step range of each wave
+    // per compute wave w, step s (s < kmax, zero past the wave's steps) and lane l:
+    const double* wave_b;         // [w][s][l] B fragment value
+    const uint32_t* wave_word;    // [w][s][l] LDS column of the alpha | (output entry + 1) << 8
+    const uint32_t* wave_mask;    // [w] bit s: step s ends a tile
     const int32_t* zero_entries;  // [n_zero]
     int n_zero;
 };
@@ -78,6 +82,16 @@ constexpr int kIoSlots = 20;
 // Returns hipErrorInvalidValue when the form does not fit this kernel (caller falls back).
 hipError_t launch_contract_persistent(int dim, int kind, int kmax, int waves, int grid, ContractArgs a,
                                       const PersistArgs& p, hipStream_t stream);
+// Persistent split-BF16 contraction (same pipeline) on cell tiles of 16 or 32 cells:
+// wave w of the 16 - kIoWaves compute waves owns A^0 tiles w, w + 10, ...; their B
+// fragments (kpad / 32 chunks each) stay in registers.
+// register steps per compute wave; LDS plan (staged = false when the form does not fit)
+int bf16_persistent_steps(int n_tiles, int kpad);
+int bf16_persistent_max_steps(int tile_cells, int n_seg);
+LdsPlan plan_bf16_persistent(int dim, int kind, int tile_cells, int n_I, int n_tiles, int kpad, int n_seg);
+// Returns hipErrorInvalidValue when the form or the output does not fit this kernel.
+hipError_t launch_contract_bf16_persistent(int dim, int kind, int tile_cells, int grid, ContractArgs a,
+                                           hipStream_t stream);
 hipError_t launch_quadrature(int dim, int kind, const QuadArgs& a, hipStream_t stream);
 size_t contract_lds_bytes(int dim, int kind, int tile_cells, int n_I, int n_alpha, int kpad, bool bf16);
 int quad_cells_per_block(int dim, int kind, int ns, int npts);

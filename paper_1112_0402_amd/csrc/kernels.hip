@@ -352,7 +352,10 @@ __global__ __launch_bounds__(1024) void contract_f64_kernel(ContractArgs A) {
     double* cf = am + (1 + D * D) * CT;
     double* Gs = reinterpret_cast<double*>(smem_raw + A.stage_bytes + A.head_bytes);
     const int64_t c0 = static_cast<int64_t>(blockIdx.x) * CT;
-    stage_tile<D, NC>(A, c0, CT, am, cf);
+    if (A.coords)
+        stage_tile_from_coords<D, NC>(A.coords, A.coeffs, A.cells, c0, CT, am, cf);
+    else
+        stage_tile<D, NC>(A, c0, CT, am, cf);
     __syncthreads();
     contract_tile_f64<D, KIND, MT>(am, cf, Gs, st, c0, A.cells, A.n_I, A.n_tiles, A.koff, A.apack, A.entry, A.b,
                                    static_cast<double*>(A.out));
@@ -486,7 +489,10 @@ __global__ __launch_bounds__(1024) void contract_bf16_kernel(ContractArgs A) {
     double* cf = am + (1 + D * D) * CT;
     unsigned short* Gp = reinterpret_cast<unsigned short*>(smem_raw + A.stage_bytes + A.head_bytes);
     const int64_t c0 = static_cast<int64_t>(blockIdx.x) * CT;
-    stage_tile<D, NC>(A, c0, CT, am, cf);
+    if (A.coords)
+        stage_tile_from_coords<D, NC>(A.coords, A.coeffs, A.cells, c0, CT, am, cf);
+    else
+        stage_tile<D, NC>(A, c0, CT, am, cf);
     __syncthreads();
     contract_tile_bf16<D, KIND, MT, NSEG>(am, cf, Gp, st, c0, A.cells, A.n_I, A.n_tiles, A.kpad, A.gpiece, A.bb,
                                           A.nonzero, static_cast<float*>(A.out));
@@ -636,23 +642,26 @@ __device__ __forceinline__ void persistent_tiles(const ContractArgs& A, const Pe
 #pragma unroll
     for (int r = 0; r < NR; ++r) R[r] = 0;
     uint32_t endmask = 0;
+    if (wave < n_compute) {
+        // this wave's fragments and words, prepared per step and lane on the host:
+        // independent coalesced loads, all in flight together
+        const double* wb = P.wave_b + static_cast<int64_t>(wave) * KMAX * 64 + lane;
+        const uint32_t* ww = P.wave_word + static_cast<int64_t>(wave) * KMAX * 64 + lane;
 #pragma unroll
-    for (int s = 0; s < KMAX; ++s) {
-        if (s < ns) {
-            const int ks = P.step_kstep[s0 + s];
-            const u32x2 bw = __builtin_bit_cast(u32x2, A.b[(static_cast<int64_t>(ks) * 4 + lk) * 16 + lr]);
+        for (int s = 0; s < KMAX; ++s) {
+            const u32x2 bw = __builtin_bit_cast(u32x2, wb[s * 64]);
             R[2 * s] = bw[0];
             R[2 * s + 1] = bw[1];
-            uint32_t word = (A.apack[ks] >> (8 * lk)) & 0xffu;
-            const int t = P.step_end[s0 + s];
-            if (t >= 0) {
-                endmask |= 1u << s;
-                word |= static_cast<uint32_t>(A.entry[t * 16 + lr] + 1) << 8;
-            }
-            R[2 * KMAX + s] = word;
+            R[2 * KMAX + s] = ww[s * 64];
         }
+        endmask = P.wave_mask[wave];
     }
     endmask = __builtin_amdgcn_readfirstlane(endmask);
+    // the register-resident fragments have arrived before the tile loop starts: without this
+    // the compiler, which cannot tell the loop's iterations apart, waits for every
+    // outstanding vector memory operation (the affine-map prefetch included) before each
+    // MFMA and each store
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
 
     // thread r*CT + c (r < ROWS) fetches row r of cell c: affine map, then coefficients
     auto fetch = [&](const MeshTile& t) -> double {
@@ -819,6 +828,281 @@ hipError_t launch_contract_persistent(int dim, int kind, int kmax, int waves, in
                     : launch_persistent_d<3>(kind, kmax, waves, grid, pl.total, a, p, stream);
 }
 
+// ------------------------------------------------ persistent split-BF16 contraction ---
+// The FP64 persistent pipeline for the split-BF16 mode, on cell tiles of CT = 16*MT cells:
+// affine map one tile ahead, the G tile's BF16 pieces built in LDS (the K padding is zeroed
+// once), the MFMA chain from LDS and registers into staged FP32 rows, and the write-out of a
+// tile by the I/O waves during the next tile's MFMA phase.  Compute wave w (of W) owns the
+// A^0 tiles w, w + W, w + 2W, ... and keeps their B fragments in registers: step s is the
+// 32-wide K chunk s mod KC of its tile number s / KC (KC = kpad / 32 chunks per tile), 8 BF16
+// values = 4 registers per lane; each step feeds MT MFMAs, one per 16-cell row block.
+
+template <int MT>
+struct Bf16PersistTraits {
+    // 16-byte register slots per I/O lane holding one staged tile (CT rows of FP32)
+    static constexpr int ios = MT == 1 ? 10 : 12;
+};
+
+template <int D, int KIND, int NSEG, int KS, int MT, class Src>
+__device__ __forceinline__ void persistent_tiles_bf16(const ContractArgs& A, Src& src, int64_t ct,
+                                                      const int64_t ct_end, const int64_t step,
+                                                      unsigned char* smem_raw) {
+    using FT = FormTraits<KIND, D>;
+    constexpr int CT = 16 * MT;
+    constexpr int NA = FT::n_alpha;
+    constexpr int NC = FT::n_coeff;
+    constexpr int ROWS = 1 + D * D + NC;
+    constexpr int IOS = Bf16PersistTraits<MT>::ios;
+    // one register file, two uses (as in the FP64 kernel): a compute lane keeps the B
+    // fragment of step s in R[4s .. 4s+3]; an I/O lane keeps 16-byte slot j of a staged
+    // tile in R[4j .. 4j+3]
+    constexpr int NR = KS > IOS ? 4 * KS : 4 * IOS;
+    float* st = reinterpret_cast<float*>(smem_raw);
+    double* am = reinterpret_cast<double*>(smem_raw + A.stage_bytes);
+    double* cf = am + (1 + D * D) * CT;
+    unsigned short* Gp = reinterpret_cast<unsigned short*>(smem_raw + A.stage_bytes + A.head_bytes);
+    const int kpad = A.kpad;
+    const int GK = kpad + 8;  // row stride of the G pieces (BF16 values)
+    const int KC = kpad / 32;
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int nI = A.n_I;
+    const int io_begin = blockDim.x - 64 * kIoWaves;
+    const int io_lane = tid - io_begin;
+    const int n_compute = (blockDim.x >> 6) - kIoWaves;
+    const int my_tiles = wave < n_compute ? (A.n_tiles - wave + n_compute - 1) / n_compute : 0;
+    const int ns = my_tiles * KC;
+
+    uint32_t R[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) R[r] = 0;
+    {
+        int j = 0, kc = 0;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            if (s < ns) {
+                const int t = wave + j * n_compute;
+                const u32x4 bw = __builtin_bit_cast(
+                    u32x4, reinterpret_cast<const u16x8*>(A.bb)[(static_cast<int64_t>(t) * (kpad / 8) + kc * 4 + lk) * 16 + lr]);
+                R[4 * s] = bw[0];
+                R[4 * s + 1] = bw[1];
+                R[4 * s + 2] = bw[2];
+                R[4 * s + 3] = bw[3];
+                if (++kc == KC) kc = 0, ++j;
+            }
+        }
+    }
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): fragments in registers before the tile loop
+    // K padding of the G pieces: zero once, no tile writes it
+    {
+        const int w = kpad - NSEG * NA;
+        for (int i = tid; i < CT * w; i += blockDim.x) {
+            const int c = i / w, k = NSEG * NA + (i - c * w);
+            Gp[c * GK + k] = 0;
+        }
+    }
+
+    // thread r*CT + c (r < ROWS) fetches row r of cell c: affine map, then coefficients
+    auto fetch = [&](const MeshTile& t) -> double {
+        const int r = tid / CT, c = tid - (tid / CT) * CT;
+        const int64_t cell = t.ct * CT + c;
+        if (cell >= t.cells) return r == 0 ? 1.0 : 0.0;
+        return r < 1 + D * D ? t.amap[r * t.astride + cell] : t.coeffs[(r - 1 - D * D) * t.cstride + cell];
+    };
+    // output run of a tile (floats)
+    auto out_run = [&](const MeshTile& t, float*& o, int64_t& n) {
+        const int64_t c0 = t.ct * CT;
+        o = reinterpret_cast<float*>(t.out) + c0 * nI;
+        n = (t.cells - c0 < CT ? t.cells - c0 : CT) * nI;
+    };
+    double pre = 0.0;
+    float* cur_out = nullptr;
+    int64_t cur_n = 0;
+    if (ct < ct_end) {
+        const MeshTile t = src.at(ct);
+        out_run(t, cur_out, cur_n);
+        if (tid < ROWS * CT) pre = fetch(t);
+    }
+    const unsigned short* grow = Gp + lr * GK + lk * 8;
+    float* io_out = nullptr;
+    int64_t io_n = 0;
+    // I/O lanes: 16-byte slot j of lane l holds floats 4 (l + j * 64 * kIoWaves) .. + 3
+    auto io_store = [&]() {
+        const int64_t nv = io_n / 4;
+        const int jn = nv > io_lane ? static_cast<int>((nv - io_lane + 64 * kIoWaves - 1) / (64 * kIoWaves)) : 0;
+        u32x4* ov = reinterpret_cast<u32x4*>(io_out) + io_lane;
+#pragma unroll
+        for (int j = 0; j < IOS; ++j) {
+            if (j < jn) *ov = u32x4{R[4 * j], R[4 * j + 1], R[4 * j + 2], R[4 * j + 3]};
+            ov += 64 * kIoWaves;
+        }
+    };
+    for (; ct < ct_end; ct += step) {
+        const bool more = ct + step < ct_end;
+        float* nxt_out = nullptr;
+        int64_t nxt_n = 0;
+        if (tid < ROWS * CT) am[tid] = pre;
+        if (more) {
+            const MeshTile t = src.at(ct + step);
+            out_run(t, nxt_out, nxt_n);
+            if (tid < ROWS * CT) pre = fetch(t);
+        }
+        lds_barrier();
+        for (int i = tid; i < CT * NA; i += blockDim.x) {
+            const int c = i / NA, al = i - c * NA;
+            const double gv = g_entry<KIND, D>(am, cf, CT, c, al);
+            double piece[3];
+            piece[0] = rn_bf16(gv);
+            piece[1] = rn_bf16(gv - piece[0]);
+            piece[2] = rn_bf16((gv - piece[0]) - piece[1]);
+#pragma unroll
+            for (int sg = 0; sg < NSEG; ++sg) Gp[c * GK + sg * NA + al] = bf16_of(piece[A.gpiece[sg]]);
+        }
+        lds_barrier();
+        if (tid >= io_begin) {
+            if (io_n > 0) io_store();  // the previous tile, during this tile's MFMA phase
+        } else {
+            f4 acc[MT];
+#pragma unroll
+            for (int m = 0; m < MT; ++m) acc[m] = f4{0.f, 0.f, 0.f, 0.f};
+            int j = 0, kc = 0;
+#pragma unroll
+            for (int s = 0; s < KS; ++s) {
+                if (s < ns) {
+                    const bf8 bv =
+                        __builtin_bit_cast(bf8, u32x4{R[4 * s], R[4 * s + 1], R[4 * s + 2], R[4 * s + 3]});
+                    u16x8 av[MT];
+#pragma unroll
+                    for (int m = 0; m < MT; ++m) av[m] = *reinterpret_cast<const u16x8*>(grow + m * 16 * GK + kc * 32);
+#pragma unroll
+                    for (int m = 0; m < MT; ++m)
+                        acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, av[m]), bv, acc[m], 0,
+                                                                         0, 0);
+                    if (++kc == KC) {
+                        const int e = (wave + j * n_compute) * 16 + lr;
+                        if (e < nI) {
+#pragma unroll
+                            for (int m = 0; m < MT; ++m)
+#pragma unroll
+                                for (int i = 0; i < 4; ++i) st[(m * 16 + lk * 4 + i) * nI + e] = acc[m][i];
+                        }
+#pragma unroll
+                        for (int m = 0; m < MT; ++m) {
+                            acc[m] = f4{0.f, 0.f, 0.f, 0.f};
+                            asm volatile("" : "+v"(acc[m]));
+                        }
+                        kc = 0;
+                        ++j;
+                    }
+                }
+            }
+        }
+        lds_barrier();
+        if (tid >= io_begin) {  // take this tile's rows into registers; st is free after the next barrier
+            io_out = cur_out;
+            io_n = cur_n;
+            const int64_t nv = io_n / 4;
+            const int jn = nv > io_lane ? static_cast<int>((nv - io_lane + 64 * kIoWaves - 1) / (64 * kIoWaves)) : 0;
+            const u32x4* sv = reinterpret_cast<const u32x4*>(st) + io_lane;
+#pragma unroll
+            for (int j = 0; j < IOS; ++j) {
+                if (j < jn) {
+                    const u32x4 w = *sv;
+                    R[4 * j] = w[0];
+                    R[4 * j + 1] = w[1];
+                    R[4 * j + 2] = w[2];
+                    R[4 * j + 3] = w[3];
+                }
+                sv += 64 * kIoWaves;
+            }
+            // a tail of fewer than 4 floats (a last, partial cell tile): stored right away
+            const int64_t tail = io_n - nv * 4;
+            if (io_lane < tail) io_out[nv * 4 + io_lane] = st[nv * 4 + io_lane];
+        }
+        cur_out = nxt_out;
+        cur_n = nxt_n;
+    }
+    if (tid >= io_begin && io_n > 0) io_store();  // the last tile
+}
+
+template <int D, int KIND, int NSEG, int KS, int MT>
+__global__ __launch_bounds__(1024) void contract_bf16_persistent(ContractArgs A) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    OneMesh src{A};
+    persistent_tiles_bf16<D, KIND, NSEG, KS, MT>(A, src, blockIdx.x, (A.cells + 16 * MT - 1) / (16 * MT), gridDim.x,
+                                                smem_raw);
+}
+
+// Register budget (128 per lane at 1024 threads): at most 16 register-resident steps, and 8
+// for 32-cell tiles with the 6-product split (its G build needs more registers).
+int bf16_persistent_max_steps(int tile_cells, int n_seg) { return tile_cells == 32 && n_seg == 6 ? 8 : 16; }
+
+template <int D, int KIND, int NSEG, int MT>
+static hipError_t launch_bf16_persistent_m(int ks, int grid, size_t lds, const ContractArgs& a, hipStream_t s) {
+    if (ks <= 8) return launch_lds(contract_bf16_persistent<D, KIND, NSEG, 8, MT>, grid, 1024u, lds, s, a);
+    if constexpr (MT == 1 || NSEG == 3)
+        return launch_lds(contract_bf16_persistent<D, KIND, NSEG, 16, MT>, grid, 1024u, lds, s, a);
+    return hipErrorInvalidValue;
+}
+
+template <int D, int KIND, int NSEG>
+static hipError_t launch_bf16_persistent_k(int mt, int ks, int grid, size_t lds, const ContractArgs& a,
+                                           hipStream_t s) {
+    return mt == 1 ? launch_bf16_persistent_m<D, KIND, NSEG, 1>(ks, grid, lds, a, s)
+                   : launch_bf16_persistent_m<D, KIND, NSEG, 2>(ks, grid, lds, a, s);
+}
+
+template <int D, int NSEG>
+static hipError_t launch_bf16_persistent_d(int kind, int mt, int ks, int grid, size_t lds, const ContractArgs& a,
+                                           hipStream_t s) {
+    switch (kind) {
+    case K_MASS: return launch_bf16_persistent_k<D, K_MASS, NSEG>(mt, ks, grid, lds, a, s);
+    case K_LAPLACE: return launch_bf16_persistent_k<D, K_LAPLACE, NSEG>(mt, ks, grid, lds, a, s);
+    case K_WLAPLACE: return launch_bf16_persistent_k<D, K_WLAPLACE, NSEG>(mt, ks, grid, lds, a, s);
+    case K_ELASTICITY: return launch_bf16_persistent_k<D, K_ELASTICITY, NSEG>(mt, ks, grid, lds, a, s);
+    default: return launch_bf16_persistent_k<D, K_NS, NSEG>(mt, ks, grid, lds, a, s);
+    }
+}
+
+int bf16_persistent_steps(int n_tiles, int kpad) {
+    const int n_compute = 16 - kIoWaves;
+    return (n_tiles + n_compute - 1) / n_compute * (kpad / 32);
+}
+
+LdsPlan plan_bf16_persistent(int dim, int kind, int tile_cells, int n_I, int n_tiles, int kpad, int n_seg) {
+    LdsPlan p = plan_lds(dim, kind, tile_cells, n_I, 0, kpad, true, kLdsBudget);
+    const int ios = tile_cells == 16 ? Bf16PersistTraits<1>::ios : Bf16PersistTraits<2>::ios;
+    const int64_t units = (tile_cells * static_cast<int64_t>(n_I) + 3) / 4;
+    const bool fits = (tile_cells == 16 || tile_cells == 32) && p.staged &&
+                      bf16_persistent_steps(n_tiles, kpad) <= bf16_persistent_max_steps(tile_cells, n_seg) &&
+                      units <= static_cast<int64_t>(ios) * 64 * kIoWaves &&
+                      (1 + dim * dim + n_coeff_of(dim, kind)) * tile_cells <= 1024;
+    if (!fits) p.staged = false;
+    return p;
+}
+
+hipError_t launch_contract_bf16_persistent(int dim, int kind, int tile_cells, int grid, ContractArgs a,
+                                           hipStream_t stream) {
+    if (a.cells <= 0) return hipSuccess;
+    if ((reinterpret_cast<uintptr_t>(a.out) & 15u) != 0) return hipErrorInvalidValue;
+    const LdsPlan pl = plan_bf16_persistent(dim, kind, tile_cells, a.n_I, a.n_tiles, a.kpad, a.n_seg);
+    if (!pl.staged) return hipErrorInvalidValue;
+    a.staged = 1;
+    a.stage_bytes = pl.stage_bytes;
+    a.head_bytes = pl.head_bytes;
+    const int ks = bf16_persistent_steps(a.n_tiles, a.kpad);
+    const int mt = tile_cells / 16;
+    const int64_t ntiles = (a.cells + tile_cells - 1) / tile_cells;
+    if (grid > ntiles) grid = static_cast<int>(ntiles);
+    if (a.n_seg == 3)
+        return dim == 2 ? launch_bf16_persistent_d<2, 3>(kind, mt, ks, grid, pl.total, a, stream)
+                        : launch_bf16_persistent_d<3, 3>(kind, mt, ks, grid, pl.total, a, stream);
+    return dim == 2 ? launch_bf16_persistent_d<2, 6>(kind, mt, ks, grid, pl.total, a, stream)
+                    : launch_bf16_persistent_d<3, 6>(kind, mt, ks, grid, pl.total, a, stream);
+}
+
 // --------------------------------------------------------------- mixed batches ---
 // Tile launch: workgroup u runs tile u of the launch, cell tile 16*MT of item unit_item[u]
 // (one launch per tile size, so each kernel's register count is that of its own tile),
@@ -915,8 +1199,8 @@ __global__ __launch_bounds__(1024) void batch_persistent_kernel(const BatchItem*
     A.entry = as_global(f.entry);
     A.stage_bytes = f.stage_bytes;
     A.head_bytes = f.head_bytes;
-    const PersistArgs P{as_global(f.p.woff), as_global(f.p.step_kstep), as_global(f.p.step_end),
-                        as_global(f.p.zero_entries), f.p.n_zero};
+    const PersistArgs P{as_global(f.p.woff), as_global(f.p.wave_b), as_global(f.p.wave_word),
+                        as_global(f.p.wave_mask), as_global(f.p.zero_entries), f.p.n_zero};
     ItemCursor src{items, n_items, -1, 0, 0, MeshTile{}};
     persistent_tiles<D, KIND, KMAX, kIoSlots>(A, P, src, blockIdx.x, total_tiles, gridDim.x, smem_raw);
 }

@@ -14,6 +14,6 @@ hipError_t mlp_backward(int in, int h, int out, int64_t batch, const float* para
                         const float* dy, float* grad, float* work, hipStream_t s);
 hipError_t mlp_mse(int64_t n, const float* y, const float* t, const float* m, float* dy, float* loss, hipStream_t s);
 hipError_t adam_step(int64_t n, float* p, const float* g, float* m, float* v, float lr, float b1, float b2, float eps,
-                     int step, hipStream_t s);
+                     float wd, int step, hipStream_t s);
 
 }  // namespace ffc

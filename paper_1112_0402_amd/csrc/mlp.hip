@@ -92,10 +92,11 @@ __global__ void mse_kernel(int64_t n, const float* __restrict__ Y, const float* 
 }
 
 __global__ void adam_kernel(int64_t n, float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
-                            float* __restrict__ v, float lr, float b1, float b2, float eps, float c1, float c2) {
+                            float* __restrict__ v, float lr, float b1, float b2, float eps, float wd, float c1,
+                            float c2) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const float gi = g[i];
+    const float gi = g[i] + wd * p[i];  // L2 term
     const float mi = b1 * m[i] + (1.f - b1) * gi;
     const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
     m[i] = mi;
@@ -158,10 +159,10 @@ hipError_t mlp_mse(int64_t n, const float* y, const float* t, const float* m, fl
 }
 
 hipError_t adam_step(int64_t n, float* p, const float* g, float* m, float* v, float lr, float b1, float b2, float eps,
-                     int step, hipStream_t s) {
+                     float wd, int step, hipStream_t s) {
     const float c1 = 1.f - powf(b1, static_cast<float>(step));
     const float c2 = 1.f - powf(b2, static_cast<float>(step));
-    adam_kernel<<<blocks(n), 256, 0, s>>>(n, p, g, m, v, lr, b1, b2, eps, c1, c2);
+    adam_kernel<<<blocks(n), 256, 0, s>>>(n, p, g, m, v, lr, b1, b2, eps, wd, c1, c2);
     return hipGetLastError();
 }
 

@@ -3,15 +3,18 @@ between the tensor-representation kernel (in several launch shapes) and the quad
 kernel -- the automatic choice between the two approaches that Sec. 4.4 leaves open.
 
 * features: form rank, degree q, log2 |i| (element tensor entries), log2(|alpha| + 1),
-  dimension, log2(cells);
-* output: predicted log(ms) of every candidate launch of ``tune.CANDIDATES_FP64``; the
-  choice is the argmin;
+  dimension, log2(cells), log2(cells |i|) (output entries);
+* output: predicted log(t_c / t_default) of every candidate launch c of
+  ``tune.CANDIDATES_FP64`` relative to the library default launch (candidate 0); the choice
+  is the argmin (the default itself predicts ~0), so the network only has to learn where
+  and by how much a launch beats the default;
 * training data: the autotuner's sweep (``tune.sweep``), whose exhaustive minimum is also
   the judge: regret = t_chosen / t_best - 1;
 * training runs on the GPU through the library's own MLP forward, backward, MSE and Adam
-  kernels (``ffc_mlp_*`` in include/ffc_hip.h); ``ref_forward`` / ``ref_backward`` are the
-  plain FP64 NumPy statements of the same network that the tests check those kernels
-  against.
+  kernels (``ffc_mlp_*`` in include/ffc_hip.h), with an L2 weight penalty (the sweeps give
+  a few hundred noisy timings; without it the network fits the noise); ``ref_forward`` /
+  ``ref_backward`` are the plain FP64 NumPy statements of the same network that the tests
+  check those kernels against.
 
 Both kernels a choice can route to are exact to their stated tolerances, so the selector
 changes speed, never results.
@@ -26,11 +29,12 @@ import numpy as np
 from . import capi
 from .tune import CANDIDATES_FP64
 
-N_FEATURES = 6
+N_FEATURES = 7
 
 
 def features(kind: str, dim: int, degree: int, cells: int, n_I: int, n_alpha: int) -> np.ndarray:
-    return np.array([2.0, degree, math.log2(n_I), math.log2(n_alpha + 1), dim, math.log2(max(cells, 1))],
+    lc = math.log2(max(cells, 1))
+    return np.array([2.0, degree, math.log2(n_I), math.log2(n_alpha + 1), dim, lc, lc + math.log2(n_I)],
                     dtype=np.float64)
 
 
@@ -135,14 +139,14 @@ class MLP:
                                           loss.data_ptr(), self._s()))
         return loss, dy
 
-    def adam(self, lr=3e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    def adam(self, lr=3e-3, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0):
         self.step_count += 1
         capi.check(capi.lib().ffc_adam_step(self.n_params, self.params.data_ptr(), self.grad.data_ptr(),
                                             self.m.data_ptr(), self.v.data_ptr(), ctypes.c_float(lr),
                                             ctypes.c_float(beta1), ctypes.c_float(beta2), ctypes.c_float(eps),
-                                            self.step_count, self._s()))
+                                            ctypes.c_float(weight_decay), self.step_count, self._s()))
 
-    def fit(self, X, Y, M, epochs=3000, lr=3e-3):
+    def fit(self, X, Y, M, epochs=3000, lr=3e-3, weight_decay=0.0):
         """Full-batch training on (X features, Y targets, M masks) -> final loss."""
         import torch
 
@@ -154,7 +158,7 @@ class MLP:
             y, act = self.forward(x)
             loss, dy = self.mse(y, t, m)
             self.backward(x, act, dy)
-            self.adam(lr)
+            self.adam(lr, weight_decay=weight_decay)
         torch.cuda.synchronize()
         return float(loss.item())
 
@@ -170,14 +174,18 @@ class MLP:
 # ----------------------------------------------------------------- the selector ---
 
 def records_to_arrays(records):
+    """Features, targets log(t_c / t_0) and masks (0 where a timing is missing)."""
     X = np.stack([features(r["kind"], r["dim"], r["degree"], r["cells"], r["n_I"], r["n_alpha"]) for r in records])
-    T = np.array([[math.log(t) if t is not None and t > 0 else 0.0 for t in r["ms"]] for r in records])
-    M = np.array([[1.0 if t is not None and t > 0 else 0.0 for t in r["ms"]] for r in records])
+    ok = lambda t: t is not None and t > 0  # noqa: E731
+    T = np.array([[math.log(t / r["ms"][0]) if ok(t) and ok(r["ms"][0]) else 0.0 for t in r["ms"]]
+                  for r in records])
+    M = np.array([[1.0 if ok(t) and ok(r["ms"][0]) else 0.0 for t in r["ms"]] for r in records])
     return X, T, M
 
 
 class Selector:
-    """Normalised features -> MLP -> argmin predicted time over the candidates."""
+    """Normalised features -> MLP -> argmin of the predicted time relative to the default
+    launch over the candidates."""
 
     def __init__(self, n_hidden=64, seed=0):
         self.net = MLP(n_hidden=n_hidden, seed=seed)
@@ -185,18 +193,19 @@ class Selector:
         self.sd = np.ones(N_FEATURES)
         self.tmu = 0.0
 
-    def fit(self, records, epochs=3000, lr=3e-3):
+    def fit(self, records, epochs=3000, lr=3e-3, weight_decay=1e-3):
         X, T, M = records_to_arrays(records)
         self.mu, self.sd = X.mean(0), X.std(0) + 1e-9
         self.tmu = float((T * M).sum() / M.sum())
-        return self.net.fit((X - self.mu) / self.sd, T - self.tmu, M, epochs, lr)
+        return self.net.fit((X - self.mu) / self.sd, T - self.tmu, M, epochs, lr, weight_decay)
 
-    def predict_log_ms(self, records):
+    def predict_rel(self, records):
+        """Predicted log(t_c / t_default) per record and candidate."""
         X, _, _ = records_to_arrays(records)
         return self.net.predict((X - self.mu) / self.sd) + self.tmu
 
     def choose(self, records):
-        return [int(i) for i in np.argmin(self.predict_log_ms(records), axis=1)]
+        return [int(i) for i in np.argmin(self.predict_rel(records), axis=1)]
 
 
 def heuristic_choice(kind: str, dim: int, degree: int) -> int:

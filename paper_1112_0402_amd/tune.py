@@ -19,17 +19,24 @@ import numpy as np
 # Candidate launches.  Index order is part of the sweep-file format (the selector's outputs).
 CANDIDATES_FP64 = (
     {"kernel": "tensor", "tile_cells": 0, "waves": 0, "persistent": 0, "tile_window": 0},      # library default
-    {"kernel": "tensor", "tile_cells": 16, "waves": 16, "persistent": -1, "tile_window": -1},  # staged, clustered
-    {"kernel": "tensor", "tile_cells": 64, "waves": 8, "persistent": -1, "tile_window": -1},
-    {"kernel": "tensor", "tile_cells": 64, "waves": 4, "persistent": -1, "tile_window": 16},   # consecutive rows
-    {"kernel": "tensor", "tile_cells": 32, "waves": 8, "persistent": -1, "tile_window": 16},
-    {"kernel": "quadrature"},
+    # geometry pass, then the contraction
+    {"kernel": "tensor", "tile_cells": 16, "waves": 16, "persistent": -1, "tile_window": -1, "geometry": "pass"},
+    {"kernel": "tensor", "tile_cells": 64, "waves": 8, "persistent": -1, "tile_window": -1, "geometry": "pass"},
+    {"kernel": "tensor", "tile_cells": 64, "waves": 4, "persistent": -1, "tile_window": 16, "geometry": "pass"},
+    {"kernel": "tensor", "tile_cells": 32, "waves": 8, "persistent": -1, "tile_window": 16, "geometry": "pass"},
+    # one launch: affine map computed per cell tile
+    {"kernel": "tensor", "tile_cells": 64, "waves": 4, "persistent": -1, "tile_window": 16, "geometry": "fused"},
+    {"kernel": "tensor", "tile_cells": 32, "waves": 8, "persistent": -1, "tile_window": 16, "geometry": "fused"},
+    {"kernel": "quadrature"},  # last: the analytic rule's alternative
 )
 CANDIDATES_SPLIT = (
     {"kernel": "tensor", "tile_cells": 0, "waves": 0},
-    {"kernel": "tensor", "tile_cells": 64, "waves": 4},
-    {"kernel": "tensor", "tile_cells": 32, "waves": 8},
-    {"kernel": "tensor", "tile_cells": 16, "waves": 8},
+    {"kernel": "tensor", "tile_cells": 0, "waves": 0, "persistent": 1},
+    {"kernel": "tensor", "tile_cells": 64, "waves": 4, "geometry": "pass"},
+    {"kernel": "tensor", "tile_cells": 32, "waves": 8, "geometry": "pass"},
+    {"kernel": "tensor", "tile_cells": 16, "waves": 8, "geometry": "pass"},
+    {"kernel": "tensor", "tile_cells": 64, "waves": 4, "geometry": "fused"},
+    {"kernel": "tensor", "tile_cells": 32, "waves": 8, "geometry": "fused"},
 )
 
 
@@ -42,27 +49,40 @@ def make_form(kind, dim, degree, precision, cand):
 
     return Form(kind, dim, degree, precision=precision if cand["kernel"] == "tensor" else "fp64",
                 kernel=cand["kernel"], tile_cells=cand.get("tile_cells", 0), waves=cand.get("waves", 0),
-                persistent=cand.get("persistent", 0), tile_window=cand.get("tile_window", 0))
+                persistent=cand.get("persistent", 0), tile_window=cand.get("tile_window", 0),
+                geometry=cand.get("geometry", 0))
 
 
 def measure(form, X, C, reps: int = 5, warmup: int = 2) -> float:
     """Median milliseconds of one tabulation (geometry + contraction, or quadrature)."""
+    return measure_all([form], X, C, reps, warmup)[0]
+
+
+def measure_all(forms, X, C, reps: int = 7, warmup: int = 2):
+    """Median milliseconds of one tabulation for each form on the same mesh, measured in
+    interleaved rounds (every form once per round), so clock and power drift during the
+    measurement falls on all candidates alike.  Forms sharing an output dtype share one
+    output buffer."""
     import torch
 
-    out = form.empty_out(X.shape[1])
-    stream = form.stream
+    outs = {}
+    for f in forms:
+        if f.out_dtype not in outs:
+            outs[f.out_dtype] = f.empty_out(X.shape[1])
     for _ in range(warmup):
-        form.tabulate(X, C, out=out)
+        for f in forms:
+            f.tabulate(X, C, out=outs[f.out_dtype])
     torch.cuda.synchronize()
-    times = []
+    times = [[] for _ in forms]
     for _ in range(reps):
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        form.tabulate(X, C, out=out)
-        b.record(stream)
-        b.synchronize()
-        times.append(a.elapsed_time(b))
-    return float(np.median(times))
+        for j, f in enumerate(forms):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(f.stream)
+            f.tabulate(X, C, out=outs[f.out_dtype])
+            b.record(f.stream)
+            b.synchronize()
+            times[j].append(a.elapsed_time(b))
+    return [float(np.median(t)) for t in times]
 
 
 def shape_key(kind, dim, degree, precision, cells) -> str:
@@ -102,11 +122,10 @@ class TuneDB:
 
 def autotune(kind, dim, degree, precision, X, C, db: TuneDB | None = None, reps: int = 5):
     """Time every candidate on this mesh; return (index, config, ms list)."""
-    times = []
-    for cand in candidates(precision):
-        form = make_form(kind, dim, degree, precision, cand)
-        times.append(measure(form, X, C, reps))
-        form.close()
+    forms = [make_form(kind, dim, degree, precision, cand) for cand in candidates(precision)]
+    times = measure_all(forms, X, C, reps)
+    for f in forms:
+        f.close()
     best = int(np.argmin(times))
     if db is not None:
         db.put(shape_key(kind, dim, degree, precision, X.shape[1]),
@@ -118,7 +137,7 @@ def sweep_shapes(variants, cells_list):
     return [(k, d, q, c) for (k, d, q) in variants for c in cells_list]
 
 
-def sweep(shapes, path: str, precision: str = "fp64", reps: int = 5, seed: int = 5, log=print):
+def sweep(shapes, path: str, precision: str = "fp64", reps: int = 7, seed: int = 5, log=print):
     """Time every candidate on every shape; one JSON line per shape, appended to `path`;
     shapes already in the file are skipped (resume)."""
     import torch
@@ -139,12 +158,11 @@ def sweep(shapes, path: str, precision: str = "fp64", reps: int = 5, seed: int =
         wl = meshgen.make_workload(kind, dim, degree, max(n, 1), seed + i, max_cells=cells)
         X = torch.from_numpy(wl.coords).cuda()
         C = None if wl.coeffs is None else torch.from_numpy(wl.coeffs).cuda()
-        times = []
         for j, cand in enumerate(candidates(precision)):
             key = (kind, dim, degree, j)
             if key not in forms:
                 forms[key] = make_form(kind, dim, degree, precision, cand)
-            times.append(measure(forms[key], X, C, reps))
+        times = measure_all([forms[(kind, dim, degree, j)] for j in range(len(candidates(precision)))], X, C, reps)
         info = Form(kind, dim, degree, precision=precision).info
         rec = {"kind": kind, "dim": dim, "degree": degree, "precision": precision, "cells": cells,
                "n_I": info["n_entries"], "n_alpha": info["n_alpha"], "ms": times, "time": time.time()}
@@ -175,7 +193,7 @@ if __name__ == "__main__":
     ap = argparse.ArgumentParser(description="time every candidate launch on a sweep of shapes (resumable)")
     ap.add_argument("--out", required=True, help="JSON-lines file to append to")
     ap.add_argument("--precision", default="fp64")
-    ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--reps", type=int, default=7)
     args = ap.parse_args()
     sweep(default_sweep_shapes(), args.out, precision=args.precision, reps=args.reps,
           log=lambda s: print(s, flush=True))

@@ -64,6 +64,50 @@ def test_fp64_launch_shapes(tile_cells, waves):
     assert rel_fro(got, ref)[0] <= FP64_TOL
 
 
+@pytest.mark.parametrize("kind,dim,q", [("wlaplace", 3, 3), ("mass", 3, 3), ("laplace", 3, 3), ("laplace", 2, 4),
+                                        ("wlaplace", 2, 4), ("ns", 2, 2), ("elasticity", 2, 3), ("mass", 2, 1)])
+@pytest.mark.parametrize("precision", ["bf16x3", "bf16x6"])
+@pytest.mark.parametrize("tile_cells", [16, 32])
+def test_persistent_split_bf16_matches_tile_kernel(kind, dim, q, precision, tile_cells):
+    """The persistent split-BF16 kernel (B fragments in registers, I/O waves) against the
+    per-tile kernel: same pieces and the same K order, so equal bit for bit, over a mesh of
+    several tiles per workgroup with a ragged tail; and the oracle on sampled cells."""
+    require_gpu()
+    n = 70 if dim == 2 else 12
+    wl = meshgen.make_workload(kind, dim, q, n, 77, max_cells=9999)
+    pers = Form(kind, dim, q, precision=precision, persistent=1, tile_cells=tile_cells)
+    tile = Form(kind, dim, q, precision=precision, persistent=-1)
+    if not pers.info["persistent_waves"]:
+        pytest.skip("form does not fit the persistent split-BF16 kernel")
+    assert not tile.info["persistent_waves"]
+    a, b = _run(pers, wl), _run(tile, wl)
+    assert np.array_equal(a, b)
+    idx = _sample(wl.cells, 64, 5)
+    ref = oracle.tabulate(kind, dim, q, np.ascontiguousarray(wl.coords[:, idx]),
+                          None if wl.coeffs is None else np.ascontiguousarray(wl.coeffs[:, idx]))
+    e = rel_fro(a[idx], ref)[0]
+    say(f"[bf16 persistent] {kind} d={dim} q={q} {precision} {tile_cells} cells: steps {pers.info['persistent_kmax']} "
+        f"max err {e:.2e}")
+    assert e <= (SPLIT6_TOL if precision == "bf16x6" else SPLIT3_BOUND)
+
+
+@pytest.mark.parametrize("kind,dim,q", [("laplace", 2, 1), ("mass", 3, 3), ("laplace", 3, 4), ("wlaplace", 3, 3),
+                                        ("elasticity", 3, 1), ("ns", 2, 2), ("wlaplace", 2, 4), ("elasticity", 2, 3)])
+@pytest.mark.parametrize("precision", ["fp64", "bf16x6"])
+@pytest.mark.parametrize("tile_cells", [0, 16, 64])
+def test_fused_geometry_matches_geometry_pass(kind, dim, q, precision, tile_cells):
+    """The one-launch path (affine map computed per tile in LDS) equals the geometry pass
+    plus contraction bit for bit, and the oracle to the precision's bound."""
+    require_gpu()
+    wl = _small(kind, dim, q)
+    fused = Form(kind, dim, q, precision=precision, geometry="fused", tile_cells=tile_cells)
+    passed = Form(kind, dim, q, precision=precision, geometry="pass", tile_cells=tile_cells)
+    a, b = _run(fused, wl), _run(passed, wl)
+    assert np.array_equal(a, b)
+    ref = oracle.tabulate(kind, dim, q, wl.coords, wl.coeffs)
+    assert rel_fro(a, ref)[0] <= (FP64_TOL if precision == "fp64" else SPLIT6_TOL)
+
+
 @pytest.mark.parametrize("kind,dim,q", [("laplace", 2, 1), ("mass", 3, 3), ("laplace", 3, 4), ("wlaplace", 3, 3),
                                         ("elasticity", 3, 2), ("ns", 3, 2), ("ns", 2, 2), ("mass", 2, 2)])
 @pytest.mark.parametrize("precision", ["bf16x3", "bf16x6"])

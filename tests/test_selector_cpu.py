@@ -50,7 +50,15 @@ def test_regret_and_features():
     r = selector.regret(recs, [0, 5])
     assert np.allclose(r, [1.0, 0.0])
     f = selector.features("laplace", 3, 2, 1024, 100, 9)
-    assert f.shape == (selector.N_FEATURES,) and f[-1] == 10
+    assert f.shape == (selector.N_FEATURES,) and f[5] == 10 and np.isclose(f[6], 10 + np.log2(100))
+
+
+def test_targets_are_relative_to_the_default_launch():
+    recs = [{"kind": "mass", "dim": 2, "degree": 1, "cells": 64, "n_I": 9, "n_alpha": 1,
+             "ms": [2.0, 1.0, None, 4.0]}]
+    X, T, M = selector.records_to_arrays(recs)
+    assert np.allclose(T[0], [0.0, np.log(0.5), 0.0, np.log(2.0)])
+    assert np.array_equal(M[0], [1, 1, 0, 1])
 
 
 def test_tune_db_roundtrip(tmp_path):

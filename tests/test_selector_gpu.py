@@ -18,13 +18,13 @@ SWEEP = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def test_mlp_kernels_match_fp64_reference():
     require_gpu()
-    net = selector.MLP(n_in=6, n_hidden=32, n_out=6, seed=3)
+    net = selector.MLP(n_in=7, n_hidden=32, n_out=6, seed=3)
     rng = np.random.default_rng(0)
-    X = rng.normal(size=(300, 6))
+    X = rng.normal(size=(300, 7))
     x = torch.tensor(X, dtype=torch.float32, device="cuda")
     y, act = net.forward(x)
     p = net.params.cpu().numpy().astype(np.float64)
-    yref, _ = selector.ref_forward(p, x.cpu().numpy().astype(np.float64), 6, 32, 6)
+    yref, _ = selector.ref_forward(p, x.cpu().numpy().astype(np.float64), 7, 32, 6)
     assert np.allclose(y.cpu().numpy(), yref, rtol=1e-4, atol=1e-4)
     T = rng.normal(size=(300, 6))
     Mk = (rng.uniform(size=(300, 6)) > 0.2).astype(np.float64)
@@ -35,20 +35,19 @@ def test_mlp_kernels_match_fp64_reference():
     assert abs(float(loss.item()) - lref) < 1e-4 * max(1.0, lref)
     assert np.allclose(dy.cpu().numpy(), dyref, rtol=1e-3, atol=1e-6)
     g = net.backward(x, act, dy).cpu().numpy()
-    gref = selector.ref_backward(p, x.cpu().numpy().astype(np.float64), dy.cpu().numpy().astype(np.float64), 6, 32, 6)
+    gref = selector.ref_backward(p, x.cpu().numpy().astype(np.float64), dy.cpu().numpy().astype(np.float64), 7, 32, 6)
     err = np.abs(g - gref).max() / np.abs(gref).max()
     say(f"[mlp] max rel gradient error vs FP64 reference {err:.2e}")
     assert err < 1e-4
-    # one Adam step vs its definition
-    m0 = np.zeros_like(p)
-    v0 = np.zeros_like(p)
-    net.adam(lr=1e-2)
+    # one Adam step with the L2 term vs its definition
+    wd = 1e-2
+    net.adam(lr=1e-2, weight_decay=wd)
     torch.cuda.synchronize()
-    m1 = 0.1 * g
-    v1 = 0.001 * g * g
+    gd = g + wd * p
+    m1 = 0.1 * gd
+    v1 = 0.001 * gd * gd
     pref = p - 1e-2 * (m1 / 0.1) / (np.sqrt(v1 / 0.001) + 1e-8)
     assert np.allclose(net.params.cpu().numpy(), pref, rtol=1e-4, atol=1e-6)
-    assert np.all(m0 == 0) and np.all(v0 == 0)
 
 
 def test_autotuner_picks_fastest_and_is_exact():
@@ -67,28 +66,33 @@ def test_autotuner_picks_fastest_and_is_exact():
 
 
 def test_selector_beats_choosing_without_it():
-    """Train on two thirds of the stored sweep (every shape whose index is not 0 mod 3),
-    evaluate on the held-out third: mean regret against the exhaustive autotuner must be
-    lower than always taking the library default launch and lower than the paper's
-    analytic tensor-vs-quadrature rule."""
+    """Three-fold cross-validation over the stored sweep (fold k holds out the shapes whose
+    index is k mod 3, so every shape is judged once by a network that never saw it): the
+    mean regret against the exhaustive autotuner must be lower than always taking the
+    library default launch and lower than the paper's analytic tensor-vs-quadrature rule."""
     require_gpu()
     if not os.path.exists(SWEEP):
         pytest.skip("no stored sweep")
     recs = tune.load_sweep(SWEEP)
-    train = [r for i, r in enumerate(recs) if i % 3 != 0]
-    test = [r for i, r in enumerate(recs) if i % 3 == 0]
-    sel = selector.Selector(n_hidden=64, seed=0)
-    loss = sel.fit(train, epochs=3000, lr=3e-3)
-    choice = sel.choose(test)
-    r_mlp = selector.regret(test, choice)
-    r_fixed = selector.regret(test, [0] * len(test))
-    r_heur = selector.regret(test, [selector.heuristic_choice(r["kind"], r["dim"], r["degree"]) for r in test])
-    t_best = sum(min(r["ms"]) for r in test)
-    t_mlp = sum(r["ms"][c] for r, c in zip(test, choice))
-    t_fixed = sum(r["ms"][0] for r in test)
-    say(f"[selector] train loss {loss:.4f}; held-out mean regret: mlp {r_mlp.mean():.3f} "
-        f"fixed {r_fixed.mean():.3f} heuristic {r_heur.mean():.3f}; total ms best {t_best:.3f} "
-        f"mlp {t_mlp:.3f} fixed {t_fixed:.3f}")
+    held, choice = [], []
+    for k in range(3):
+        train = [r for i, r in enumerate(recs) if i % 3 != k]
+        test = [r for i, r in enumerate(recs) if i % 3 == k]
+        sel = selector.Selector(n_hidden=64, seed=k)
+        loss = sel.fit(train, epochs=3000, lr=3e-3)
+        held += test
+        choice += sel.choose(test)
+        say(f"[selector] fold {k}: train loss {loss:.4f}")
+    r_mlp = selector.regret(held, choice)
+    r_fixed = selector.regret(held, [0] * len(held))
+    r_heur = selector.regret(held, [selector.heuristic_choice(r["kind"], r["dim"], r["degree"]) for r in held])
+    t_best = sum(min(r["ms"]) for r in held)
+    t_mlp = sum(r["ms"][c] for r, c in zip(held, choice))
+    t_fixed = sum(r["ms"][0] for r in held)
+    t_heur = sum(r["ms"][selector.heuristic_choice(r["kind"], r["dim"], r["degree"])] for r in held)
+    say(f"[selector] held-out mean regret: mlp {r_mlp.mean():.3f} fixed default {r_fixed.mean():.3f} "
+        f"analytic rule {r_heur.mean():.3f}; total ms: exhaustive {t_best:.3f} mlp {t_mlp:.3f} "
+        f"fixed {t_fixed:.3f} analytic {t_heur:.3f}")
     assert r_mlp.mean() < r_fixed.mean()
     assert r_mlp.mean() < r_heur.mean()
 
