@@ -84,7 +84,7 @@ def cpu_baseline(wl, out_fn, seconds, np):
     import oracle
 
     threads = oracle.max_threads()
-    calib = min(500, wl.cells)
+    calib = min(4096, wl.cells)
 
     def coeffs(n):
         return None if wl.coeffs is None else np.ascontiguousarray(wl.coeffs[:, :n])
@@ -92,7 +92,7 @@ def cpu_baseline(wl, out_fn, seconds, np):
     t = time.perf_counter()
     oracle.tabulate(wl.kind, wl.dim, wl.degree, wl.coords[:, :calib], coeffs(calib))
     dt = time.perf_counter() - t
-    sample = int(min(65536, wl.cells, max(calib, calib * seconds / max(dt, 1e-6))))
+    sample = int(min(wl.cells, max(calib, calib * seconds / max(dt, 1e-6))))
     sub = np.ascontiguousarray(wl.coords[:, :sample])
     t = time.perf_counter()
     ref = oracle.tabulate(wl.kind, wl.dim, wl.degree, sub, coeffs(sample))

@@ -476,13 +476,13 @@ int ffc_tabulate_tensor(const ffc_form* f, int64_t cells, const double* coords, 
 // one form's items.  Each launch has its own device copy of its items' descriptors.
 struct BatchLaunch {
     bool persistent = false;
-    int dim = 0, kind = 0, kmax = 0;  // persistent launches
+    int dim = 0, kind = 0, kmax = 0;  // persistent launches (FP64 or split BF16 per the batch)
     std::vector<ffc::BatchItem> items;
     ffc::BatchItem* d_items = nullptr;
     int32_t* d_unit_item = nullptr;  // tile launches: [units] item of each tile
     int64_t units = 0;               // tiles
     int waves = 16, mt = 1, grid = 0;  // tile launches: workgroup size and tile size 16*mt
-    size_t lds = 0, stage_cap = 0, head_cap = 0;
+    size_t lds = 0;
 };
 
 struct ffc_batch {
@@ -508,10 +508,12 @@ struct ffc_batch {
 };
 
 namespace {
-// Tile launches are grouped by workgroup size, tile size and LDS size class, so that each
-// kernel has the register count of its own tile and small-LDS items keep several
-// workgroups per CU.
-int lds_class(size_t bytes) { return bytes <= 40 * 1024 ? 0 : bytes <= 80 * 1024 ? 1 : 2; }
+// Tile launches are grouped by workgroup size, tile size and the number of workgroups per
+// CU that an item's LDS plan allows (1 .. 4), so that each kernel has the register count of
+// its own tile and no item runs at a lower occupancy than its own plan gives.
+int lds_class(size_t bytes) {
+    return static_cast<int>(std::min<size_t>(4, (160 * 1024) / std::max<size_t>(bytes, 1)));
+}
 }  // namespace
 
 int ffc_batch_create(int32_t n, const ffc_form* const* forms, const int64_t* cells, const double* const* coords,
@@ -570,7 +572,16 @@ int ffc_batch_create(int32_t n, const ffc_form* const* forms, const int64_t* cel
         std::copy(f->gpiece, f->gpiece + 6, it.gpiece);
         const bool aligned = (reinterpret_cast<uintptr_t>(outs[i]) & 15u) == 0;
         const ffc::LdsPlan p16 = ffc::plan_lds(d, f->desc.kind, 16, f->rt.n_I, f->rt.n_alpha, 0, false, ffc::kLdsBudget);
-        if (!bf && f->pwaves == 16 && aligned && p16.staged &&
+        if (bf && f->bpersistent && aligned) {
+            const ffc::LdsPlan pb =
+                ffc::plan_bf16_persistent(d, f->desc.kind, f->ptile, f->rt.n_I, f->n_tiles, f->kpad, f->n_seg);
+            it.kmax = f->pkmax;
+            it.mt = f->ptile / 16;
+            it.stage_bytes = pb.stage_bytes;
+            it.head_bytes = pb.head_bytes;
+            amap_doubles += cells[i] * (1 + d * d);
+            pgroups[f].push_back(it);
+        } else if (!bf && f->pwaves == 16 && aligned && p16.staged &&
             (1 + d * d + f->rt.n_coeff) * 16 <= 64 * (16 - ffc::kIoWaves)) {
             it.kmax = f->pkmax;
             it.p = ffc::PersistArgs{f->d_woff, f->d_wave_b, f->d_wave_word, f->d_wave_mask, f->d_zero, f->n_zero};
@@ -584,7 +595,9 @@ int ffc_batch_create(int32_t n, const ffc_form* const* forms, const int64_t* cel
             const ffc::LdsPlan pl = ffc::plan_lds(d, f->desc.kind, ct, f->rt.n_I, f->rt.n_alpha, f->kpad, bf,
                                                   ffc::kLdsBudget);
             it.staged = pl.staged && aligned;
-            const size_t lds = (it.staged ? pl.stage_bytes : 0) + pl.head_bytes + pl.g_bytes;
+            it.stage_bytes = it.staged ? pl.stage_bytes : 0;
+            it.head_bytes = pl.head_bytes;
+            const size_t lds = it.stage_bytes + pl.head_bytes + pl.g_bytes;
             tgroups[(f->waves << 8) | (it.mt << 4) | lds_class(lds)].push_back(it);
         }
     }
@@ -600,18 +613,21 @@ int ffc_batch_create(int32_t n, const ffc_form* const* forms, const int64_t* cel
         L.dim = L.items[0].dim;
         L.kind = L.items[0].kind;
         L.kmax = L.items[0].kmax;
-        const ffc::LdsPlan p16 = ffc::plan_lds(L.dim, L.kind, 16, L.items[0].n_I, L.items[0].n_alpha, 0, false,
-                                               ffc::kLdsBudget);
-        L.lds = p16.total;
+        L.mt = bf16 ? L.items[0].mt : 1;
+        const int ct = 16 * L.mt;
+        L.lds = bf16 ? ffc::plan_bf16_persistent(L.dim, L.kind, ct, L.items[0].n_I, L.items[0].n_tiles,
+                                                 L.items[0].kpad, L.items[0].n_seg).total
+                     : ffc::plan_lds(L.dim, L.kind, 16, L.items[0].n_I, L.items[0].n_alpha, 0, false,
+                                     ffc::kLdsBudget).total;
         for (auto& it : L.items) {
             it.unit_begin = L.units;
-            L.units += (it.cells + 15) / 16;
+            L.units += (it.cells + ct - 1) / ct;
             it.amap = b->d_amap + amap_off;
             b->geometry.push_back({it.dim, it.cells, it.coords, b->d_amap + amap_off});
             amap_off += it.cells * (1 + it.dim * it.dim);
         }
-        const int per_cu = std::max(1, std::min(2, static_cast<int>((160 * 1024) / std::max<size_t>(L.lds, 1))));
-        L.grid = static_cast<int>(std::min<int64_t>(static_cast<int64_t>(prop.multiProcessorCount) * per_cu, L.units));
+        // one 1024-thread workgroup per CU (the register file holds one)
+        L.grid = static_cast<int>(std::min<int64_t>(prop.multiProcessorCount, L.units));
         b->launches.push_back(std::move(L));
     }
     for (auto& kv : tgroups) {
@@ -620,19 +636,15 @@ int ffc_batch_create(int32_t n, const ffc_form* const* forms, const int64_t* cel
         L.mt = (kv.first >> 4) & 15;
         L.items = kv.second;
         std::vector<int32_t> unit_item;
-        size_t g_cap = 0;
         for (size_t i = 0; i < L.items.size(); ++i) {
             ffc::BatchItem& it = L.items[i];
             const int ct = 16 * it.mt;
             const ffc::LdsPlan pl = ffc::plan_lds(it.dim, it.kind, ct, it.n_I, it.n_alpha, it.kpad, bf16,
                                                   ffc::kLdsBudget);
-            if (it.staged) L.stage_cap = std::max(L.stage_cap, pl.stage_bytes);
-            L.head_cap = std::max(L.head_cap, ffc::batch_head_bytes(it.dim, it.kind, ct));
-            g_cap = std::max(g_cap, pl.g_bytes);
+            L.lds = std::max(L.lds, it.stage_bytes + it.head_bytes + pl.g_bytes);
             it.unit_begin = static_cast<int64_t>(unit_item.size());
             unit_item.insert(unit_item.end(), static_cast<size_t>((it.cells + ct - 1) / ct), static_cast<int32_t>(i));
         }
-        L.lds = L.stage_cap + L.head_cap + g_cap;
         if (L.lds > ffc::kLdsBudget) return fail(FFC_E_UNSUPPORTED, "batch tile does not fit LDS");
         L.units = static_cast<int64_t>(unit_item.size());
         if (L.units > INT32_MAX) return fail(FFC_E_UNSUPPORTED, "too many tiles in one batch launch");
@@ -655,11 +667,11 @@ int ffc_batch_run(ffc_batch* b) {
     }
     for (const auto& L : b->launches) {
         hipError_t e = L.persistent
-                           ? ffc::launch_batch_persistent(L.dim, L.kind, L.kmax, L.d_items,
+                           ? ffc::launch_batch_persistent(L.dim, L.kind, L.kmax, b->nseg, L.mt, L.d_items,
                                                           static_cast<int>(L.items.size()), L.units, L.grid, L.lds,
                                                           b->stream)
                            : ffc::launch_batch_tiles(L.d_items, L.d_unit_item, L.units, L.waves, L.mt, b->nseg,
-                                                     L.lds, L.stage_cap, L.head_cap, b->stream);
+                                                     L.lds, b->stream);
         if (e != hipSuccess) return hip_fail(e, "batch kernel launch");
     }
     return FFC_OK;

@@ -110,7 +110,7 @@ struct BatchItem {
     int32_t dim, kind, n_I, n_alpha, n_tiles, kpad, n_seg, n_coeff;
     int32_t mt, staged;     // tile items: cell tile 16*mt, output rows staged in LDS
     int32_t kmax, reserved; // persistent items: register steps per wave
-    size_t stage_bytes, head_bytes;  // persistent items: LDS plan
+    size_t stage_bytes, head_bytes;  // LDS plan: staged rows (0 = direct stores), map + coefficients
     const int32_t* koff;
     const uint32_t* apack;
     const int32_t* entry;
@@ -122,15 +122,15 @@ struct BatchItem {
 };
 
 // Tile launch over items of one tile size (16*mt cells): grid = total tiles, unit_item[u] =
-// item of tile u; nseg 0 = FP64, 3 / 6 = split BF16 with that many products; LDS =
-// stage_cap + head_cap + G.
+// item of tile u; nseg 0 = FP64, 3 / 6 = split BF16 with that many products; each item's LDS
+// plan (stage_bytes, head_bytes, G) fits in `lds`.
 hipError_t launch_batch_tiles(const BatchItem* items, const int32_t* unit_item, int64_t units, int waves, int mt,
-                              int nseg, size_t lds, size_t stage_cap, size_t head_cap, hipStream_t stream);
-// Persistent launch over the items of one form (items in unit_begin order, `tiles` 16-cell
+                              int nseg, size_t lds, hipStream_t stream);
+// Persistent launch over the items of one form (items in unit_begin order, `tiles` cell
 // tiles in all): `grid` workgroups of 16 waves, workgroup w runs tiles w, w + grid, ...
-hipError_t launch_batch_persistent(int dim, int kind, int kmax, const BatchItem* items, int n_items, int64_t tiles,
-                                   int grid, size_t lds, hipStream_t stream);
-// head part of a tile launch's LDS: affine map and coefficients of one tile
-size_t batch_head_bytes(int dim, int kind, int tile_cells);
+// nseg 0: FP64 kernel (16-cell tiles, kmax register steps); nseg 3 / 6: split-BF16 kernel
+// (16*mt-cell tiles, kmax = its register steps).
+hipError_t launch_batch_persistent(int dim, int kind, int kmax, int nseg, int mt, const BatchItem* items, int n_items,
+                                   int64_t tiles, int grid, size_t lds, hipStream_t stream);
 
 }  // namespace ffc

@@ -580,8 +580,9 @@ struct OneMesh {
     }
 };
 
-// Tile source of a batch launch: the tiles of items[0], then of items[1], ... (items in
-// unit_begin order); queried with increasing g, so a cursor advances over the items.
+// Tile source of a batch launch: the CT-cell tiles of items[0], then of items[1], ... (items
+// in unit_begin order); queried with increasing g, so a cursor advances over the items.
+template <int CT>
 struct ItemCursor {
     const BatchItem* items;
     int n, idx;
@@ -592,7 +593,7 @@ struct ItemCursor {
             ++idx;
             const BatchItem& it = items[idx];
             begin = it.unit_begin;
-            end = begin + (it.cells + 15) / 16;
+            end = begin + (it.cells + CT - 1) / CT;
             base = MeshTile{as_global(it.amap), it.cells, as_global(it.coeffs), it.cells,
                             as_global(static_cast<double*>(it.out)), it.cells, 0};
         }
@@ -1107,21 +1108,18 @@ hipError_t launch_contract_bf16_persistent(int dim, int kind, int tile_cells, in
 // Tile launch: workgroup u runs tile u of the launch, cell tile 16*MT of item unit_item[u]
 // (one launch per tile size, so each kernel's register count is that of its own tile),
 // geometry computed in place (one lane per cell), then the FP64 or split-BF16 contraction of
-// the single-mesh kernel.  LDS: staged rows [stage_cap], affine map and coefficients
-// [head_cap], G tile.
+// the single-mesh kernel.  LDS per the item's own plan: staged rows [stage_bytes], affine
+// map and coefficients [head_bytes], G tile; the launch reserves the largest item plan.
 
-size_t batch_head_bytes(int dim, int kind, int tile_cells) {
-    return align16(static_cast<size_t>(1 + dim * dim + n_coeff_of(dim, kind)) * tile_cells * sizeof(double));
-}
 
 template <int D, int KIND, int MT, int NSEG>
-__device__ __forceinline__ void batch_tile(const BatchItem& it, int64_t c0, unsigned char* smem, size_t stage_cap,
-                                           size_t head_cap) {
+__device__ __forceinline__ void batch_tile(const BatchItem& it, int64_t c0, unsigned char* smem) {
     constexpr int NC = FormTraits<KIND, D>::n_coeff;
     constexpr int CT = 16 * MT;
-    double* am = reinterpret_cast<double*>(smem + stage_cap);
+    // the item's own LDS plan: staged rows, affine map and coefficients, G tile
+    double* am = reinterpret_cast<double*>(smem + it.stage_bytes);
     double* cf = am + (1 + D * D) * CT;
-    unsigned char* g = smem + stage_cap + head_cap;
+    unsigned char* g = smem + it.stage_bytes + it.head_bytes;
     stage_tile_from_coords<D, NC>(as_global(it.coords), as_global(it.coeffs), it.cells, c0, CT, am, cf);
     __syncthreads();
     if constexpr (NSEG > 0) {
@@ -1139,46 +1137,43 @@ __device__ __forceinline__ void batch_tile(const BatchItem& it, int64_t c0, unsi
 
 template <int NSEG, int MT>
 __global__ __launch_bounds__(1024) void batch_tiles_kernel(const BatchItem* __restrict__ items,
-                                                           const int32_t* __restrict__ unit_item, size_t stage_cap,
-                                                           size_t head_cap) {
+                                                           const int32_t* __restrict__ unit_item) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     const int64_t u = blockIdx.x;
     const BatchItem& it = items[__builtin_amdgcn_readfirstlane(unit_item[u])];
     const int64_t c0 = (u - it.unit_begin) * 16 * MT;
     switch (it.dim * 8 + it.kind) {
-    case 16 + K_MASS: batch_tile<2, K_MASS, MT, NSEG>(it, c0, smem_raw, stage_cap, head_cap); break;
-    case 16 + K_LAPLACE: batch_tile<2, K_LAPLACE, MT, NSEG>(it, c0, smem_raw, stage_cap, head_cap); break;
-    case 16 + K_WLAPLACE: batch_tile<2, K_WLAPLACE, MT, NSEG>(it, c0, smem_raw, stage_cap, head_cap); break;
-    case 16 + K_ELASTICITY: batch_tile<2, K_ELASTICITY, MT, NSEG>(it, c0, smem_raw, stage_cap, head_cap); break;
-    case 16 + K_NS: batch_tile<2, K_NS, MT, NSEG>(it, c0, smem_raw, stage_cap, head_cap); break;
-    case 24 + K_MASS: batch_tile<3, K_MASS, MT, NSEG>(it, c0, smem_raw, stage_cap, head_cap); break;
-    case 24 + K_LAPLACE: batch_tile<3, K_LAPLACE, MT, NSEG>(it, c0, smem_raw, stage_cap, head_cap); break;
-    case 24 + K_WLAPLACE: batch_tile<3, K_WLAPLACE, MT, NSEG>(it, c0, smem_raw, stage_cap, head_cap); break;
-    case 24 + K_ELASTICITY: batch_tile<3, K_ELASTICITY, MT, NSEG>(it, c0, smem_raw, stage_cap, head_cap); break;
-    default: batch_tile<3, K_NS, MT, NSEG>(it, c0, smem_raw, stage_cap, head_cap); break;
+    case 16 + K_MASS: batch_tile<2, K_MASS, MT, NSEG>(it, c0, smem_raw); break;
+    case 16 + K_LAPLACE: batch_tile<2, K_LAPLACE, MT, NSEG>(it, c0, smem_raw); break;
+    case 16 + K_WLAPLACE: batch_tile<2, K_WLAPLACE, MT, NSEG>(it, c0, smem_raw); break;
+    case 16 + K_ELASTICITY: batch_tile<2, K_ELASTICITY, MT, NSEG>(it, c0, smem_raw); break;
+    case 16 + K_NS: batch_tile<2, K_NS, MT, NSEG>(it, c0, smem_raw); break;
+    case 24 + K_MASS: batch_tile<3, K_MASS, MT, NSEG>(it, c0, smem_raw); break;
+    case 24 + K_LAPLACE: batch_tile<3, K_LAPLACE, MT, NSEG>(it, c0, smem_raw); break;
+    case 24 + K_WLAPLACE: batch_tile<3, K_WLAPLACE, MT, NSEG>(it, c0, smem_raw); break;
+    case 24 + K_ELASTICITY: batch_tile<3, K_ELASTICITY, MT, NSEG>(it, c0, smem_raw); break;
+    default: batch_tile<3, K_NS, MT, NSEG>(it, c0, smem_raw); break;
     }
 }
 
 template <int NSEG>
 static hipError_t launch_batch_tiles_n(int mt, unsigned grid, unsigned block, size_t lds, hipStream_t s,
-                                       const BatchItem* items, const int32_t* unit_item, size_t stage_cap,
-                                       size_t head_cap) {
+                                       const BatchItem* items, const int32_t* unit_item) {
     switch (mt) {
-    case 1: return launch_lds(batch_tiles_kernel<NSEG, 1>, grid, block, lds, s, items, unit_item, stage_cap, head_cap);
-    case 2: return launch_lds(batch_tiles_kernel<NSEG, 2>, grid, block, lds, s, items, unit_item, stage_cap, head_cap);
-    default:
-        return launch_lds(batch_tiles_kernel<NSEG, 4>, grid, block, lds, s, items, unit_item, stage_cap, head_cap);
+    case 1: return launch_lds(batch_tiles_kernel<NSEG, 1>, grid, block, lds, s, items, unit_item);
+    case 2: return launch_lds(batch_tiles_kernel<NSEG, 2>, grid, block, lds, s, items, unit_item);
+    default: return launch_lds(batch_tiles_kernel<NSEG, 4>, grid, block, lds, s, items, unit_item);
     }
 }
 
 hipError_t launch_batch_tiles(const BatchItem* items, const int32_t* unit_item, int64_t units, int waves, int mt,
-                              int nseg, size_t lds, size_t stage_cap, size_t head_cap, hipStream_t stream) {
+                              int nseg, size_t lds, hipStream_t stream) {
     if (units <= 0) return hipSuccess;
     const unsigned grid = static_cast<unsigned>(units);
     const unsigned block = 64u * waves;
-    if (nseg == 3) return launch_batch_tiles_n<3>(mt, grid, block, lds, stream, items, unit_item, stage_cap, head_cap);
-    if (nseg == 6) return launch_batch_tiles_n<6>(mt, grid, block, lds, stream, items, unit_item, stage_cap, head_cap);
-    return launch_batch_tiles_n<0>(mt, grid, block, lds, stream, items, unit_item, stage_cap, head_cap);
+    if (nseg == 3) return launch_batch_tiles_n<3>(mt, grid, block, lds, stream, items, unit_item);
+    if (nseg == 6) return launch_batch_tiles_n<6>(mt, grid, block, lds, stream, items, unit_item);
+    return launch_batch_tiles_n<0>(mt, grid, block, lds, stream, items, unit_item);
 }
 
 // Persistent launch over the items of one form: the 16-cell tiles of all items form one
@@ -1201,8 +1196,54 @@ __global__ __launch_bounds__(1024) void batch_persistent_kernel(const BatchItem*
     A.head_bytes = f.head_bytes;
     const PersistArgs P{as_global(f.p.woff), as_global(f.p.wave_b), as_global(f.p.wave_word),
                         as_global(f.p.wave_mask), as_global(f.p.zero_entries), f.p.n_zero};
-    ItemCursor src{items, n_items, -1, 0, 0, MeshTile{}};
+    ItemCursor<16> src{items, n_items, -1, 0, 0, MeshTile{}};
     persistent_tiles<D, KIND, KMAX, kIoSlots>(A, P, src, blockIdx.x, total_tiles, gridDim.x, smem_raw);
+}
+
+template <int D, int KIND, int NSEG, int KS, int MT>
+__global__ __launch_bounds__(1024) void batch_persistent_bf16_kernel(const BatchItem* __restrict__ items, int n_items,
+                                                                     int64_t total_tiles) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    const BatchItem& f = items[0];  // every item of the launch has the same form
+    ContractArgs A{};
+    A.n_I = f.n_I;
+    A.n_tiles = f.n_tiles;
+    A.kpad = f.kpad;
+    A.n_seg = f.n_seg;
+    for (int i = 0; i < 6; ++i) A.gpiece[i] = f.gpiece[i];
+    A.bb = as_global(f.bb);
+    A.stage_bytes = f.stage_bytes;
+    A.head_bytes = f.head_bytes;
+    ItemCursor<16 * MT> src{items, n_items, -1, 0, 0, MeshTile{}};
+    persistent_tiles_bf16<D, KIND, NSEG, KS, MT>(A, src, blockIdx.x, total_tiles, gridDim.x, smem_raw);
+}
+
+template <int D, int KIND, int NSEG, int MT>
+static hipError_t launch_batch_bf16_m(int ks, const BatchItem* items, int n_items, int64_t tiles, int grid, size_t lds,
+                                      hipStream_t s) {
+    if (ks <= 8)
+        return launch_lds(batch_persistent_bf16_kernel<D, KIND, NSEG, 8, MT>, grid, 1024u, lds, s, items, n_items,
+                          tiles);
+    if constexpr (MT == 1 || NSEG == 3)
+        return launch_lds(batch_persistent_bf16_kernel<D, KIND, NSEG, 16, MT>, grid, 1024u, lds, s, items, n_items,
+                          tiles);
+    return hipErrorInvalidValue;
+}
+
+template <int D, int NSEG>
+static hipError_t launch_batch_bf16_d(int kind, int mt, int ks, const BatchItem* items, int n_items, int64_t tiles,
+                                      int grid, size_t lds, hipStream_t s) {
+#define FFC_BATCH_BF16_KIND(K)                                                                \
+    return mt == 1 ? launch_batch_bf16_m<D, K, NSEG, 1>(ks, items, n_items, tiles, grid, lds, s) \
+                   : launch_batch_bf16_m<D, K, NSEG, 2>(ks, items, n_items, tiles, grid, lds, s)
+    switch (kind) {
+    case K_MASS: FFC_BATCH_BF16_KIND(K_MASS);
+    case K_LAPLACE: FFC_BATCH_BF16_KIND(K_LAPLACE);
+    case K_WLAPLACE: FFC_BATCH_BF16_KIND(K_WLAPLACE);
+    case K_ELASTICITY: FFC_BATCH_BF16_KIND(K_ELASTICITY);
+    default: FFC_BATCH_BF16_KIND(K_NS);
+    }
+#undef FFC_BATCH_BF16_KIND
 }
 
 template <int D, int KIND>
@@ -1227,10 +1268,16 @@ static hipError_t launch_batch_persistent_d(int kind, int kmax, const BatchItem*
     }
 }
 
-hipError_t launch_batch_persistent(int dim, int kind, int kmax, const BatchItem* items, int n_items, int64_t tiles,
-                                   int grid, size_t lds, hipStream_t stream) {
+hipError_t launch_batch_persistent(int dim, int kind, int kmax, int nseg, int mt, const BatchItem* items, int n_items,
+                                   int64_t tiles, int grid, size_t lds, hipStream_t stream) {
     if (tiles <= 0 || n_items <= 0) return hipSuccess;
     if (grid > tiles) grid = static_cast<int>(tiles);
+    if (nseg == 3)
+        return dim == 2 ? launch_batch_bf16_d<2, 3>(kind, mt, kmax, items, n_items, tiles, grid, lds, stream)
+                        : launch_batch_bf16_d<3, 3>(kind, mt, kmax, items, n_items, tiles, grid, lds, stream);
+    if (nseg == 6)
+        return dim == 2 ? launch_batch_bf16_d<2, 6>(kind, mt, kmax, items, n_items, tiles, grid, lds, stream)
+                        : launch_batch_bf16_d<3, 6>(kind, mt, kmax, items, n_items, tiles, grid, lds, stream);
     return dim == 2 ? launch_batch_persistent_d<2>(kind, kmax, items, n_items, tiles, grid, lds, stream)
                     : launch_batch_persistent_d<3>(kind, kmax, items, n_items, tiles, grid, lds, stream);
 }
