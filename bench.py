@@ -295,14 +295,20 @@ def bench_batch(args, torch, np):
     from paper_1112_0402_amd import meshgen
     from paper_1112_0402_amd.forms import Batch, Form
 
+    from paper_1112_0402_amd import tune
+
     precision = args.precision
     wls = meshgen.config4()
-    forms = {}
-    for w in wls:
-        key = (w.kind, w.dim, w.degree)
-        if key not in forms:
-            forms[key] = Form(w.kind, w.dim, w.degree, precision=precision)
-    fl = [forms[(w.kind, w.dim, w.degree)] for w in wls]
+    sel = None
+    if args.launch == "selector":
+        if precision != "fp64":
+            raise SystemExit("the selector is trained on the FP64 sweep; use --launch autotune for split modes")
+        from paper_1112_0402_amd import selector as selmod
+
+        sel = selmod.Selector(seed=0)
+        sel.fit(tune.load_sweep(os.path.join(ROOT, "paper_1112_0402_amd", "data", "sweep_mi355x_fp64.jsonl")))
+    fl, picks = tune.batch_forms(wls, precision, args.launch, db=tune.TuneDB(None), selector=sel)
+    forms = {id(f): f for f in fl}
     X = [torch.from_numpy(w.coords).cuda() for w in wls]
     C = [None if w.coeffs is None else torch.from_numpy(w.coeffs).cuda() for w in wls]
     outs = [f.empty_out(w.cells) for f, w in zip(fl, wls)]
@@ -346,7 +352,9 @@ def bench_batch(args, torch, np):
         "dtype": "f64" if precision == "fp64" else precision + "->f32",
         "data": "synthetic",
         "config": {"workload": "batch64_mixed", "meshes": len(wls), "cells": cells, "precision": precision,
-                   "variants": len(forms), "work_units": b.work_units, "launches": b.launches},
+                   "variants": len({(w.kind, w.dim, w.degree) for w in wls}), "forms": len(forms),
+                   "launch_choice": args.launch, "candidates_picked": {str(k): picks.count(k) for k in sorted(set(picks))},
+                   "work_units": b.work_units, "launches": b.launches},
         "roofline": {"kernel": "batch_persistent_kernel + batch_tiles_kernel", "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gbs / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes_per_launch": byt,
                      "ms_per_launch": ms},
@@ -369,6 +377,9 @@ def main() -> int:
     ap.add_argument("--tile-cells", type=int, default=0)
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--persistent", type=int, default=0, help="0 auto, 1 on, -1 off")
+    ap.add_argument("--launch", default="default", choices=["default", "autotune", "selector"],
+                    help="batch: launch shape per mesh from the library defaults, the exhaustive autotuner, or "
+                         "the selector trained on the stored sweep")
     ap.add_argument("--geometry", default="default", choices=["default", "pass", "fused"],
                     help="affine map in a separate pass or inside the contraction")
     ap.add_argument("--tile-window", type=int, default=0,

@@ -133,6 +133,53 @@ def autotune(kind, dim, degree, precision, X, C, db: TuneDB | None = None, reps:
     return best, candidates(precision)[best], times
 
 
+def batch_forms(workloads, precision="fp64", choice="default", db: TuneDB | None = None, selector=None, reps=5):
+    """One form per batch item (a Batch groups items by launch shape): the library default
+    launch (`choice="default"`), the exhaustive autotuner's winner on the item's own mesh,
+    cached in `db` per (form, log2 cells) shape (`"autotune"`), or the trained selector's
+    pick (`"selector"`, FP64).  Batches run the tensor kernel, so the quadrature candidate
+    is excluded; items with the same form and launch share one Form."""
+    import torch
+
+    from .forms import Form
+
+    cands = candidates(precision)
+    tensor_idx = [i for i, c in enumerate(cands) if c["kernel"] == "tensor"]
+    forms, out, picks = {}, [], []
+    for w in workloads:
+        if choice == "default":
+            j = 0
+        elif choice == "autotune":
+            hit = db.lookup(w.kind, w.dim, w.degree, precision, w.cells) if db is not None else None
+            key = shape_key(w.kind, w.dim, w.degree, precision, w.cells)
+            if hit is not None and db is not None and key in db.db and "tensor_candidate" in db.db[key]:
+                j = db.db[key]["tensor_candidate"]
+            else:
+                X = torch.from_numpy(w.coords).cuda()
+                C = None if w.coeffs is None else torch.from_numpy(w.coeffs).cuda()
+                fl = [make_form(w.kind, w.dim, w.degree, precision, cands[i]) for i in tensor_idx]
+                t = measure_all(fl, X, C, reps)
+                for f in fl:
+                    f.close()
+                j = tensor_idx[int(np.argmin(t))]
+                if db is not None:
+                    db.put(key, {"candidate": j, "tensor_candidate": j, "config": cands[j], "ms": min(t)})
+        elif choice == "selector":
+            info = Form(w.kind, w.dim, w.degree, precision=precision).info
+            rec = {"kind": w.kind, "dim": w.dim, "degree": w.degree, "cells": w.cells, "n_I": info["n_entries"],
+                   "n_alpha": info["n_alpha"], "ms": [1.0] * len(cands)}
+            pred = selector.predict_rel([rec])[0]
+            j = min(tensor_idx, key=lambda i: pred[i])
+        else:
+            raise ValueError(f"unknown choice {choice!r}")
+        key = (w.kind, w.dim, w.degree, j)
+        if key not in forms:
+            forms[key] = make_form(w.kind, w.dim, w.degree, precision, cands[j])
+        out.append(forms[key])
+        picks.append(j)
+    return out, picks
+
+
 def sweep_shapes(variants, cells_list):
     return [(k, d, q, c) for (k, d, q) in variants for c in cells_list]
 

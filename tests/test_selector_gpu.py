@@ -118,3 +118,31 @@ def test_selected_launch_is_exact():
         torch.cuda.synchronize()
         ref = oracle.tabulate(kind, dim, q, wl.coords, wl.coeffs)
         assert rel_fro(out.cpu().numpy(), ref)[0] <= 1e-12, (kind, c)
+
+
+@pytest.mark.parametrize("choice", ["autotune", "selector"])
+def test_tuned_batch_is_exact(choice):
+    """A batch whose per-mesh launch shapes come from the autotuner (or the selector) groups
+    the items by shape and still equals the oracle."""
+    require_gpu()
+    from paper_1112_0402_amd.forms import Batch
+
+    if choice == "selector" and not os.path.exists(SWEEP):
+        pytest.skip("no stored sweep")
+    wls = meshgen.config4(n_meshes=16, scale=0.01)
+    sel = None
+    if choice == "selector":
+        sel = selector.Selector(seed=2)
+        sel.fit(tune.load_sweep(SWEEP), epochs=1000)
+    fl, picks = tune.batch_forms(wls, "fp64", choice, db=tune.TuneDB(None), selector=sel)
+    say(f"[tuned batch] {choice}: picks {picks}")
+    assert all(tune.CANDIDATES_FP64[j]["kernel"] == "tensor" for j in picks)
+    X = [to_dev(w.coords) for w in wls]
+    C = [to_dev(w.coeffs) for w in wls]
+    outs = [f.empty_out(w.cells) for f, w in zip(fl, wls)]
+    b = Batch(fl, X, C, outs)
+    b.run()
+    torch.cuda.synchronize()
+    for w, o in zip(wls, outs):
+        ref = oracle.tabulate(w.kind, w.dim, w.degree, w.coords, w.coeffs)
+        assert rel_fro(o.cpu().numpy(), ref)[0] <= 1e-12, w.name
