@@ -363,12 +363,79 @@ def bench_batch(args, torch, np):
     }
 
 
+def bench_assembly(args, torch, np):
+    """Global assembly of the elasticity workload's element tensors into CSR (the insertion
+    step after the hot path): tabulation + assembly per step, the assembly kernel timed on
+    its own; the CPU baseline is the scipy assembly oracle on a sample."""
+    from paper_1112_0402_amd import meshgen
+    from paper_1112_0402_amd.forms import Assembly, Form
+
+    wl = meshgen.config2()
+    dm, ng = meshgen.lagrange_dofmap(wl.meta["cells"], 2, 3)
+    cells, n = dm.shape
+    stream = torch.cuda.Stream()
+    form = Form("elasticity", 3, 2, stream=stream)
+    X = torch.from_numpy(wl.coords).cuda()
+    T = form.empty_out(cells)
+    t0 = time.perf_counter()
+    asm = Assembly(dm, ng, stream=stream)
+    symbolic_s = time.perf_counter() - t0
+    vals = torch.empty(asm.nnz, dtype=torch.float64, device="cuda")
+    with torch.cuda.stream(stream):
+        for _ in range(max(1, args.warmup)):
+            form.tabulate(X, None, out=T)
+            asm.assemble(T, values=vals)
+        torch.cuda.synchronize()
+        asm_ms = timed(lambda: asm.assemble(T, values=vals), args.steps, stream, torch)
+        step_ms = timed(lambda: (form.tabulate(X, None, out=T), asm.assemble(T, values=vals)), args.steps, stream,
+                        torch)
+    entries = cells * n * n
+    # algorithmic bytes of one assembly: element tensors and their CSR indices read once,
+    # every value written once, the per-row lists (row and slot offsets, slots) read once
+    byt = entries * (8 + 4) + asm.nnz * 8 + cells * n * 4 + ng * 16
+    gbs = byt / (asm_ms * 1e-3) / 1e9
+    result = {
+        "metric": "assembled element-tensor entries/s (global CSR assembly after tabulation)",
+        "value": entries / (asm_ms * 1e-3),
+        "unit": "entries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": step_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "assembly_elasticity3d_p2_750k", "cells": cells, "dofs": ng, "nnz": asm.nnz,
+                   "entries": entries, "symbolic_host_s": symbolic_s,
+                   "step": "tabulation (persistent FP64 contraction) + assembly"},
+        "roofline": {"kernel": "gather_rows_kernel", "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_launch": byt, "ms_per_launch": asm_ms},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        from oracle.assemble import assemble
+
+        sample = min(cells, 100_000)
+        Th = T[:sample].cpu().numpy()
+        t = time.perf_counter()
+        assemble(Th, dm[:sample], ng)
+        dt = time.perf_counter() - t
+        result["cpu_baseline"] = {"value": sample * n * n / dt, "unit": "entries/s", "cores": 1, "kind": "oracle",
+                                  "sample": f"scipy COO->CSR assembly of the first {sample} cells' tensors, {dt:.1f} s"}
+        del oracle
+    return result
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="elasticity", choices=["elasticity", "poisson2d", "wlaplace", "batch"])
+    ap.add_argument("--workload", default="elasticity",
+                    choices=["elasticity", "poisson2d", "wlaplace", "batch", "assembly"])
     ap.add_argument("--precision", default="bf16x3", choices=["fp64", "bf16x3", "bf16x6"],
                     help="contraction arithmetic of the wlaplace and batch workloads")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target wall time of the oracle sample")
@@ -408,7 +475,12 @@ def main() -> int:
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_read": src.numel() * 8, "bytes_written": dst.numel() * 8}))
         return 0
-    result = bench_batch(args, torch, np) if args.workload == "batch" else bench_single(args, torch, np)
+    if args.workload == "batch":
+        result = bench_batch(args, torch, np)
+    elif args.workload == "assembly":
+        result = bench_assembly(args, torch, np)
+    else:
+        result = bench_single(args, torch, np)
     print(json.dumps(result), flush=True)
     return 0
 

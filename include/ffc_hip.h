@@ -195,6 +195,35 @@ int ffc_batch_run(ffc_batch* batch);
 int ffc_batch_info(const ffc_batch* batch, int64_t* total_cells, int64_t* work_units, int32_t* launches);
 void ffc_batch_destroy(ffc_batch* batch);
 
+/* Global assembly (Sec. 2.3: the element-by-element algorithm, Algorithm 2's insertion
+ * step): A = sum over cells K of P_K^T A^K P_K into a CSR matrix, with the same
+ * local-to-global map for test and trial functions.
+ *
+ * ffc_assembly_create: symbolic phase, once per mesh.  dofmap is a HOST array
+ * [cells][n_local] of global dof indices in [0, n_global) (local order = the element
+ * tensor's row/column order); the library builds the CSR pattern (row r = every dof sharing
+ * a cell with dof r, columns ascending) and the CSR index of every element-tensor entry, on
+ * the device of the current HIP context.  Fails with FFC_E_UNSUPPORTED if the pattern
+ * would have 2^31 entries or more.  `stream` (hipStream_t, NULL = default) is used by
+ * ffc_assemble.
+ * ffc_assembly_info: rows (= n_global) and nonzeros.
+ * ffc_assembly_pattern: copies the pattern to HOST arrays row_ptr [n_global + 1] (int64)
+ * and col_idx [nnz] (int32).
+ * ffc_assemble: numeric phase.  element_tensors: device [cells][n_local][n_local], FP64
+ * (tensor_bytes 8) or FP32 (4, the split modes' output), row = test function; values:
+ * device [nnz] FP64, overwritten, or added to if accumulate != 0.  Asynchronous on the
+ * stream; no allocation, no memset (graph-capturable).  Each matrix row is summed by one
+ * wave in a fixed order (cells ascending), without atomics: results are reproducible.
+ * n_local <= 64; rows of at most 1024 entries. */
+typedef struct ffc_assembly ffc_assembly;
+int ffc_assembly_create(int64_t cells, int32_t n_local, const int32_t* dofmap, int64_t n_global, void* stream,
+                        ffc_assembly** assembly);
+int ffc_assembly_info(const ffc_assembly* assembly, int64_t* n_rows, int64_t* nnz);
+int ffc_assembly_pattern(const ffc_assembly* assembly, int64_t* row_ptr, int32_t* col_idx);
+int ffc_assemble(ffc_assembly* assembly, const void* element_tensors, int32_t tensor_bytes, double* values,
+                 int32_t accumulate);
+void ffc_assembly_destroy(ffc_assembly* assembly);
+
 /* Kernel selector network.  A multilayer perceptron that predicts the log run time of each
  * candidate launch (tensor or quadrature kernel, launch shape) of a tabulation from its
  * features (form rank, degree, |i|, |alpha|, dimension, cells); the candidate with the

@@ -37,7 +37,7 @@ def build(verbose: bool = True) -> str:
     o = os.path.join(objdir, "reference_tensor.o")
     _run(["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-c", os.path.join(CSRC, "reference_tensor.cpp"), "-o", o])
     objs.append(o)
-    for src in ("kernels.hip", "mlp.hip", "capi.cpp"):
+    for src in ("kernels.hip", "mlp.hip", "assembly.hip", "capi.cpp"):
         o = os.path.join(objdir, src.split(".")[0] + ".o")
         extra = ["-x", "hip"] if src.endswith(".cpp") else []
         _run([HIPCC, *HIP_FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", o])

@@ -87,6 +87,14 @@ def lib():
     L.ffc_batch_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i32)]
     L.ffc_batch_destroy.argtypes = [vp]
     L.ffc_batch_destroy.restype = None
+    L.ffc_assembly_create.argtypes = [i64, i32, vp, i64, vp, ctypes.POINTER(vp)]
+    L.ffc_assembly_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.ffc_assembly_pattern.argtypes = [vp, vp, vp]
+    L.ffc_assemble.argtypes = [vp, vp, i32, vp, i32]
+    L.ffc_assembly_destroy.argtypes = [vp]
+    L.ffc_assembly_destroy.restype = None
+    for name in ("ffc_assembly_create", "ffc_assembly_info", "ffc_assembly_pattern", "ffc_assemble"):
+        getattr(L, name).restype = ctypes.c_int
     fp = ctypes.c_float
     L.ffc_mlp_param_count.argtypes = [i32, i32, i32]
     L.ffc_mlp_param_count.restype = i64

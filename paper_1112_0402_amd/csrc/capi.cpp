@@ -11,6 +11,7 @@
 
 #include "../../include/ffc_hip.h"
 #include "kernels.h"
+#include "assembly.h"
 #include "mlp.h"
 #include "reference_tensor.h"
 
@@ -686,6 +687,101 @@ int ffc_batch_info(const ffc_batch* b, int64_t* total_cells, int64_t* work_units
 }
 
 void ffc_batch_destroy(ffc_batch* b) { delete b; }
+
+// ------------------------------------------------------------------- assembly ----
+
+struct ffc_assembly {
+    int64_t cells = 0, n_global = 0, nnz = 0;
+    int n = 0, max_row = 0;
+    std::vector<int64_t> row_ptr;
+    std::vector<int32_t> col;
+    int32_t* d_pos = nullptr;       // [cells][n][n] CSR index of each element-tensor entry
+    int64_t* d_row_ptr = nullptr;   // [n_global + 1]
+    int64_t* d_slot_ptr = nullptr;  // [n_global + 1]
+    int32_t* d_slots = nullptr;     // [cells * n] element-tensor rows per matrix row
+    hipStream_t stream = nullptr;
+    ~ffc_assembly() {
+        for (void* p : {static_cast<void*>(d_pos), static_cast<void*>(d_row_ptr), static_cast<void*>(d_slot_ptr),
+                        static_cast<void*>(d_slots)})
+            if (p) (void)hipFree(p);
+    }
+};
+
+int ffc_assembly_create(int64_t cells, int32_t n_local, const int32_t* dofmap, int64_t n_global, void* stream,
+                        ffc_assembly** out) {
+    if (!out) return fail(FFC_E_INVALID, "assembly output pointer is NULL");
+    *out = nullptr;
+    if (cells < 0 || n_local <= 0 || n_global <= 0 || n_global > INT32_MAX)
+        return fail(FFC_E_INVALID, "bad assembly sizes");
+    if (n_local > 64) return fail(FFC_E_UNSUPPORTED, "at most 64 dofs per cell");
+    if (cells * n_local > INT32_MAX) return fail(FFC_E_UNSUPPORTED, "cells * n_local must be below 2^31");
+    if (cells > 0 && !dofmap) return fail(FFC_E_INVALID, "dofmap is NULL");
+    for (int64_t k = 0; k < cells * n_local; ++k)
+        if (dofmap[k] < 0 || dofmap[k] >= n_global) return fail(FFC_E_INVALID, "dofmap entry out of [0, n_global)");
+    int dev;
+    int rc = check_device(&dev);
+    if (rc) return rc;
+    std::unique_ptr<ffc_assembly> a(new ffc_assembly());
+    a->cells = cells;
+    a->n = n_local;
+    a->n_global = n_global;
+    a->stream = static_cast<hipStream_t>(stream);
+    std::vector<int64_t> slot_ptr;
+    std::vector<int32_t> slots;
+    if (!ffc::csr_pattern(cells, n_local, dofmap, n_global, &a->row_ptr, &a->col, &slot_ptr, &slots))
+        return fail(FFC_E_UNSUPPORTED, "assembled pattern has 2^31 entries or more");
+    a->nnz = a->row_ptr.back();
+    for (int64_t r = 0; r < n_global; ++r)
+        a->max_row = std::max<int>(a->max_row, static_cast<int>(a->row_ptr[r + 1] - a->row_ptr[r]));
+    if (a->max_row > 1024) return fail(FFC_E_UNSUPPORTED, "a matrix row longer than 1024 entries");
+    if (cells > 0) {
+        int32_t* d_dofmap = nullptr;
+        int32_t* d_col = nullptr;
+        std::vector<int32_t> dm(dofmap, dofmap + cells * n_local);
+        const size_t entries = static_cast<size_t>(cells) * n_local * n_local;
+        if ((rc = upload(dm, &d_dofmap)) || (rc = upload(a->row_ptr, &a->d_row_ptr)) || (rc = upload(a->col, &d_col)) ||
+            (rc = upload(slot_ptr, &a->d_slot_ptr)) || (rc = upload(slots, &a->d_slots))) {
+            (void)hipFree(d_dofmap), (void)hipFree(d_col);
+            return rc;
+        }
+        hipError_t e = hipMalloc(reinterpret_cast<void**>(&a->d_pos), entries * sizeof(int32_t));
+        if (e == hipSuccess)
+            e = ffc::scatter_positions(cells, n_local, d_dofmap, a->d_row_ptr, d_col, a->d_pos, a->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(a->stream);
+        (void)hipFree(d_dofmap), (void)hipFree(d_col);
+        if (e != hipSuccess) return hip_fail(e, "assembly symbolic phase");
+    }
+    *out = a.release();
+    return FFC_OK;
+}
+
+int ffc_assembly_info(const ffc_assembly* a, int64_t* n_rows, int64_t* nnz) {
+    if (!a) return fail(FFC_E_INVALID, "assembly is NULL");
+    if (n_rows) *n_rows = a->n_global;
+    if (nnz) *nnz = a->nnz;
+    return FFC_OK;
+}
+
+int ffc_assembly_pattern(const ffc_assembly* a, int64_t* row_ptr, int32_t* col_idx) {
+    if (!a || !row_ptr || (a->nnz > 0 && !col_idx)) return fail(FFC_E_INVALID, "NULL argument");
+    std::copy(a->row_ptr.begin(), a->row_ptr.end(), row_ptr);
+    std::copy(a->col.begin(), a->col.end(), col_idx);
+    return FFC_OK;
+}
+
+int ffc_assemble(ffc_assembly* a, const void* element_tensors, int32_t tensor_bytes, double* values,
+                 int32_t accumulate) {
+    if (!a) return fail(FFC_E_INVALID, "assembly is NULL");
+    if (tensor_bytes != 8 && tensor_bytes != 4) return fail(FFC_E_INVALID, "tensor_bytes must be 8 or 4");
+    if (a->nnz > 0 && !values) return fail(FFC_E_INVALID, "values is NULL");
+    if (a->cells > 0 && !element_tensors) return fail(FFC_E_INVALID, "element_tensors is NULL");
+    if (a->cells == 0) return FFC_OK;  // every row is empty
+    hipError_t e = ffc::gather_rows(a->n_global, a->n, a->d_slot_ptr, a->d_slots, element_tensors, tensor_bytes,
+                                    a->d_pos, a->d_row_ptr, values, accumulate ? 1 : 0, a->max_row, a->stream);
+    return e == hipSuccess ? FFC_OK : hip_fail(e, "assembly launch");
+}
+
+void ffc_assembly_destroy(ffc_assembly* a) { delete a; }
 
 // ------------------------------------------------------------- selector network ----
 

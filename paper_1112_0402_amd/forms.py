@@ -4,6 +4,8 @@ from __future__ import annotations
 
 import ctypes
 
+import numpy as np
+
 import torch
 
 from . import capi
@@ -155,6 +157,57 @@ class Batch:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             capi.lib().ffc_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Assembly:
+    """Global assembly into CSR (the insertion step of Algorithm 2): the pattern and the
+    CSR index of every element-tensor entry are built once from a local-to-global map."""
+
+    def __init__(self, dofmap: np.ndarray, n_global: int, stream=None):
+        dm = np.ascontiguousarray(dofmap, dtype=np.int32)
+        if dm.ndim != 2:
+            raise ValueError("dofmap must be [cells, n_local]")
+        self.cells, self.n_local = dm.shape
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        capi.check(capi.lib().ffc_assembly_create(self.cells, self.n_local, dm.ctypes.data, int(n_global),
+                                                  _stream_handle(self.stream), ctypes.byref(h)))
+        self._h = h
+        nr, nz = ctypes.c_int64(), ctypes.c_int64()
+        capi.check(capi.lib().ffc_assembly_info(h, ctypes.byref(nr), ctypes.byref(nz)))
+        self.n_rows, self.nnz = nr.value, nz.value
+
+    def pattern(self):
+        """(row_ptr int64 [n_rows + 1], col_idx int32 [nnz]) on the host."""
+        rp = np.empty(self.n_rows + 1, dtype=np.int64)
+        ci = np.empty(max(self.nnz, 1), dtype=np.int32)
+        capi.check(capi.lib().ffc_assembly_pattern(self._h, rp.ctypes.data, ci.ctypes.data))
+        return rp, ci[: self.nnz]
+
+    def assemble(self, tensors: torch.Tensor, values: torch.Tensor | None = None, accumulate: bool = False):
+        """CSR values [nnz] (FP64) of the sum of the element tensors [cells, n, n]."""
+        if tensors.dtype not in (torch.float64, torch.float32):
+            raise TypeError("element tensors must be float64 or float32")
+        _check_tensor("element_tensors", tensors, tensors.dtype)
+        if tensors.numel() != self.cells * self.n_local * self.n_local:
+            raise ValueError("element tensors of the wrong size")
+        if values is None:
+            values = torch.empty(self.nnz, dtype=torch.float64, device="cuda")
+        _check_tensor("values", values, torch.float64, (self.nnz,))
+        capi.check(capi.lib().ffc_assemble(self._h, _ptr(tensors), 8 if tensors.dtype == torch.float64 else 4,
+                                           _ptr(values), 1 if accumulate else 0))
+        return values
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            capi.lib().ffc_assembly_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

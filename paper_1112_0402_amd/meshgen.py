@@ -154,11 +154,17 @@ def _mesh(dim: int, n: int, seed: int, max_cells: int | None = None):
     return unit_cube(n, seed, max_cells=max_cells)
 
 
-def make_workload(kind, dim, degree, n, seed, max_cells=None, name="", coeff_seed=None):
+def make_workload(kind, dim, degree, n, seed, max_cells=None, name="", coeff_seed=None, jitter=JITTER):
     """Mesh of side n (2 n^2 or 6 n^3 cells, optionally cut to max_cells) with the
     coefficient field the form needs: wlaplace w ~ U(0.5, 2) per vertex, ns w ~ N(0, 1)
-    per vertex and component."""
-    verts, cells = _mesh(dim, n, seed, max_cells)
+    per vertex and component.  meta holds the topology (cells [nc, d+1] vertex indices,
+    n_vertices) for building local-to-global maps."""
+    if dim == 2:
+        verts, cells = unit_square(n, seed, jitter)
+        if max_cells is not None:
+            cells = cells[:max_cells]
+    else:
+        verts, cells = unit_cube(n, seed, jitter, max_cells=max_cells)
     coords = soa_coords(verts, cells)
     rng = np.random.Generator(np.random.PCG64(seed + 7919 if coeff_seed is None else coeff_seed))
     coeffs = None
@@ -166,7 +172,69 @@ def make_workload(kind, dim, degree, n, seed, max_cells=None, name="", coeff_see
         coeffs = p1_scalar_coeffs(cells, rng.uniform(0.5, 2.0, size=verts.shape[0]))
     elif kind == "ns":
         coeffs = p1_vector_coeffs(cells, rng.standard_normal(size=(verts.shape[0], dim)))
-    return Workload(kind, dim, degree, coords, coeffs, name=name)
+    return Workload(kind, dim, degree, coords, coeffs, name=name,
+                    meta={"cells": cells, "n_vertices": int(verts.shape[0])})
+
+
+# ------------------------------------------------------------ local-to-global maps ---
+# Topology only (no element arithmetic): a Lagrange node of a cell is named by its
+# barycentric lattice index a (a_v >= 0, sum = q) over the cell's vertices; the same
+# node seen from any cell sharing it has the same set {(global vertex, a_v) : a_v > 0},
+# which serves as its global key.  The local node order is the element tensor's: the
+# vertices, then the nodes inside the edges (triangle: edge k opposite vertex k;
+# tetrahedron: (2,3), (1,3), (1,2), (0,3), (0,2), (0,1)), the faces (face k opposite
+# vertex k), the interior; inside a sub-simplex with local vertices s_0 < ... < s_m,
+# ascending lexicographically in the weights of s_1, ..., s_m.
+
+def _lattice_nodes(dim: int, q: int):
+    nodes = []
+    for v in range(dim + 1):
+        a = [0] * (dim + 1)
+        a[v] = q
+        nodes.append(a)
+    if dim == 2:
+        subs = [(1, 2), (0, 2), (0, 1), (0, 1, 2)]
+    else:
+        subs = [(2, 3), (1, 3), (1, 2), (0, 3), (0, 2), (0, 1), (1, 2, 3), (0, 2, 3), (0, 1, 3), (0, 1, 2),
+                (0, 1, 2, 3)]
+    for s in subs:
+        m = len(s) - 1
+        for tail in itertools.product(range(1, q), repeat=m):  # ascending lexicographic
+            b0 = q - sum(tail)
+            if b0 >= 1:
+                a = [0] * (dim + 1)
+                a[s[0]] = b0
+                for vert, bv in zip(s[1:], tail):
+                    a[vert] = bv
+                nodes.append(a)
+    return np.array(nodes, dtype=np.int64)
+
+
+def lagrange_dofmap(cells: np.ndarray, degree: int, components: int = 1):
+    """Local-to-global map of the degree-q Lagrange space on a simplicial mesh: (dofmap
+    int32 [nc, components * n_s], n_global).  Vector spaces are component-blocked: local
+    dof (c, s) = c * n_s + s, global dof = c * N_s + (scalar global dof)."""
+    nc, nv1 = cells.shape
+    dim = nv1 - 1
+    nodes = _lattice_nodes(dim, degree)
+    n_s = nodes.shape[0]
+    keys = np.full((nc, n_s, 2 * nv1), -1, dtype=np.int64)
+    for p, a in enumerate(nodes):
+        sup = np.nonzero(a)[0]
+        g = cells[:, sup]                        # global vertices carrying the node
+        order = np.argsort(g, axis=1, kind="stable")
+        gs = np.take_along_axis(g, order, axis=1)
+        ws = a[sup][order]
+        keys[:, p, 0:2 * len(sup):2] = gs
+        keys[:, p, 1:2 * len(sup):2] = ws
+    flat = keys.reshape(nc * n_s, 2 * nv1)
+    _, inv = np.unique(flat, axis=0, return_inverse=True)
+    n_global = int(inv.max()) + 1 if inv.size else 0
+    scalar = inv.reshape(nc, n_s).astype(np.int64)
+    if components == 1:
+        return scalar.astype(np.int32), n_global
+    blocks = [scalar + c * n_global for c in range(components)]
+    return np.concatenate(blocks, axis=1).astype(np.int32), n_global * components
 
 
 def config1():

@@ -184,6 +184,37 @@ def test_config3_full_size_sampled(precision):
     assert emax <= (SPLIT6_TOL if precision == "bf16x6" else SPLIT3_BOUND)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "bf16x3"])
+def test_config4_full_size_batch_sampled(precision):
+    """The mixed batch at full size (64 meshes, 7,426,598 cells) in the launch sequence the
+    bench times, captured in a graph and replayed: 24 sampled cells of every mesh against
+    the oracle (FP64 to 1e-12; split to its bound)."""
+    require_gpu()
+    wls, forms = _batch_inputs(precision, scale=1.0)
+    assert sum(w.cells for w in wls) == 7_426_598
+    fl = [forms[(w.kind, w.dim, w.degree)] for w in wls]
+    X = [to_dev(w.coords) for w in wls]
+    C = [to_dev(w.coeffs) for w in wls]
+    outs = [f.empty_out(w.cells).fill_(float("nan")) for f, w in zip(fl, wls)]
+    s = torch.cuda.Stream()
+    b = Batch(fl, X, C, outs, stream=s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        b.run()
+    with torch.cuda.stream(s):
+        g.replay()
+    torch.cuda.synchronize()
+    worst = 0.0
+    for k, (w, o) in enumerate(zip(wls, outs)):
+        idx = np.arange(w.cells) if w.cells <= 24 else _sample(w.cells, 20, 100 + k)
+        ref = oracle.tabulate(w.kind, w.dim, w.degree, np.ascontiguousarray(w.coords[:, idx]),
+                              None if w.coeffs is None else np.ascontiguousarray(w.coeffs[:, idx]))
+        got = o[torch.from_numpy(idx).cuda()].cpu().numpy()
+        worst = max(worst, rel_fro(got, ref)[0])
+    say(f"[cfg4] {precision}: {b.total_cells} cells, {b.launches} launches, max sampled error {worst:.2e}")
+    assert worst <= (FP64_TOL if precision == "fp64" else SPLIT3_BOUND)
+
+
 def test_chunked_tabulation_beyond_workspace():
     """More cells than the geometry workspace holds (2^21): processed in chunks."""
     require_gpu()
