@@ -130,7 +130,8 @@ def bench_single(args, torch, np):
     C = None if wl.coeffs is None else torch.from_numpy(wl.coeffs).cuda()
     stream = torch.cuda.Stream()  # the form's launches and every timing event live on this stream
     form = Form(wl.kind, d, wl.degree, precision=precision, tile_cells=args.tile_cells, waves=args.waves,
-                tile_window=args.tile_window, persistent=args.persistent, geometry=args.geometry, stream=stream)
+                tile_window=args.tile_window, persistent=args.persistent, geometry=args.geometry,
+                symmetry=args.symmetry, stream=stream)
     info = form.info
     fused = bool(info["fused_geometry"])
     amap = None if fused else torch.empty((1 + d * d, cells), dtype=torch.float64, device="cuda")
@@ -449,6 +450,8 @@ def main() -> int:
                          "the selector trained on the stored sweep")
     ap.add_argument("--geometry", default="default", choices=["default", "pass", "fused"],
                     help="affine map in a separate pass or inside the contraction")
+    ap.add_argument("--symmetry", type=int, default=0, choices=[0, -1],
+                    help="FP64 symmetric forms: 0 computes the entries i1 <= i2 only, -1 every entry")
     ap.add_argument("--tile-window", type=int, default=0,
                     help="grouping of output entries into MFMA tiles (0 = library default)")
     ap.add_argument("--copy-calibration", action="store_true",

@@ -106,6 +106,12 @@ typedef struct {
                             always uses the pass.  0 = default: fused for the per-tile
                             kernels (measured faster on MI355X at every swept shape), the
                             pass for the persistent kernel. */
+    int32_t symmetry;    /* FP64 tensor kernel: 0 = auto (for the symmetric forms -- all but
+                            FFC_NS_CONVECTION -- compute only the entries i1 <= i2 on the
+                            matrix cores and write each also at (i2, i1): half the MFMA
+                            work; used where it saves MFMA steps and the output rows are
+                            staged in LDS, i.e. the persistent kernel or a staged tile
+                            launch), -1 = compute every entry */
     double lambda, mu;   /* Lame parameters (FFC_ELASTICITY only) */
     void* stream;        /* hipStream_t the form's work is enqueued on; NULL = default stream */
 } ffc_form_desc;
@@ -129,6 +135,9 @@ typedef struct {
     int64_t waves;            /* waves per workgroup of the (non-persistent) contraction */
     int64_t fused_geometry;   /* 1: ffc_tabulate_tensor computes the affine map inside the
                                  contraction (one launch); 0: geometry pass first */
+    int64_t symmetric;        /* 1: the FP64 tiles hold the entries i1 <= i2 only, each result
+                                 written at (i1, i2) and (i2, i1) -- the element matrices are
+                                 exactly symmetric; 0: every entry computed */
 } ffc_form_info;
 
 /* Compile step only, host only, touches no device: the reference tensor A^0 of the form

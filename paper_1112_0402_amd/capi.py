@@ -38,6 +38,7 @@ class FormDesc(ctypes.Structure):
         ("tile_window", ctypes.c_int32),
         ("persistent", ctypes.c_int32),
         ("geometry", ctypes.c_int32),
+        ("symmetry", ctypes.c_int32),
         ("lambda_", ctypes.c_double),
         ("mu", ctypes.c_double),
         ("stream", ctypes.c_void_p),
@@ -48,7 +49,7 @@ class FormInfo(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in (
         "n_dofs", "n_entries", "n_alpha", "nnz_a0", "n_coords", "n_coeffs", "out_bytes",
         "mfma_k_per_tile", "n_tiles", "quad_points", "persistent_waves", "persistent_kmax", "tile_cells",
-        "waves", "fused_geometry")]
+        "waves", "fused_geometry", "symmetric")]
 
 
 class FFCError(RuntimeError):
@@ -118,7 +119,7 @@ def check(rc: int) -> None:
 
 
 def make_desc(kind, dim, degree, precision="fp64", kernel="tensor", tile_cells=0, waves=0,
-              lam=1.0, mu=1.0, stream=None, tile_window=0, persistent=0, geometry=0) -> FormDesc:
+              lam=1.0, mu=1.0, stream=None, tile_window=0, persistent=0, geometry=0, symmetry=0) -> FormDesc:
     d = FormDesc()
     d.kind = KINDS[kind] if isinstance(kind, str) else int(kind)
     d.dim = dim
@@ -130,6 +131,7 @@ def make_desc(kind, dim, degree, precision="fp64", kernel="tensor", tile_cells=0
     d.tile_window = tile_window
     d.persistent = persistent
     d.geometry = GEOMETRY[geometry] if isinstance(geometry, str) else int(geometry)
+    d.symmetry = int(symmetry)
     d.lambda_ = lam
     d.mu = mu
     d.stream = stream

@@ -88,6 +88,7 @@ int check_desc(const ffc_form_desc* d, ffc::FormSpec* spec) {
     if (d->tile_cells != 0 && !valid_tile(d->tile_cells)) return fail(FFC_E_INVALID, "tile_cells must be 0, 16, 32 or 64");
     if (d->waves != 0 && !valid_waves(d->waves)) return fail(FFC_E_INVALID, "waves must be 0, 1, 2, 4, 8 or 16");
     if (d->geometry < 0 || d->geometry > FFC_GEOMETRY_FUSED) return fail(FFC_E_INVALID, "geometry must be 0, 1 or 2");
+    if (d->symmetry < -1 || d->symmetry > 0) return fail(FFC_E_INVALID, "symmetry must be 0 or -1");
     if (d->persistent < -1 || d->persistent > 1) return fail(FFC_E_INVALID, "persistent must be -1, 0 or 1");
     if (d->tile_window != 0 && d->tile_window != -1 && (d->tile_window < 16 || d->tile_window % 16 != 0))
         return fail(FFC_E_INVALID, "tile_window must be 0, -1 or a positive multiple of 16");
@@ -123,6 +124,7 @@ struct ffc_form {
     bool bpersistent = false;  // split modes: persistent BF16 contraction (pwaves, pkmax, pgrid set)
     int ptile = 16;            // its cell tile
     bool fused = false;  // ffc_tabulate_tensor computes the affine map inside the tile kernel
+    int sym_n = 0;       // FP64 symmetric tiles: element dofs
     int32_t* d_woff = nullptr;
     double* d_wave_b = nullptr;
     uint32_t* d_wave_word = nullptr;
@@ -190,7 +192,16 @@ int ffc_form_create(const ffc_form_desc* desc, ffc_form** out) {
         // default grouping: greedy clustering over all rows for large element tensors (the
         // persistent kernel), consecutive rows for small ones (64-cell tiles)
         f->tile_window = desc->tile_window ? desc->tile_window : (rt.n_I >= kPersistentMinEntries ? -1 : 16);
-        ffc::TilesF64 t = ffc::make_tiles_f64(rt, f->tile_window);
+        // symmetric forms: tiles over the entries i1 <= i2, where that takes fewer MFMA steps
+        ffc::TilesF64 t = ffc::make_tiles_f64(rt, f->tile_window, false);
+        f->sym_n = 0;
+        if (desc->symmetry == 0 && spec.kind != FFC_NS_CONVECTION) {
+            ffc::TilesF64 ts = ffc::make_tiles_f64(rt, f->tile_window, true);
+            if (ts.koff.back() < t.koff.back()) {
+                t = std::move(ts);
+                f->sym_n = rt.n;
+            }
+        }
         f->n_tiles = t.n_tiles;
         f->mfma_k = t.koff.back();
         if ((rc = upload(t.koff, &f->d_koff)) || (rc = upload(t.apack, &f->d_apack)) ||
@@ -231,7 +242,13 @@ int ffc_form_create(const ffc_form_desc* desc, ffc_form** out) {
                             const size_t i = (static_cast<size_t>(w) * km + s) * 64 + l;
                             wb[i] = t.b[(static_cast<size_t>(ks) * 4 + lk) * 16 + lr];
                             uint32_t word = (t.apack[ks] >> (8 * lk)) & 0xffu;
-                            if (te >= 0) word |= static_cast<uint32_t>(t.entry[te * 16 + lr] + 1) << 8;
+                            const int e = te >= 0 ? t.entry[te * 16 + lr] : -1;
+                            if (e >= 0) {
+                                word |= static_cast<uint32_t>(e + 1) << 8;
+                                // symmetric forms: the transposed entry too (off the diagonal)
+                                const int e2 = f->sym_n ? (e % f->sym_n) * f->sym_n + e / f->sym_n : e;
+                                if (e2 != e) word |= static_cast<uint32_t>(e2 + 1) << 20;
+                            }
                             wword[i] = word;
                         }
                     }
@@ -316,6 +333,21 @@ int ffc_form_create(const ffc_form_desc* desc, ffc_form** out) {
             }
         }
         if (f->waves == 0) f->waves = dw ? dw : f->tile_cells == 16 ? 16 : bf ? 8 : 4;
+        if (!bf && f->sym_n && f->pwaves == 0 && !plan(f->tile_cells).staged) {
+            // direct stores: the transposed entries of a tile's columns would be scattered
+            // writes, so this launch shape computes every entry
+            for (void* p : {static_cast<void*>(f->d_koff), static_cast<void*>(f->d_apack),
+                            static_cast<void*>(f->d_entry), static_cast<void*>(f->d_b)})
+                if (p) hipFree(p);
+            f->d_koff = nullptr, f->d_apack = nullptr, f->d_entry = nullptr, f->d_b = nullptr;
+            const ffc::TilesF64 t = ffc::make_tiles_f64(rt, f->tile_window, false);
+            f->sym_n = 0;
+            f->n_tiles = t.n_tiles;
+            f->mfma_k = t.koff.back();
+            if ((rc = upload(t.koff, &f->d_koff)) || (rc = upload(t.apack, &f->d_apack)) ||
+                (rc = upload(t.entry, &f->d_entry)) || (rc = upload(t.b, &f->d_b)))
+                return rc;
+        }
         const size_t lds = ffc::contract_lds_bytes(spec.dim, spec.kind, f->tile_cells, rt.n_I, rt.n_alpha, f->kpad, bf);
         if (lds > ffc::kLdsBudget) return fail(FFC_E_UNSUPPORTED, "tile does not fit the 160 KiB LDS of a CU");
     }
@@ -342,6 +374,7 @@ int ffc_form_get_info(const ffc_form* f, ffc_form_info* info) {
     info->tile_cells = f->bpersistent ? f->ptile : f->pwaves ? 16 : f->tile_cells;
     info->waves = f->waves;
     info->fused_geometry = f->fused ? 1 : 0;
+    info->symmetric = f->sym_n ? 1 : 0;
     return FFC_OK;
 }
 
@@ -385,6 +418,7 @@ ffc::ContractArgs contract_args(const ffc_form* f, int64_t n, const double* amap
     a.nonzero = f->d_nz;
     a.kpad = f->kpad;
     a.n_seg = f->n_seg;
+    a.sym_n = f->sym_n;
     std::copy(f->gpiece, f->gpiece + 6, a.gpiece);
     return a;
 }
@@ -564,6 +598,7 @@ int ffc_batch_create(int32_t n, const ffc_form* const* forms, const int64_t* cel
         it.kpad = f->kpad;
         it.n_seg = f->n_seg;
         it.n_coeff = f->rt.n_coeff;
+        it.sym_n = f->sym_n;
         it.koff = f->d_koff;
         it.apack = f->d_apack;
         it.entry = f->d_entry;

@@ -17,7 +17,9 @@ struct ContractArgs {
                             // per tile in LDS (amap unused; tile kernels only)
     void* out;              // [cells][n_I] double or float
     int n_I, n_alpha, n_tiles;
-    double lambda, mu;      // unused by the contraction (inside A^0), kept for symmetry
+    int sym_n;              // FP64 tiles of a symmetric form: element dofs (tiles hold the
+                            // entries i1 <= i2; each result also goes to i2 * n + i1); else 0
+    double lambda, mu;      // unused by the contraction (inside A^0)
     // FP64 tiles
     const int32_t* koff;    // [n_tiles + 1]
     const uint32_t* apack;  // [koff[n_tiles] / 4] alpha indices, 4 per word
@@ -70,6 +72,7 @@ struct PersistArgs {
     // per compute wave w, step s (s < kmax, zero past the wave's steps) and lane l:
     const double* wave_b;         // [w][s][l] B fragment value
     const uint32_t* wave_word;    // [w][s][l] LDS column of the alpha | (output entry + 1) << 8
+                                  // | (transposed entry + 1) << 20 (symmetric forms, else 0)
     const uint32_t* wave_mask;    // [w] bit s: step s ends a tile
     const int32_t* zero_entries;  // [n_zero]
     int n_zero;
@@ -109,6 +112,7 @@ struct BatchItem {
     const double* amap;     // persistent items: SoA [1 + d*d][cells]
     int32_t dim, kind, n_I, n_alpha, n_tiles, kpad, n_seg, n_coeff;
     int32_t mt, staged;     // tile items: cell tile 16*mt, output rows staged in LDS
+    int32_t sym_n, reserved2;  // FP64 symmetric forms: element dofs, else 0
     int32_t kmax, reserved; // persistent items: register steps per wave
     size_t stage_bytes, head_bytes;  // LDS plan: staged rows (0 = direct stores), map + coefficients
     const int32_t* koff;

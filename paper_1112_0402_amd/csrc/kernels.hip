@@ -275,7 +275,7 @@ __device__ __forceinline__ void contract_tile_f64(const double* am, const double
                                                   int64_t c0, int64_t cells, int nI, int n_tiles,
                                                   const int32_t* __restrict__ koff, const uint32_t* __restrict__ apack,
                                                   const int32_t* __restrict__ entry, const double* __restrict__ bvals,
-                                                  double* __restrict__ out) {
+                                                  double* __restrict__ out, int sym_n) {
     using FT = FormTraits<KIND, D>;
     constexpr int CT = 16 * MT;
     constexpr int NA = FT::n_alpha;
@@ -318,18 +318,26 @@ __device__ __forceinline__ void contract_tile_f64(const double* am, const double
             }
         }
         if (e >= 0) {
+            // symmetric forms: the same value at the transposed entry (sym_n = element dofs)
+            const int e2 = sym_n ? (e % sym_n) * sym_n + e / sym_n : e;
             if (st) {
 #pragma unroll
                 for (int m = 0; m < MT; ++m)
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) st[(m * 16 + i * 4 + lk) * nI + e] = acc[m][i];
+                    for (int i = 0; i < 4; ++i) {
+                        st[(m * 16 + i * 4 + lk) * nI + e] = acc[m][i];
+                        st[(m * 16 + i * 4 + lk) * nI + e2] = acc[m][i];
+                    }
             } else {
 #pragma unroll
                 for (int m = 0; m < MT; ++m)
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
                         const int64_t cell = c0 + m * 16 + i * 4 + lk;
-                        if (cell < cells) out[cell * nI + e] = acc[m][i];
+                        if (cell < cells) {
+                            out[cell * nI + e] = acc[m][i];
+                            if (e2 != e) out[cell * nI + e2] = acc[m][i];
+                        }
                     }
             }
         }
@@ -358,7 +366,7 @@ __global__ __launch_bounds__(1024) void contract_f64_kernel(ContractArgs A) {
         stage_tile<D, NC>(A, c0, CT, am, cf);
     __syncthreads();
     contract_tile_f64<D, KIND, MT>(am, cf, Gs, st, c0, A.cells, A.n_I, A.n_tiles, A.koff, A.apack, A.entry, A.b,
-                                   static_cast<double*>(A.out));
+                                   static_cast<double*>(A.out), A.sym_n);
 }
 
 template <int D, int KIND>
@@ -739,10 +747,16 @@ __device__ __forceinline__ void persistent_tiles(const ContractArgs& A, const Pe
                     const double bv = __builtin_bit_cast(double, u32x2{R[2 * s], R[2 * s + 1]});
                     acc = __builtin_amdgcn_mfma_f64_16x16x4f64(grow[word & 0xffu], bv, acc, 0, 0, 0);
                     if ((endmask >> s) & 1u) {
-                        const int e = static_cast<int>(word >> 8) - 1;
+                        const int e = static_cast<int>((word >> 8) & 0xfffu) - 1;
                         if (e >= 0) {
 #pragma unroll
                             for (int i = 0; i < 4; ++i) st[(i * 4 + lk) * nIs + e] = acc[i];
+                        }
+                        // symmetric forms: the transposed entry (none on the diagonal)
+                        const int e2 = static_cast<int>(word >> 20) - 1;
+                        if (e2 >= 0) {
+#pragma unroll
+                            for (int i = 0; i < 4; ++i) st[(i * 4 + lk) * nIs + e2] = acc[i];
                         }
                         acc = d4{0.0, 0.0, 0.0, 0.0};
                         // keeps the reset inside this branch (no select on every step that
@@ -1131,7 +1145,7 @@ __device__ __forceinline__ void batch_tile(const BatchItem& it, int64_t c0, unsi
         contract_tile_f64<D, KIND, MT>(am, cf, reinterpret_cast<double*>(g),
                                        it.staged ? reinterpret_cast<double*>(smem) : nullptr, c0, it.cells, it.n_I,
                                        it.n_tiles, as_global(it.koff), as_global(it.apack), as_global(it.entry),
-                                       as_global(it.b), as_global(static_cast<double*>(it.out)));
+                                       as_global(it.b), as_global(static_cast<double*>(it.out)), it.sym_n);
     }
 }
 

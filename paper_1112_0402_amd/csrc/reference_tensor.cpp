@@ -398,19 +398,26 @@ std::vector<std::vector<int>> cluster_rows(const std::vector<int>& rows, const s
 
 }  // namespace
 
-TilesF64 make_tiles_f64(const ReferenceTensor& rt, int window) {
+TilesF64 make_tiles_f64(const ReferenceTensor& rt, int window, bool sym) {
     TilesF64 T;
     const int nI = rt.n_I, na = rt.n_alpha;
     T.window = window;
+    T.sym = sym;
+    T.n = rt.n;
     std::vector<Mask> mask(nI, Mask{0, 0});
     for (int r = 0; r < nI; ++r)
         for (int a = 0; a < na; ++a)
             if (rt.A0[static_cast<size_t>(r) * na + a] != 0) mask[r][a >> 6] |= uint64_t(1) << (a & 63);
+    // the entries to compute: all, or those with i1 <= i2 (entry = i1 * n + i2)
+    std::vector<int> todo;
+    for (int r = 0; r < nI; ++r)
+        if (!sym || r / rt.n <= r % rt.n) todo.push_back(r);
+    const int nT = static_cast<int>(todo.size());
     std::vector<std::vector<int>> groups;
-    const int W = window <= 0 ? nI : window;
-    for (int w0 = 0; w0 < nI; w0 += W) {
+    const int W = window <= 0 ? nT : window;
+    for (int w0 = 0; w0 < nT; w0 += W) {
         std::vector<int> rows;
-        for (int r = w0; r < std::min(nI, w0 + W); ++r) rows.push_back(r);
+        for (int q = w0; q < std::min(nT, w0 + W); ++q) rows.push_back(todo[q]);
         if (W == 16) {
             groups.push_back(rows);
         } else {
@@ -453,11 +460,16 @@ WaveSchedule make_wave_schedule(const TilesF64& T, int waves) {
     S.waves = waves;
     std::vector<int> tiles;
     for (int t = 0; t < T.n_tiles; ++t) {
-        if (T.koff[t + 1] > T.koff[t])
+        if (T.koff[t + 1] > T.koff[t]) {
             tiles.push_back(t);
-        else
-            for (int e = 0; e < 16; ++e)
-                if (T.entry[static_cast<size_t>(t) * 16 + e] >= 0) S.zero_entries.push_back(T.entry[t * 16 + e]);
+        } else {
+            for (int e = 0; e < 16; ++e) {
+                const int x = T.entry[static_cast<size_t>(t) * 16 + e];
+                if (x < 0) continue;
+                S.zero_entries.push_back(x);
+                if (T.sym && (x % T.n) * T.n + x / T.n != x) S.zero_entries.push_back((x % T.n) * T.n + x / T.n);
+            }
+        }
     }
     std::stable_sort(tiles.begin(), tiles.end(), [&](int a, int b) {
         return (T.koff[a + 1] - T.koff[a]) > (T.koff[b + 1] - T.koff[b]);

@@ -49,6 +49,10 @@ struct TilesF64 {
     std::vector<uint32_t> apack;  // [koff[n_tiles] / 4]: the 4 alpha indices of a k step, one byte each
     std::vector<double> b;        // [koff[n_tiles]][16] A^0 values, 0 for padding
     std::vector<int32_t> entry;   // [n_tiles][16] output entry of each tile column, -1 = padding
+    // symmetric forms: only the entries i1 <= i2 of the element tensor are computed; each
+    // result also lands at the transposed entry (n = element dofs)
+    bool sym = false;
+    int n = 0;
 };
 
 // Split-BF16 contraction: concatenated K = n_seg segments of n_alpha, segment s pairs
@@ -75,7 +79,7 @@ bool supported(const FormSpec& s, std::string* why);
 
 LagrangeBasis make_basis(int dim, int degree);
 bool build_reference_tensor(const FormSpec& s, ReferenceTensor* out, std::string* err);
-TilesF64 make_tiles_f64(const ReferenceTensor& rt, int window);
+TilesF64 make_tiles_f64(const ReferenceTensor& rt, int window, bool sym = false);
 
 // Static schedule of the FP64 tiles over the waves of a persistent workgroup: the tiles
 // with a nonzero contraction are dealt to `waves` waves, longest first onto the least

@@ -36,12 +36,12 @@ class Form:
     """A compiled form on the current device (compile step + upload happen here)."""
 
     def __init__(self, kind, dim, degree, precision="fp64", kernel="tensor", tile_cells=0, waves=0,
-                 lam=1.0, mu=1.0, stream=None, tile_window=0, persistent=0, geometry=0):
+                 lam=1.0, mu=1.0, stream=None, tile_window=0, persistent=0, geometry=0, symmetry=0):
         self.kind, self.dim, self.degree = kind, dim, degree
         self.precision, self.kernel = precision, kernel
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self._desc = capi.make_desc(kind, dim, degree, precision, kernel, tile_cells, waves, lam, mu,
-                                    _stream_handle(self.stream), tile_window, persistent, geometry)
+                                    _stream_handle(self.stream), tile_window, persistent, geometry, symmetry)
         h = ctypes.c_void_p()
         capi.check(capi.lib().ffc_form_create(ctypes.byref(self._desc), ctypes.byref(h)))
         self._h = h

@@ -108,6 +108,47 @@ def test_fused_geometry_matches_geometry_pass(kind, dim, q, precision, tile_cell
     assert rel_fro(a, ref)[0] <= (FP64_TOL if precision == "fp64" else SPLIT6_TOL)
 
 
+@pytest.mark.parametrize("kind,dim,q", [("elasticity", 3, 2), ("laplace", 3, 3), ("mass", 2, 4), ("wlaplace", 3, 2),
+                                        ("elasticity", 2, 1), ("laplace", 2, 2)])
+@pytest.mark.parametrize("launch", [dict(), dict(persistent=-1, tile_cells=16), dict(persistent=-1, tile_cells=64),
+                                    dict(persistent=-1, tile_cells=32, waves=8, geometry="pass")])
+def test_symmetric_tiles(kind, dim, q, launch):
+    """Symmetric forms compute the entries i1 <= i2 only and write each at (i2, i1) too: the
+    element matrices come out exactly symmetric, agree with every entry computed (symmetry=-1)
+    to rounding, and with the oracle to the FP64 bound."""
+    require_gpu()
+    n = 40 if dim == 2 else 9
+    wl = meshgen.make_workload(kind, dim, q, n, 31, max_cells=9999)
+    fh, ff = Form(kind, dim, q, **launch), Form(kind, dim, q, symmetry=-1, **launch)
+    assert ff.info["symmetric"] == 0
+    # every form listed saves MFMA steps with half tiles; direct stores (output rows not
+    # staged in LDS) keep every entry
+    if not fh.info["symmetric"]:
+        assert fh.info["persistent_waves"] == 0
+        assert fh.info["tile_cells"] * fh.info["n_entries"] * 8 > 96 * 1024
+    half, full = _run(fh, wl), _run(ff, wl)
+    half = half.reshape(len(half), -1)
+    full = full.reshape(len(full), -1)
+    ne = int(round(math.sqrt(half.shape[1])))
+    m = half.reshape(-1, ne, ne)
+    if fh.info["symmetric"]:
+        assert np.array_equal(m, m.transpose(0, 2, 1))
+    assert rel_fro(half, full)[0] <= 1e-13
+    ref = oracle.tabulate(kind, dim, q, wl.coords, wl.coeffs)
+    assert rel_fro(half, ref)[0] <= FP64_TOL
+
+
+def test_nonsymmetric_form_ignores_symmetry():
+    require_gpu()
+    wl = _small("ns", 3, 2)
+    a = _run(Form("ns", 3, 2), wl)
+    b = _run(Form("ns", 3, 2, symmetry=-1), wl)
+    assert np.array_equal(a, b)
+    ne = int(round(math.sqrt(a[0].size)))
+    m = a.reshape(-1, ne, ne)
+    assert not np.allclose(m, m.transpose(0, 2, 1))
+
+
 @pytest.mark.parametrize("kind,dim,q", [("laplace", 2, 1), ("mass", 3, 3), ("laplace", 3, 4), ("wlaplace", 3, 3),
                                         ("elasticity", 3, 2), ("ns", 3, 2), ("ns", 2, 2), ("mass", 2, 2)])
 @pytest.mark.parametrize("precision", ["bf16x3", "bf16x6"])
