@@ -135,6 +135,10 @@ typedef struct {
     int64_t waves;            /* waves per workgroup of the (non-persistent) contraction */
     int64_t fused_geometry;   /* 1: ffc_tabulate_tensor computes the affine map inside the
                                  contraction (one launch); 0: geometry pass first */
+    int64_t g_entries;        /* G_K entries computed per cell: n_alpha, or fewer for the
+                                 symmetric geometry tensors (Laplacian, weighted Laplacian,
+                                 elasticity), whose two A^0 columns per unordered index pair
+                                 are summed in the compile step */
     int64_t symmetric;        /* 1: the FP64 tiles hold the entries i1 <= i2 only, each result
                                  written at (i1, i2) and (i2, i1) -- the element matrices are
                                  exactly symmetric; 0: every entry computed */

@@ -49,7 +49,7 @@ class FormInfo(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in (
         "n_dofs", "n_entries", "n_alpha", "nnz_a0", "n_coords", "n_coeffs", "out_bytes",
         "mfma_k_per_tile", "n_tiles", "quad_points", "persistent_waves", "persistent_kmax", "tile_cells",
-        "waves", "fused_geometry", "symmetric")]
+        "waves", "fused_geometry", "g_entries", "symmetric")]
 
 
 class FFCError(RuntimeError):

@@ -125,6 +125,8 @@ struct ffc_form {
     int ptile = 16;            // its cell tile
     bool fused = false;  // ffc_tabulate_tensor computes the affine map inside the tile kernel
     int sym_n = 0;       // FP64 symmetric tiles: element dofs
+    int n_alpha_form = 0;  // |alpha| and nnz of A^0 as the form defines them (before the fold)
+    int64_t nnz_form = 0;
     int32_t* d_woff = nullptr;
     double* d_wave_b = nullptr;
     uint32_t* d_wave_word = nullptr;
@@ -180,6 +182,14 @@ int ffc_form_create(const ffc_form_desc* desc, ffc_form** out) {
     f->waves = desc->waves;
     std::string err;
     if (!ffc::build_reference_tensor(spec, &f->rt, &err)) return fail(FFC_E_UNSUPPORTED, err);
+    f->n_alpha_form = f->rt.n_alpha;
+    f->nnz_form = f->rt.nnz;
+    // tensor kernels contract symmetric geometry tensors over unordered index pairs
+    if (desc->kernel == FFC_KERNEL_TENSOR) {
+        f->rt = ffc::fold_symmetric_g(f->rt);
+        if (f->rt.n_alpha != ffc::folded_n_alpha(spec.kind, spec.dim))
+            return fail(FFC_E_UNSUPPORTED, "internal: G entry count does not match the kernels");
+    }
     const ffc::ReferenceTensor& rt = f->rt;
     if (desc->kernel == FFC_KERNEL_QUADRATURE) {
         ffc::QuadTables qt = ffc::make_quad_tables(spec);
@@ -361,8 +371,9 @@ int ffc_form_get_info(const ffc_form* f, ffc_form_info* info) {
     const int d = f->desc.dim;
     info->n_dofs = rt.n;
     info->n_entries = rt.n_I;
-    info->n_alpha = rt.n_alpha;
-    info->nnz_a0 = rt.nnz;
+    info->n_alpha = f->n_alpha_form;
+    info->nnz_a0 = f->nnz_form;
+    info->g_entries = rt.n_alpha;
     info->n_coords = (d + 1) * d;
     info->n_coeffs = rt.n_coeff;
     info->out_bytes = (f->desc.kernel == FFC_KERNEL_TENSOR && f->desc.precision != FFC_FP64) ? 4 : 8;

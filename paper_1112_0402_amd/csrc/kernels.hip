@@ -55,10 +55,11 @@ __device__ __forceinline__ T* as_global(T* p) {
 
 template <int KIND, int D>
 struct FormTraits {
+    // G entries per cell; the symmetric geometry tensors keep each unordered index pair once
     static constexpr int n_alpha = KIND == K_MASS ? 1
-                                 : KIND == K_LAPLACE ? D * D
-                                 : KIND == K_WLAPLACE ? (D + 1) * D * D
-                                 : KIND == K_ELASTICITY ? D * D * D * D
+                                 : KIND == K_LAPLACE ? D * (D + 1) / 2
+                                 : KIND == K_WLAPLACE ? (D + 1) * D * (D + 1) / 2
+                                 : KIND == K_ELASTICITY ? D * D * (D * D + 1) / 2
                                                         : D * (D + 1) * D;
     static constexpr int n_coeff = KIND == K_WLAPLACE ? D + 1 : KIND == K_NS ? D * (D + 1) : 0;
 };
@@ -131,26 +132,43 @@ hipError_t launch_geometry(int dim, int64_t cells, const double* coords, int64_t
 // am: affine map of the tile in LDS, [1 + D*D][CT] (row 0 = det J, row 1 + a*D + b = g_ab)
 // cf: coefficients of the tile in LDS, [n_coeff][CT]
 
+// Index pair (u, v), u <= v < N, of pair number p, pairs numbered row by row (row u
+// starts at u*N - u*(u-1)/2).
+template <int N>
+__device__ __forceinline__ void upper_pair(int p, int& u, int& v) {
+    int r = 0;
+#pragma unroll
+    for (int k = 1; k < N; ++k) r += p >= k * N - k * (k - 1) / 2;
+    u = r;
+    v = p - (r * N - r * (r - 1) / 2) + r;
+}
+
 template <int KIND, int D>
 __device__ __forceinline__ double g_entry(const double* am, const double* cf, int CT, int c, int alpha) {
     const double adet = fabs(am[c]);
     auto g = [&](int a, int b) { return am[(1 + a * D + b) * CT + c]; };
     if constexpr (KIND == K_MASS) {
         return adet;
-    } else if constexpr (KIND == K_LAPLACE) {
-        const int a = alpha / D, b = alpha % D;
+    } else if constexpr (KIND == K_LAPLACE) {  // alpha = pair (a, b), a <= b
+        int a, b;
+        upper_pair<D>(alpha, a, b);
         double s = 0.0;
 #pragma unroll
         for (int k = 0; k < D; ++k) s += g(a, k) * g(b, k);
         return adet * s;
-    } else if constexpr (KIND == K_WLAPLACE) {
-        const int t = alpha / (D * D), a = (alpha / D) % D, b = alpha % D;
+    } else if constexpr (KIND == K_WLAPLACE) {  // alpha = t * pairs + pair (a, b)
+        constexpr int NP = D * (D + 1) / 2;
+        const int t = alpha / NP;
+        int a, b;
+        upper_pair<D>(alpha - t * NP, a, b);
         double s = 0.0;
 #pragma unroll
         for (int k = 0; k < D; ++k) s += g(a, k) * g(b, k);
         return cf[t * CT + c] * adet * s;
-    } else if constexpr (KIND == K_ELASTICITY) {
-        const int a = alpha / (D * D * D), j = (alpha / (D * D)) % D, b = (alpha / D) % D, l = alpha % D;
+    } else if constexpr (KIND == K_ELASTICITY) {  // alpha = pair (a*D + j, b*D + l)
+        int u, v;
+        upper_pair<D * D>(alpha, u, v);
+        const int a = u / D, j = u % D, b = v / D, l = v % D;
         return adet * g(a, j) * g(b, l);
     } else {  // K_NS: alpha = (k*(D+1) + t)*D + a, G = |det| g_ak w_{k,t}
         const int kt = alpha / D, a = alpha % D;

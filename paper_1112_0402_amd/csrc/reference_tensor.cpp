@@ -349,6 +349,44 @@ bool build_reference_tensor(const FormSpec& s, ReferenceTensor* rt, std::string*
     return true;
 }
 
+int folded_n_alpha(int kind, int d) {
+    switch (kind) {
+    case LAPLACE: return d * (d + 1) / 2;
+    case WLAPLACE: return (d + 1) * d * (d + 1) / 2;
+    case ELASTICITY: return d * d * (d * d + 1) / 2;
+    case MASS: return 1;
+    default: return d * (d + 1) * d;
+    }
+}
+
+ReferenceTensor fold_symmetric_g(const ReferenceTensor& rt) {
+    const int kind = rt.spec.kind, d = rt.spec.dim;
+    if (kind != LAPLACE && kind != WLAPLACE && kind != ELASTICITY) return rt;
+    // pair index space: N indices per side, `outer` independent copies (weight dofs)
+    const int N = kind == ELASTICITY ? d * d : d;
+    const int outer = kind == WLAPLACE ? d + 1 : 1;
+    const int np = N * (N + 1) / 2;
+    ReferenceTensor f = rt;
+    f.n_alpha = outer * np;
+    f.A0.assign(static_cast<size_t>(rt.n_I) * f.n_alpha, 0.0);
+    double amax = 0;
+    for (double v : rt.A0) amax = std::max(amax, std::fabs(v));
+    f.nnz = 0;
+    for (int i = 0; i < rt.n_I; ++i)
+        for (int t = 0; t < outer; ++t) {
+            int p = 0;
+            for (int u = 0; u < N; ++u)
+                for (int v = u; v < N; ++v, ++p) {
+                    const double* row = &rt.A0[static_cast<size_t>(i) * rt.n_alpha + t * N * N];
+                    double x = u == v ? row[u * N + v] : row[u * N + v] + row[v * N + u];
+                    if (std::fabs(x) <= 1e-12 * amax) x = 0;  // cancellation to rounding level
+                    f.A0[static_cast<size_t>(i) * f.n_alpha + t * np + p] = x;
+                    f.nnz += (x != 0);
+                }
+        }
+    return f;
+}
+
 // ------------------------------------------------------------ MFMA tiles -------
 
 namespace {

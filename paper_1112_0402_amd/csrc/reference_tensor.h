@@ -79,6 +79,14 @@ bool supported(const FormSpec& s, std::string* why);
 
 LagrangeBasis make_basis(int dim, int degree);
 bool build_reference_tensor(const FormSpec& s, ReferenceTensor* out, std::string* err);
+// Symmetric geometry tensors (Sec. 3.3): G^{ab} = G^{ba} for the Laplacian and, per weight
+// dof, for the weighted Laplacian; G^{(aj)(bl)} = G^{(bl)(aj)} for elasticity.  The
+// contraction then needs each unordered pair once, against the sum of its two A^0 columns.
+// Returns A^0 with the columns folded that way -- pairs (u, v), u <= v, row by row; the
+// weighted Laplacian keeps the weight dof as the outer index -- and every other form as it is.
+ReferenceTensor fold_symmetric_g(const ReferenceTensor& rt);
+// G entries per cell after the fold
+int folded_n_alpha(int kind, int dim);
 TilesF64 make_tiles_f64(const ReferenceTensor& rt, int window, bool sym = false);
 
 // Static schedule of the FP64 tiles over the waves of a persistent workgroup: the tiles

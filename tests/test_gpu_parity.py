@@ -138,6 +138,23 @@ def test_symmetric_tiles(kind, dim, q, launch):
     assert rel_fro(half, ref)[0] <= FP64_TOL
 
 
+@pytest.mark.parametrize("kind,dim,q,n_alpha,g_entries", [("laplace", 2, 2, 4, 3), ("laplace", 3, 1, 9, 6),
+                                                          ("wlaplace", 3, 3, 36, 24), ("elasticity", 3, 2, 81, 45),
+                                                          ("elasticity", 2, 1, 16, 10), ("mass", 3, 2, 1, 1),
+                                                          ("ns", 3, 2, 36, 36)])
+def test_symmetric_geometry_tensor_fold(kind, dim, q, n_alpha, g_entries):
+    """Symmetric G (Laplacian, weighted Laplacian, elasticity): the tensor kernels compute
+    each unordered index pair once against summed A^0 columns; |alpha| as the form defines
+    it is still reported, and the result matches the quadrature kernel and the oracle."""
+    require_gpu()
+    f = Form(kind, dim, q)
+    assert f.info["n_alpha"] == n_alpha and f.info["g_entries"] == g_entries
+    wl = _small(kind, dim, q)
+    ref = oracle.tabulate(kind, dim, q, wl.coords, wl.coeffs)
+    assert rel_fro(_run(f, wl), ref)[0] <= FP64_TOL
+    assert rel_fro(_run(Form(kind, dim, q, precision="bf16x6"), wl), ref)[0] <= SPLIT6_TOL
+
+
 def test_nonsymmetric_form_ignores_symmetry():
     require_gpu()
     wl = _small("ns", 3, 2)
