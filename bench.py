@@ -14,6 +14,8 @@ Other workloads (same JSON line layout):
   wlaplace    3D weighted Laplacian, P3 tets, w in P1, 1,500,282 cells, split BF16 (x3 / x6)
   batch       64 meshes of 1e3..5e5 cells, 16 form variants, the batch's fixed launch
               sequence replayed from a captured graph (FP64 or split BF16)
+  assembly    tabulation + global CSR assembly of the elasticity mesh
+  action      matrix-free operator action on the elasticity mesh (per cell and global)
 
 Forms that do not use the persistent kernel compute the affine map inside the contraction
 (one launch per step) unless --geometry pass is given.  The timed step is the hot path
@@ -430,13 +432,104 @@ def bench_assembly(args, torch, np):
     return result
 
 
+def bench_action(args, torch, np):
+    """Operator action on the 750,000-cell elasticity mesh: y_K = A^K x_K for every cell
+    (element tensors built on chip, only x and y in HBM), the global matrix-free y = A x
+    (gather through the dofmap, action, fixed-order sum per dof), and for comparison the
+    assembled CSR matrix times x (hipSPARSE through torch)."""
+    from paper_1112_0402_amd import meshgen
+    from paper_1112_0402_amd.forms import Assembly, Form
+
+    wl = meshgen.config2()
+    dm, ng = meshgen.lagrange_dofmap(wl.meta["cells"], 2, 3)
+    cells, n = dm.shape
+    stream = torch.cuda.Stream()
+    form = Form("elasticity", 3, 2, stream=stream)
+    info = form.info
+    X = torch.from_numpy(wl.coords).cuda()
+    rng = np.random.default_rng(6)
+    xg = torch.from_numpy(rng.uniform(-1.0, 1.0, size=ng)).cuda()
+    xl = torch.from_numpy(rng.uniform(-1.0, 1.0, size=(cells, n))).cuda()
+    yl = torch.empty_like(xl)
+    yg = torch.empty_like(xg)
+    asm = Assembly(dm, ng, stream=stream)
+    work = torch.empty(2 * cells * n, dtype=torch.float64, device="cuda")
+    T = form.empty_out(cells)
+    vals = torch.empty(asm.nnz, dtype=torch.float64, device="cuda")
+    with torch.cuda.stream(stream):
+        for _ in range(max(1, args.warmup)):
+            form.apply(X, xl, y=yl)
+            asm.apply(form, X, xg, y=yg, work=work)
+        form.tabulate(X, None, out=T)
+        asm.assemble(T, values=vals)
+        torch.cuda.synchronize()
+        act_ms = timed(lambda: form.apply(X, xl, y=yl), args.steps, stream, torch)
+        op_ms = timed(lambda: asm.apply(form, X, xg, y=yg, work=work), args.steps, stream, torch)
+        rp, ci = asm.pattern()
+        K = torch.sparse_csr_tensor(torch.from_numpy(rp).cuda(), torch.from_numpy(ci.astype(np.int64)).cuda(), vals,
+                                    size=(ng, ng))
+        ys = K @ xg
+        torch.cuda.synchronize()
+        spmv_ms = timed(lambda: K @ xg, args.steps, stream, torch)
+    op_err = float((ys - yg).abs().max() / ys.abs().max())
+    nnz = info["nnz_a0"]
+    flops = cells * (2 * nnz + 2 * n * n)   # element tensor (zeros of A^0 skipped) + its product with x
+    byt = cells * (12 * 8 + 2 * n * 8)       # coordinates, x_K and y_K
+    tf = flops / (act_ms * 1e-3) / 1e12
+    result = {
+        "metric": "operator actions y_K = A^K x_K per second (matrix-free tensor representation)",
+        "value": cells / (act_ms * 1e-3),
+        "unit": "cells/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": act_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "action_elasticity3d_p2_750k", "cells": cells, "dofs": ng, "n_local": n,
+                   "persistent": bool(info["persistent_waves"]),
+                   "step": "geometry pass + action kernel (element tensors built in LDS, times x_K)"},
+        "roofline": {"kernel": "geometry_kernel + contract_f64_persistent (action)", "bound": "mfma",
+                     "achieved": tf, "peak": FP64_MFMA_PEAK_TF, "unit": "TFLOP/s", "frac": tf / FP64_MFMA_PEAK_TF,
+                     "traffic": None, "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": byt,
+                     "achieved_gbs": byt / (act_ms * 1e-3) / 1e9, "ms_per_launch": act_ms},
+        "global_operator": {"ms": op_ms, "dofs_per_s": ng / (op_ms * 1e-3),
+                            "steps": "gather x_K, action, fixed-order sum per dof",
+                            "rel_diff_vs_assembled_spmv": op_err},
+        "assembled_spmv": {"ms_per_call": spmv_ms, "nnz": asm.nnz,
+                           "note": "torch CSR times vector (rocSPARSE) on the same operator, values from "
+                                   "ffc_assemble; per-call time includes torch's set-up, the SpMV kernel's own "
+                                   "duration is in the kernel trace; excludes the tabulation and assembly that "
+                                   "build the matrix"},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+
+        sample = min(cells, 131072)  # about 5-10 s of oracle work on a 16-core host
+        t = time.perf_counter()
+        A = oracle.tabulate("elasticity", 3, 2, np.ascontiguousarray(wl.coords[:, :sample]))
+        yr = np.einsum("cij,cj->ci", A.reshape(sample, n, n), xl[:sample].cpu().numpy())
+        dt = time.perf_counter() - t
+        got = yl[:sample].cpu().numpy()
+        err = np.linalg.norm(got - yr, axis=1) / (np.linalg.norm(A.reshape(sample, -1), axis=1)
+                                                 * np.linalg.norm(xl[:sample].cpu().numpy(), axis=1))
+        result["cpu_baseline"] = {"value": sample / dt, "unit": "cells/s", "cores": oracle.max_threads(),
+                                  "kind": "oracle", "sample": f"first {sample} cells: oracle element tensors times "
+                                  f"x_K, {dt:.1f} s"}
+        result["rel_err_vs_oracle"] = {"max": float(err.max()), "cells": sample, "tol": 1e-12}
+    return result
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="elasticity",
-                    choices=["elasticity", "poisson2d", "wlaplace", "batch", "assembly"])
+                    choices=["elasticity", "poisson2d", "wlaplace", "batch", "assembly", "action"])
     ap.add_argument("--precision", default="bf16x3", choices=["fp64", "bf16x3", "bf16x6"],
                     help="contraction arithmetic of the wlaplace and batch workloads")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target wall time of the oracle sample")
@@ -482,6 +575,8 @@ def main() -> int:
         result = bench_batch(args, torch, np)
     elif args.workload == "assembly":
         result = bench_assembly(args, torch, np)
+    elif args.workload == "action":
+        result = bench_action(args, torch, np)
     else:
         result = bench_single(args, torch, np)
     print(json.dumps(result), flush=True)

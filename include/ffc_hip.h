@@ -180,6 +180,18 @@ int ffc_tabulate_tensor(const ffc_form* form, int64_t cells, const double* coord
 int ffc_tabulate_tensor_affine(const ffc_form* form, int64_t cells, const double* affine_map, const double* coeffs,
                                void* out);
 
+/* Operator action (matrix-free): y_K = A^K x_K for every cell, A^K = A^0 : G_K as in
+ * ffc_tabulate_tensor (rows = test functions, Sec. 2.1), the element tensors built and used
+ * on chip and never written to memory -- the matrix-free use of the tensor representation
+ * that the paper points to as related work (Sec. 1).  x: device [cells][n] local vectors
+ * (n = element dofs, the trial-function dofs of each cell in the element's dof order), y:
+ * device [cells][n], overwritten.  FP64 tensor-kernel forms only (FFC_E_UNSUPPORTED
+ * otherwise, or when the element tensors of a 16-cell tile do not fit the LDS of a CU).
+ * Asynchronous on the form's stream, like ffc_tabulate_tensor; results equal A^K x_K
+ * computed from ffc_tabulate_tensor's output to FP64 rounding. */
+int ffc_apply_tensor(const ffc_form* form, int64_t cells, const double* coords, const double* coeffs, const double* x,
+                     double* y);
+
 /* The geometry pass alone (kernel 1 above), for inspection: affine map of each cell as
  * SoA [1 + d*d][cells] FP64 into caller-owned device memory: row 0 = det J, row
  * 1 + a*d + b = g_ab = (J^{-1})_ab.  Asynchronous on `stream` (hipStream_t, NULL =
@@ -191,16 +203,17 @@ int ffc_compute_geometry(int32_t dim, int64_t cells, const double* coords, doubl
  * coords, coeffs, out) items; all forms must share one precision and use the tensor
  * kernel.  ffc_batch_run enqueues a fixed, short sequence of launches on `stream` (fit
  * for graph capture; no memset, no allocation):
- *   - FP64 items whose form uses the persistent contraction: one geometry pass each into
- *     a batch-owned workspace, then one persistent launch per (dim, form kind, register
- *     schedule depth) whose workgroups claim chunks of 16-cell tiles of any of its items
- *     from an atomic queue (the queue counters reset themselves at the end of every run);
- *   - every other item: one launch per group of items sharing a workgroup size and an LDS
- *     size class, one workgroup per cell tile, geometry computed in place.
+ *   - items whose form uses a persistent contraction (FP64 or split BF16): one geometry
+ *     pass each into a batch-owned workspace, then one persistent launch per form over
+ *     the cell tiles of all its items in sequence (workgroup w takes tiles w, w + grid,
+ *     ...; the form's A^0 fragments stay in registers across items);
+ *   - every other item: one launch per group of items sharing a workgroup size, a cell
+ *     tile size and an LDS size class, one workgroup per cell tile, geometry computed in
+ *     place from the coordinates.
  * Results equal those of ffc_tabulate_tensor on each item.  The arrays are copied; the
  * device pointers must stay valid while the batch exists; runs of one batch must not
- * overlap (they share the queue counters).  ffc_batch_info: total cells, work units
- * (tiles plus claims) and the number of kernel launches one run enqueues. */
+ * overlap (they share the geometry workspace).  ffc_batch_info: total cells, work units
+ * (cell tiles) and the number of kernel launches one run enqueues. */
 typedef struct ffc_batch ffc_batch;
 int ffc_batch_create(int32_t n, const ffc_form* const* forms, const int64_t* cells, const double* const* coords,
                      const double* const* coeffs, void* const* outs, void* stream, ffc_batch** batch);
@@ -235,6 +248,17 @@ int ffc_assembly_info(const ffc_assembly* assembly, int64_t* n_rows, int64_t* nn
 int ffc_assembly_pattern(const ffc_assembly* assembly, int64_t* row_ptr, int32_t* col_idx);
 int ffc_assemble(ffc_assembly* assembly, const void* element_tensors, int32_t tensor_bytes, double* values,
                  int32_t accumulate);
+/* Matrix-free operator: y = A x, A = sum_K P_K^T A^K P_K the matrix ffc_assemble would
+ * build from `form`'s element tensors on this assembly's mesh (Algorithm 2), without
+ * forming A or the element tensors: x_K = P_K x (gather through the dofmap), y_K = A^K x_K
+ * (ffc_apply_tensor), then y[r] = sum of the y_K entries of dof r in a fixed order (cells
+ * ascending; no atomics).  coords / coeffs: the mesh as for ffc_tabulate_tensor, with the
+ * assembly's cell count; x, y: device [n_global] FP64 (y overwritten; dofs no cell touches
+ * get 0); work: caller-owned device scratch of 2 * cells * n_local doubles.  The form must
+ * be an FP64 tensor-kernel form with n_local element dofs.  Asynchronous on the form's
+ * stream; no allocation. */
+int ffc_operator_apply(const ffc_assembly* assembly, const ffc_form* form, const double* coords, const double* coeffs,
+                       const double* x, double* y, double* work);
 void ffc_assembly_destroy(ffc_assembly* assembly);
 
 /* Kernel selector network.  A multilayer perceptron that predicts the log run time of each

@@ -81,6 +81,7 @@ def lib():
     L.ffc_form_destroy.restype = None
     L.ffc_tabulate_tensor.argtypes = [vp, i64, vp, vp, vp]
     L.ffc_tabulate_tensor_affine.argtypes = [vp, i64, vp, vp, vp]
+    L.ffc_apply_tensor.argtypes = [vp, i64, vp, vp, vp, vp]
     L.ffc_compute_geometry.argtypes = [i32, i64, vp, vp, vp]
     L.ffc_batch_create.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(i64), ctypes.POINTER(vp),
                                    ctypes.POINTER(vp), ctypes.POINTER(vp), vp, ctypes.POINTER(vp)]
@@ -92,9 +93,11 @@ def lib():
     L.ffc_assembly_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     L.ffc_assembly_pattern.argtypes = [vp, vp, vp]
     L.ffc_assemble.argtypes = [vp, vp, i32, vp, i32]
+    L.ffc_operator_apply.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.ffc_assembly_destroy.argtypes = [vp]
     L.ffc_assembly_destroy.restype = None
-    for name in ("ffc_assembly_create", "ffc_assembly_info", "ffc_assembly_pattern", "ffc_assemble"):
+    for name in ("ffc_assembly_create", "ffc_assembly_info", "ffc_assembly_pattern", "ffc_assemble",
+                 "ffc_operator_apply"):
         getattr(L, name).restype = ctypes.c_int
     fp = ctypes.c_float
     L.ffc_mlp_param_count.argtypes = [i32, i32, i32]
@@ -106,7 +109,7 @@ def lib():
     for name in ("ffc_mlp_forward", "ffc_mlp_backward", "ffc_mlp_mse", "ffc_adam_step"):
         getattr(L, name).restype = ctypes.c_int
     for name in ("ffc_compile_reference_tensor", "ffc_form_create", "ffc_form_get_info", "ffc_tabulate_tensor",
-                 "ffc_tabulate_tensor_affine",
+                 "ffc_tabulate_tensor_affine", "ffc_apply_tensor",
                  "ffc_compute_geometry", "ffc_batch_create", "ffc_batch_run", "ffc_batch_info"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L

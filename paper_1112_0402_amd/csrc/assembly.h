@@ -29,4 +29,11 @@ hipError_t gather_rows(int64_t n_rows, int n, const int64_t* slot_ptr, const int
                        int tensor_bytes, const int32_t* pos, const int64_t* row_ptr, double* values, int accumulate,
                        int max_row, hipStream_t s);
 
+// Matrix-free operator steps.  Gather: xl[k] = x[dofmap[k]] for k < m (m = cells * n).
+// Sum: y[r] = sum of yl[slots[k]] over the slots of dof r, in slot order (one lane per dof;
+// every dof is written, 0 where no cell touches it).
+hipError_t gather_local(int64_t m, const int32_t* dofmap, const double* x, double* xl, hipStream_t s);
+hipError_t sum_slots(int64_t n_rows, const int64_t* slot_ptr, const int32_t* slots, const double* yl, double* y,
+                     hipStream_t s);
+
 }  // namespace ffc

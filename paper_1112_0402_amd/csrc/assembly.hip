@@ -174,4 +174,35 @@ hipError_t gather_rows(int64_t n_rows, int n, const int64_t* slot_ptr, const int
     return hipGetLastError();
 }
 
+namespace {
+__global__ void gather_local_kernel(int64_t m, const int32_t* __restrict__ dofmap, const double* __restrict__ x,
+                                    double* __restrict__ xl) {
+    const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k < m) xl[k] = x[dofmap[k]];
+}
+
+__global__ void sum_slots_kernel(int64_t n_rows, const int64_t* __restrict__ slot_ptr,
+                                 const int32_t* __restrict__ slots, const double* __restrict__ yl,
+                                 double* __restrict__ y) {
+    const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= n_rows) return;
+    double s = 0.0;
+    for (int64_t k = slot_ptr[r]; k < slot_ptr[r + 1]; ++k) s += yl[slots[k]];
+    y[r] = s;
+}
+}  // namespace
+
+hipError_t gather_local(int64_t m, const int32_t* dofmap, const double* x, double* xl, hipStream_t s) {
+    if (m <= 0) return hipSuccess;
+    gather_local_kernel<<<static_cast<unsigned>((m + 255) / 256), 256, 0, s>>>(m, dofmap, x, xl);
+    return hipGetLastError();
+}
+
+hipError_t sum_slots(int64_t n_rows, const int64_t* slot_ptr, const int32_t* slots, const double* yl, double* y,
+                     hipStream_t s) {
+    if (n_rows <= 0) return hipSuccess;
+    sum_slots_kernel<<<static_cast<unsigned>((n_rows + 255) / 256), 256, 0, s>>>(n_rows, slot_ptr, slots, yl, y);
+    return hipGetLastError();
+}
+
 }  // namespace ffc

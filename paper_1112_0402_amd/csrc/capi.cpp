@@ -463,6 +463,65 @@ int ffc_tabulate_tensor_affine(const ffc_form* f, int64_t cells, const double* a
     return contract_chunk(f, cells, affine_map, cells, coeffs, cells, out);
 }
 
+namespace {
+// launch shape of the operator action's tile kernel: the largest cell tile whose element
+// tensors and local vectors fit the LDS (64-cell tiles only while several workgroups stay
+// resident per CU)
+bool apply_tile_shape(const ffc_form* f, int* tile_cells, int* waves) {
+    const auto& rt = f->rt;
+    for (int ct : {64, 32, 16}) {
+        const size_t lds = ffc::apply_lds_bytes(f->desc.dim, f->desc.kind, ct, rt.n_I, rt.n_alpha, rt.n);
+        const ffc::LdsPlan p =
+            ffc::plan_lds(f->desc.dim, f->desc.kind, ct, rt.n_I, rt.n_alpha, 0, false, ffc::kLdsBudget);
+        if (!p.staged || lds > (ct == 64 ? 48 * 1024 : ffc::kLdsBudget)) continue;
+        *tile_cells = ct;
+        *waves = ct == 64 ? 4 : ct == 32 ? 8 : 16;
+        return true;
+    }
+    return false;
+}
+}  // namespace
+
+int ffc_apply_tensor(const ffc_form* f, int64_t cells, const double* coords, const double* coeffs, const double* x,
+                     double* y) {
+    if (!f) return fail(FFC_E_INVALID, "form is NULL");
+    if (f->desc.kernel != FFC_KERNEL_TENSOR || f->desc.precision != FFC_FP64)
+        return fail(FFC_E_UNSUPPORTED, "the operator action needs an FP64 tensor-kernel form");
+    if (cells < 0) return fail(FFC_E_INVALID, "cells < 0");
+    if (cells == 0) return FFC_OK;
+    if (!coords || !x || !y) return fail(FFC_E_INVALID, "coords / x / y is NULL");
+    const auto& rt = f->rt;
+    if (rt.n_coeff > 0 && !coeffs) return fail(FFC_E_INVALID, "this form needs coefficients (coeffs is NULL)");
+    const int d = f->desc.dim, kind = f->desc.kind, n = rt.n;
+    if (f->pwaves > 0) {
+        hipError_t e = hipSuccess;
+        for (int64_t c0 = 0; c0 < cells; c0 += f->amap_cap) {
+            const int64_t m = std::min(f->amap_cap, cells - c0);
+            e = ffc::launch_geometry(d, m, coords + c0, cells, f->d_amap, f->amap_cap, f->stream);
+            if (e != hipSuccess) return hip_fail(e, "geometry kernel launch");
+            ffc::ContractArgs a =
+                contract_args(f, m, f->d_amap, f->amap_cap, coeffs ? coeffs + c0 : nullptr, cells, y + c0 * n);
+            a.xloc = x + c0 * n;
+            a.n_dof = n;
+            ffc::PersistArgs p{f->d_woff, f->d_wave_b, f->d_wave_word, f->d_wave_mask, f->d_zero, f->n_zero};
+            e = ffc::launch_apply_persistent(d, kind, f->pkmax, f->pwaves, f->pgrid, a, p, f->stream);
+            if (e == hipErrorInvalidValue) break;  // the form does not fit it: tile kernel below
+            if (e != hipSuccess) return hip_fail(e, "operator action kernel launch");
+        }
+        if (e == hipSuccess) return FFC_OK;
+    }
+    int ct = 0, w = 0;
+    if (!apply_tile_shape(f, &ct, &w))
+        return fail(FFC_E_UNSUPPORTED, "the element tensors of a 16-cell tile do not fit the LDS of a CU");
+    ffc::ContractArgs a = contract_args(f, cells, nullptr, 0, coeffs, cells, y);
+    a.coords = coords;
+    a.xloc = x;
+    a.n_dof = n;
+    hipError_t e = ffc::launch_apply(d, kind, ct, w, a, f->stream);
+    if (e != hipSuccess) return hip_fail(e, "operator action kernel launch");
+    return FFC_OK;
+}
+
 int ffc_tabulate_tensor(const ffc_form* f, int64_t cells, const double* coords, const double* coeffs, void* out) {
     if (!f) return fail(FFC_E_INVALID, "form is NULL");
     if (cells < 0) return fail(FFC_E_INVALID, "cells < 0");
@@ -745,10 +804,11 @@ struct ffc_assembly {
     int64_t* d_row_ptr = nullptr;   // [n_global + 1]
     int64_t* d_slot_ptr = nullptr;  // [n_global + 1]
     int32_t* d_slots = nullptr;     // [cells * n] element-tensor rows per matrix row
+    int32_t* d_dofmap = nullptr;    // [cells][n] (operator action: gather of the local vectors)
     hipStream_t stream = nullptr;
     ~ffc_assembly() {
         for (void* p : {static_cast<void*>(d_pos), static_cast<void*>(d_row_ptr), static_cast<void*>(d_slot_ptr),
-                        static_cast<void*>(d_slots)})
+                        static_cast<void*>(d_slots), static_cast<void*>(d_dofmap)})
             if (p) (void)hipFree(p);
     }
 };
@@ -781,20 +841,20 @@ int ffc_assembly_create(int64_t cells, int32_t n_local, const int32_t* dofmap, i
         a->max_row = std::max<int>(a->max_row, static_cast<int>(a->row_ptr[r + 1] - a->row_ptr[r]));
     if (a->max_row > 1024) return fail(FFC_E_UNSUPPORTED, "a matrix row longer than 1024 entries");
     if (cells > 0) {
-        int32_t* d_dofmap = nullptr;
         int32_t* d_col = nullptr;
         std::vector<int32_t> dm(dofmap, dofmap + cells * n_local);
         const size_t entries = static_cast<size_t>(cells) * n_local * n_local;
-        if ((rc = upload(dm, &d_dofmap)) || (rc = upload(a->row_ptr, &a->d_row_ptr)) || (rc = upload(a->col, &d_col)) ||
-            (rc = upload(slot_ptr, &a->d_slot_ptr)) || (rc = upload(slots, &a->d_slots))) {
-            (void)hipFree(d_dofmap), (void)hipFree(d_col);
+        if ((rc = upload(dm, &a->d_dofmap)) || (rc = upload(a->row_ptr, &a->d_row_ptr)) ||
+            (rc = upload(a->col, &d_col)) || (rc = upload(slot_ptr, &a->d_slot_ptr)) ||
+            (rc = upload(slots, &a->d_slots))) {
+            (void)hipFree(d_col);
             return rc;
         }
         hipError_t e = hipMalloc(reinterpret_cast<void**>(&a->d_pos), entries * sizeof(int32_t));
         if (e == hipSuccess)
-            e = ffc::scatter_positions(cells, n_local, d_dofmap, a->d_row_ptr, d_col, a->d_pos, a->stream);
+            e = ffc::scatter_positions(cells, n_local, a->d_dofmap, a->d_row_ptr, d_col, a->d_pos, a->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(a->stream);
-        (void)hipFree(d_dofmap), (void)hipFree(d_col);
+        (void)hipFree(d_col);
         if (e != hipSuccess) return hip_fail(e, "assembly symbolic phase");
     }
     *out = a.release();
@@ -825,6 +885,25 @@ int ffc_assemble(ffc_assembly* a, const void* element_tensors, int32_t tensor_by
     hipError_t e = ffc::gather_rows(a->n_global, a->n, a->d_slot_ptr, a->d_slots, element_tensors, tensor_bytes,
                                     a->d_pos, a->d_row_ptr, values, accumulate ? 1 : 0, a->max_row, a->stream);
     return e == hipSuccess ? FFC_OK : hip_fail(e, "assembly launch");
+}
+
+int ffc_operator_apply(const ffc_assembly* a, const ffc_form* f, const double* coords, const double* coeffs,
+                       const double* x, double* y, double* work) {
+    if (!a || !f) return fail(FFC_E_INVALID, "assembly / form is NULL");
+    if (f->rt.n != a->n) return fail(FFC_E_INVALID, "the form's element dofs differ from the dofmap's");
+    if (!x || !y) return fail(FFC_E_INVALID, "x / y is NULL");
+    if (a->cells > 0 && (!coords || !work)) return fail(FFC_E_INVALID, "coords / work is NULL");
+    const int64_t m = a->cells * a->n;
+    double* xl = work;
+    double* yl = work + m;
+    hipError_t e = ffc::gather_local(m, a->d_dofmap, x, xl, f->stream);
+    if (e != hipSuccess) return hip_fail(e, "gather launch");
+    if (a->cells > 0) {
+        const int rc = ffc_apply_tensor(f, a->cells, coords, coeffs, xl, yl);
+        if (rc) return rc;
+    }
+    e = ffc::sum_slots(a->n_global, a->d_slot_ptr, a->d_slots, yl, y, f->stream);
+    return e == hipSuccess ? FFC_OK : hip_fail(e, "sum launch");
 }
 
 void ffc_assembly_destroy(ffc_assembly* a) { delete a; }

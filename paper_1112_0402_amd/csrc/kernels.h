@@ -30,6 +30,9 @@ struct ContractArgs {
     const uint8_t* nonzero; // [n_tiles]
     int kpad, n_seg;
     int gpiece[6];
+    // operator action (y_K = A^K x_K): local vectors x [cells][n_dof]; out = y [cells][n_dof]
+    const double* xloc;
+    int n_dof;
     // LDS plan, filled by launch_contract
     int staged;
     size_t stage_bytes, head_bytes;
@@ -95,6 +98,15 @@ LdsPlan plan_bf16_persistent(int dim, int kind, int tile_cells, int n_I, int n_t
 // Returns hipErrorInvalidValue when the form or the output does not fit this kernel.
 hipError_t launch_contract_bf16_persistent(int dim, int kind, int tile_cells, int grid, ContractArgs a,
                                            hipStream_t stream);
+// Operator action of FP64 forms, y_K = A^K x_K per cell: the element tensors of a cell tile are
+// built in LDS exactly as for tabulation and multiplied there by the cells' local vectors;
+// only x and y (n_dof doubles per cell) cross HBM.  Tile kernel: returns hipErrorInvalidValue
+// when the tile's rows cannot be staged; persistent kernel: same conditions as the persistent
+// contraction, plus at most 16 register steps per wave and 16 * n_dof <= 2 * 64 * kIoWaves.
+size_t apply_lds_bytes(int dim, int kind, int tile_cells, int n_I, int n_alpha, int n_dof);
+hipError_t launch_apply(int dim, int kind, int tile_cells, int waves, ContractArgs a, hipStream_t stream);
+hipError_t launch_apply_persistent(int dim, int kind, int kmax, int waves, int grid, ContractArgs a,
+                                   const PersistArgs& p, hipStream_t stream);
 hipError_t launch_quadrature(int dim, int kind, const QuadArgs& a, hipStream_t stream);
 size_t contract_lds_bytes(int dim, int kind, int tile_cells, int n_I, int n_alpha, int kpad, bool bf16);
 int quad_cells_per_block(int dim, int kind, int ns, int npts);

@@ -360,7 +360,7 @@ __device__ __forceinline__ void contract_tile_f64(const double* am, const double
             }
         }
     }
-    if (st) {
+    if (st && out) {
         __syncthreads();
         const int64_t nc = cells - c0 < CT ? cells - c0 : CT;
         write_region(st, out + c0 * nI, nc * nI);
@@ -385,6 +385,45 @@ __global__ __launch_bounds__(1024) void contract_f64_kernel(ContractArgs A) {
     __syncthreads();
     contract_tile_f64<D, KIND, MT>(am, cf, Gs, st, c0, A.cells, A.n_I, A.n_tiles, A.koff, A.apack, A.entry, A.b,
                                    static_cast<double*>(A.out), A.sym_n);
+}
+
+// Operator action, one cell tile per workgroup: the tile's local vectors go to LDS beside
+// the G tile, the element tensors to the staged rows, then thread (c, i1) forms
+// y[c][i1] = sum_i2 A^K[c][i1][i2] x[c][i2] and the tile's y rows leave as one contiguous run.
+template <int D, int KIND, int MT>
+__global__ __launch_bounds__(1024) void apply_f64_kernel(ContractArgs A) {
+    using FT = FormTraits<KIND, D>;
+    constexpr int CT = 16 * MT;
+    constexpr int NC = FT::n_coeff;
+    constexpr int GS = FT::n_alpha | 1;
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    double* st = reinterpret_cast<double*>(smem_raw);
+    double* am = reinterpret_cast<double*>(smem_raw + A.stage_bytes);
+    double* cf = am + (1 + D * D) * CT;
+    double* Gs = reinterpret_cast<double*>(smem_raw + A.stage_bytes + A.head_bytes);
+    double* xs = Gs + CT * GS;
+    const int n = A.n_dof, nI = A.n_I;
+    const int64_t c0 = static_cast<int64_t>(blockIdx.x) * CT;
+    const int64_t nc = A.cells - c0 < CT ? A.cells - c0 : CT;
+    const double* xg = A.xloc + c0 * n;
+    for (int i = threadIdx.x; i < CT * n; i += blockDim.x) xs[i] = i < nc * n ? xg[i] : 0.0;
+    if (A.coords)
+        stage_tile_from_coords<D, NC>(A.coords, A.coeffs, A.cells, c0, CT, am, cf);
+    else
+        stage_tile<D, NC>(A, c0, CT, am, cf);
+    __syncthreads();
+    contract_tile_f64<D, KIND, MT>(am, cf, Gs, st, c0, A.cells, nI, A.n_tiles, A.koff, A.apack, A.entry, A.b,
+                                   nullptr, A.sym_n);
+    __syncthreads();
+    double* y = static_cast<double*>(A.out) + c0 * n;
+    for (int t = threadIdx.x; t < nc * n; t += blockDim.x) {
+        const int c = t / n, i1 = t - c * n;
+        const double* row = st + c * nI + i1 * n;
+        const double* xc = xs + c * n;
+        double s = 0.0;
+        for (int i2 = 0; i2 < n; ++i2) s = fma(row[i2], xc[i2], s);
+        y[t] = s;
+    }
 }
 
 template <int D, int KIND>
@@ -630,8 +669,11 @@ struct ItemCursor {
 };
 
 // The tiles g, g + step, ... below g_end of a tile source (one mesh, or the items of a
-// batch that share one form).
-template <int D, int KIND, int KMAX, int IOS, class Src>
+// batch that share one form).  ACT (operator action, one mesh): the I/O waves prefetch the
+// next tile's local vectors into registers, put them in LDS (two alternating buffers, so
+// that one tile's products and the next tile's vectors never share one), and, once a
+// tile's element tensors are staged, form y = A^K x there and store only y.
+template <int D, int KIND, int KMAX, int IOS, bool ACT = false, class Src>
 __device__ __forceinline__ void persistent_tiles(const ContractArgs& A, const PersistArgs& P, Src& src, int64_t ct,
                                                  const int64_t ct_end, const int64_t step, unsigned char* smem_raw) {
     using FT = FormTraits<KIND, D>;
@@ -644,7 +686,8 @@ __device__ __forceinline__ void persistent_tiles(const ContractArgs& A, const Pe
     // role, so separate arrays would both count): a compute lane keeps the B fragment of
     // step s in R[2s], R[2s+1] and its packed word in R[2*KMAX + s]; an I/O lane keeps
     // 16-byte slot j of a staged tile in R[4j .. 4j+3].
-    constexpr int NR = (3 * KMAX > 4 * IOS) ? 3 * KMAX : 4 * IOS;
+    // (the operator action keeps no staged tile in registers)
+    constexpr int NR = (ACT || 3 * KMAX > 4 * IOS) ? 3 * KMAX : 4 * IOS;
     // Wave roles: the first blockDim/64 - kIoWaves waves ("compute waves") prefetch the next
     // tile's affine map and coefficients and run the MFMA steps; the last kIoWaves waves
     // move the staged output to global memory and nothing else.  A wave that has stores in
@@ -697,12 +740,23 @@ __device__ __forceinline__ void persistent_tiles(const ContractArgs& A, const Pe
         if (cell >= t.cells) return r == 0 ? 1.0 : 0.0;
         return r < 1 + D * D ? t.amap[r * t.astride + cell] : t.coeffs[(r - 1 - D * D) * t.cstride + cell];
     };
-    // output run of a tile: start and length in doubles
+    // output run of a tile: start and length in doubles (element tensors, or y)
+    const int nd = A.n_dof;
     auto out_run = [&](const MeshTile& t, double*& o, int64_t& n) {
         const int64_t c0 = t.ct * CT;
-        o = t.out + c0 * nI;
-        n = (t.cells - c0 < CT ? t.cells - c0 : CT) * nI;
+        const int64_t w = ACT ? nd : nI;
+        o = t.out + c0 * w;
+        n = (t.cells - c0 < CT ? t.cells - c0 : CT) * w;
     };
+    // operator action: I/O lane l prefetches values l and l + 64 * kIoWaves of the tile's
+    // local vectors (CT * nd <= 2 * 64 * kIoWaves doubles)
+    double* xs = Gs + CT * GS;
+    auto fetchx = [&](const MeshTile& t, int i) -> double {
+        const int64_t g = t.ct * CT * nd + i;
+        return i < CT * nd && g < t.cells * nd ? A.xloc[g] : 0.0;
+    };
+    double px0 = 0.0, px1 = 0.0;
+    int xbuf = 0;
     double pre = 0.0;
     double* cur_out = nullptr;
     int64_t cur_n = 0;
@@ -710,6 +764,10 @@ __device__ __forceinline__ void persistent_tiles(const ContractArgs& A, const Pe
         const MeshTile t = src.at(ct);
         out_run(t, cur_out, cur_n);
         if (tid < ROWS * CT) pre = fetch(t);
+        if (ACT && tid >= io_begin) {
+            px0 = fetchx(t, io_lane);
+            px1 = fetchx(t, io_lane + 64 * kIoWaves);
+        }
     }
     const double* grow = Gs + lr * GS;
     double* io_out = nullptr;
@@ -734,10 +792,21 @@ __device__ __forceinline__ void persistent_tiles(const ContractArgs& A, const Pe
         double* nxt_out = nullptr;
         int64_t nxt_n = 0;
         if (tid < ROWS * CT) am[tid] = pre;
+        if constexpr (ACT) {
+            if (tid >= io_begin) {
+                double* xb = xs + xbuf * CT * nd;
+                if (io_lane < CT * nd) xb[io_lane] = px0;
+                if (io_lane + 64 * kIoWaves < CT * nd) xb[io_lane + 64 * kIoWaves] = px1;
+            }
+        }
         if (more) {
             const MeshTile t = src.at(ct + step);
             out_run(t, nxt_out, nxt_n);
             if (tid < ROWS * CT) pre = fetch(t);
+            if (ACT && tid >= io_begin) {
+                px0 = fetchx(t, io_lane);
+                px1 = fetchx(t, io_lane + 64 * kIoWaves);
+            }
         }
         lds_barrier();
         for (int i = tid; i < CT * NA; i += blockDim.x) {
@@ -750,7 +819,7 @@ __device__ __forceinline__ void persistent_tiles(const ContractArgs& A, const Pe
         }
         lds_barrier();
         if (tid >= io_begin) {
-            if (io_n > 0) io_store();  // the previous tile, during this tile's MFMA phase
+            if (!ACT && io_n > 0) io_store();  // the previous tile, during this tile's MFMA phase
         } else {
             // compiler-only barrier (emits no instruction) on the row stride: keeps the
             // staging addresses of the steps from being precomputed outside the cell-tile
@@ -785,7 +854,23 @@ __device__ __forceinline__ void persistent_tiles(const ContractArgs& A, const Pe
             }
         }
         lds_barrier();
-        if (tid >= io_begin) {  // take this tile's rows into registers; st is free after the next barrier
+        if (ACT && tid >= io_begin) {  // y = A^K x for this tile, straight to global memory
+            const double* xb = xs + xbuf * CT * nd;
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const int t = io_lane + r * 64 * kIoWaves;
+                if (t < cur_n) {
+                    const int c = t / nd, i1 = t - c * nd;
+                    const double* row = st + c * nI + i1 * nd;
+                    const double* xc = xb + c * nd;
+                    double s = 0.0;
+#pragma unroll 4
+                    for (int i2 = 0; i2 < nd; ++i2) s = fma(row[i2], xc[i2], s);
+                    cur_out[t] = s;
+                }
+            }
+            xbuf ^= 1;
+        } else if (!ACT && tid >= io_begin) {  // take this tile's rows into registers; st is free after the next barrier
             io_out = cur_out;
             io_n = cur_n;
             const int64_t nv = io_n / 2;
@@ -811,34 +896,38 @@ __device__ __forceinline__ void persistent_tiles(const ContractArgs& A, const Pe
         cur_out = nxt_out;
         cur_n = nxt_n;
     }
-    if (tid >= io_begin && io_n > 0) io_store();  // the last tile
+    if (!ACT && tid >= io_begin && io_n > 0) io_store();  // the last tile
 }
 
-template <int D, int KIND, int KMAX, int MAXT, int IOS>
+template <int D, int KIND, int KMAX, int MAXT, int IOS, bool ACT = false>
 __global__ __launch_bounds__(MAXT) void contract_f64_persistent(ContractArgs A, PersistArgs P) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     OneMesh src{A};
-    persistent_tiles<D, KIND, KMAX, IOS>(A, P, src, blockIdx.x, (A.cells + 15) / 16, gridDim.x, smem_raw);
+    persistent_tiles<D, KIND, KMAX, IOS, ACT>(A, P, src, blockIdx.x, (A.cells + 15) / 16, gridDim.x, smem_raw);
 }
 
-template <int D, int KIND>
+template <int D, int KIND, bool ACT>
 static hipError_t launch_persistent_k(int kmax, int waves, int grid, size_t lds, const ContractArgs& a,
                                       const PersistArgs& p, hipStream_t s) {
     const unsigned block = 64u * waves;
-    if (kmax <= 8) return launch_lds(contract_f64_persistent<D, KIND, 8, 1024, kIoSlots>, grid, block, lds, s, a, p);
-    if (kmax <= 16) return launch_lds(contract_f64_persistent<D, KIND, 16, 1024, kIoSlots>, grid, block, lds, s, a, p);
-    return launch_lds(contract_f64_persistent<D, KIND, 24, 1024, kIoSlots>, grid, block, lds, s, a, p);
+    if (kmax <= 8)
+        return launch_lds(contract_f64_persistent<D, KIND, 8, 1024, kIoSlots, ACT>, grid, block, lds, s, a, p);
+    if (kmax <= 16)
+        return launch_lds(contract_f64_persistent<D, KIND, 16, 1024, kIoSlots, ACT>, grid, block, lds, s, a, p);
+    // the operator action stops at 16 register steps (past them its registers spill)
+    if constexpr (ACT) return hipErrorInvalidValue;
+    else return launch_lds(contract_f64_persistent<D, KIND, 24, 1024, kIoSlots, ACT>, grid, block, lds, s, a, p);
 }
 
-template <int D>
+template <int D, bool ACT = false>
 static hipError_t launch_persistent_d(int kind, int kmax, int waves, int grid, size_t lds, const ContractArgs& a,
                                       const PersistArgs& p, hipStream_t s) {
     switch (kind) {
-    case K_MASS: return launch_persistent_k<D, K_MASS>(kmax, waves, grid, lds, a, p, s);
-    case K_LAPLACE: return launch_persistent_k<D, K_LAPLACE>(kmax, waves, grid, lds, a, p, s);
-    case K_WLAPLACE: return launch_persistent_k<D, K_WLAPLACE>(kmax, waves, grid, lds, a, p, s);
-    case K_ELASTICITY: return launch_persistent_k<D, K_ELASTICITY>(kmax, waves, grid, lds, a, p, s);
-    default: return launch_persistent_k<D, K_NS>(kmax, waves, grid, lds, a, p, s);
+    case K_MASS: return launch_persistent_k<D, K_MASS, ACT>(kmax, waves, grid, lds, a, p, s);
+    case K_LAPLACE: return launch_persistent_k<D, K_LAPLACE, ACT>(kmax, waves, grid, lds, a, p, s);
+    case K_WLAPLACE: return launch_persistent_k<D, K_WLAPLACE, ACT>(kmax, waves, grid, lds, a, p, s);
+    case K_ELASTICITY: return launch_persistent_k<D, K_ELASTICITY, ACT>(kmax, waves, grid, lds, a, p, s);
+    default: return launch_persistent_k<D, K_NS, ACT>(kmax, waves, grid, lds, a, p, s);
     }
 }
 
@@ -859,6 +948,69 @@ hipError_t launch_contract_persistent(int dim, int kind, int kmax, int waves, in
     if (grid > ntiles) grid = static_cast<int>(ntiles);
     return dim == 2 ? launch_persistent_d<2>(kind, kmax, waves, grid, pl.total, a, p, stream)
                     : launch_persistent_d<3>(kind, kmax, waves, grid, pl.total, a, p, stream);
+}
+
+hipError_t launch_apply_persistent(int dim, int kind, int kmax, int waves, int grid, ContractArgs a,
+                                   const PersistArgs& p, hipStream_t stream) {
+    if (a.cells <= 0) return hipSuccess;
+    if (kmax > 16 || waves != 16 || !a.xloc || a.n_dof <= 0 || a.n_I != a.n_dof * a.n_dof ||
+        16 * a.n_dof > 2 * 64 * kIoWaves)
+        return hipErrorInvalidValue;
+    const LdsPlan pl = plan_lds(dim, kind, 16, a.n_I, a.n_alpha, 0, false, kLdsBudget);
+    const size_t lds = pl.total + 2 * 16 * static_cast<size_t>(a.n_dof) * sizeof(double);  // + two x buffers
+    if (!pl.staged || lds > kLdsBudget || (1 + dim * dim + n_coeff_of(dim, kind)) * 16 > 64 * (waves - kIoWaves))
+        return hipErrorInvalidValue;
+    a.staged = 1;
+    a.stage_bytes = pl.stage_bytes;
+    a.head_bytes = pl.head_bytes;
+    const int64_t ntiles = (a.cells + 15) / 16;
+    if (grid > ntiles) grid = static_cast<int>(ntiles);
+    return dim == 2 ? launch_persistent_d<2, true>(kind, kmax, waves, grid, lds, a, p, stream)
+                    : launch_persistent_d<3, true>(kind, kmax, waves, grid, lds, a, p, stream);
+}
+
+size_t apply_lds_bytes(int dim, int kind, int tile_cells, int n_I, int n_alpha, int n_dof) {
+    const LdsPlan p = plan_lds(dim, kind, tile_cells, n_I, n_alpha, 0, false, ~size_t(0));
+    return p.total + align16(static_cast<size_t>(tile_cells) * n_dof * sizeof(double));
+}
+
+template <int D, int KIND>
+static hipError_t launch_apply_k(int tile_cells, unsigned grid, unsigned block, size_t lds, const ContractArgs& a,
+                                 hipStream_t s) {
+    switch (tile_cells) {
+    case 16: return launch_lds(apply_f64_kernel<D, KIND, 1>, grid, block, lds, s, a);
+    case 32: return launch_lds(apply_f64_kernel<D, KIND, 2>, grid, block, lds, s, a);
+    default: return launch_lds(apply_f64_kernel<D, KIND, 4>, grid, block, lds, s, a);
+    }
+}
+
+template <int D>
+static hipError_t launch_apply_d(int kind, int tile_cells, unsigned grid, unsigned block, size_t lds,
+                                 const ContractArgs& a, hipStream_t s) {
+    switch (kind) {
+    case K_MASS: return launch_apply_k<D, K_MASS>(tile_cells, grid, block, lds, a, s);
+    case K_LAPLACE: return launch_apply_k<D, K_LAPLACE>(tile_cells, grid, block, lds, a, s);
+    case K_WLAPLACE: return launch_apply_k<D, K_WLAPLACE>(tile_cells, grid, block, lds, a, s);
+    case K_ELASTICITY: return launch_apply_k<D, K_ELASTICITY>(tile_cells, grid, block, lds, a, s);
+    default: return launch_apply_k<D, K_NS>(tile_cells, grid, block, lds, a, s);
+    }
+}
+
+hipError_t launch_apply(int dim, int kind, int tile_cells, int waves, ContractArgs a, hipStream_t stream) {
+    if (a.cells <= 0) return hipSuccess;
+    if (!a.xloc || a.n_dof <= 0 || a.n_I != a.n_dof * a.n_dof || waves < 1 || waves > 16 ||
+        (tile_cells != 16 && tile_cells != 32 && tile_cells != 64))
+        return hipErrorInvalidValue;
+    const LdsPlan p = plan_lds(dim, kind, tile_cells, a.n_I, a.n_alpha, 0, false, kLdsBudget);
+    const size_t lds = apply_lds_bytes(dim, kind, tile_cells, a.n_I, a.n_alpha, a.n_dof);
+    if (!p.staged || lds > kLdsBudget) return hipErrorInvalidValue;
+    a.staged = 1;
+    a.stage_bytes = p.stage_bytes;
+    a.head_bytes = p.head_bytes;
+    const unsigned grid = static_cast<unsigned>((a.cells + tile_cells - 1) / tile_cells);
+    const unsigned block = 64u * waves;
+    return dim == 2 ? launch_apply_d<2>(kind, tile_cells, grid, block, lds, a, stream)
+                    : launch_apply_d<3>(kind, tile_cells, grid, block, lds, a, stream);
 }
 
 // ------------------------------------------------ persistent split-BF16 contraction ---

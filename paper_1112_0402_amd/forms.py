@@ -99,6 +99,30 @@ class Form:
         capi.check(capi.lib().ffc_tabulate_tensor_affine(self._h, cells, _ptr(affine_map), _ptr(coeffs), _ptr(out)))
         return out
 
+    def apply(self, coords: torch.Tensor, x: torch.Tensor, coeffs: torch.Tensor | None = None,
+              y: torch.Tensor | None = None) -> torch.Tensor:
+        """Operator action y_K = A^K x_K per cell (x, y: [cells, n] FP64), without writing
+        the element tensors; FP64 tensor-kernel forms."""
+        d = self.dim
+        _check_tensor("coords", coords, torch.float64)
+        if coords.dim() != 2 or coords.shape[0] != (d + 1) * d:
+            raise ValueError(f"coords must be [(d+1)*d, cells] = [{(d + 1) * d}, cells]")
+        cells, n = coords.shape[1], self.info["n_dofs"]
+        if self.info["n_coeffs"]:
+            if coeffs is None:
+                raise ValueError(f"form {self.kind} needs coefficients [{self.info['n_coeffs']}, cells]")
+            _check_tensor("coeffs", coeffs, torch.float64, (self.info["n_coeffs"], cells))
+        _check_tensor("x", x, torch.float64)
+        if x.numel() != cells * n:
+            raise ValueError(f"x must hold [cells, n] = [{cells}, {n}] values")
+        if y is None:
+            y = torch.empty((cells, n), dtype=torch.float64, device=coords.device)
+        _check_tensor("y", y, torch.float64)
+        if y.numel() != cells * n:
+            raise ValueError("y has the wrong number of entries")
+        capi.check(capi.lib().ffc_apply_tensor(self._h, cells, _ptr(coords), _ptr(coeffs), _ptr(x), _ptr(y)))
+        return y
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             capi.lib().ffc_form_destroy(self._h)
@@ -204,6 +228,30 @@ class Assembly:
         capi.check(capi.lib().ffc_assemble(self._h, _ptr(tensors), 8 if tensors.dtype == torch.float64 else 4,
                                            _ptr(values), 1 if accumulate else 0))
         return values
+
+    def apply(self, form: "Form", coords: torch.Tensor, x: torch.Tensor, coeffs: torch.Tensor | None = None,
+              y: torch.Tensor | None = None, work: torch.Tensor | None = None) -> torch.Tensor:
+        """Matrix-free y = A x (x, y: [n_rows] FP64) for the matrix `form` would assemble on
+        this mesh; work: optional scratch of 2 * cells * n_local doubles."""
+        _check_tensor("coords", coords, torch.float64)
+        if coords.dim() != 2 or coords.shape[1] != self.cells:
+            raise ValueError(f"coords must be [(d+1)*d, {self.cells}]")
+        if form.info["n_coeffs"]:
+            if coeffs is None:
+                raise ValueError(f"form {form.kind} needs coefficients")
+            _check_tensor("coeffs", coeffs, torch.float64, (form.info["n_coeffs"], self.cells))
+        _check_tensor("x", x, torch.float64, (self.n_rows,))
+        if y is None:
+            y = torch.empty(self.n_rows, dtype=torch.float64, device="cuda")
+        _check_tensor("y", y, torch.float64, (self.n_rows,))
+        if work is None:
+            work = torch.empty(2 * self.cells * self.n_local, dtype=torch.float64, device="cuda")
+        _check_tensor("work", work, torch.float64)
+        if work.numel() < 2 * self.cells * self.n_local:
+            raise ValueError("work holds fewer than 2 * cells * n_local doubles")
+        capi.check(capi.lib().ffc_operator_apply(self._h, form._h, _ptr(coords), _ptr(coeffs), _ptr(x), _ptr(y),
+                                                 _ptr(work)))
+        return y
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
