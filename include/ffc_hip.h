@@ -12,7 +12,7 @@
  *   1. a geometry kernel, one lane per cell, FP64: coords -> (det J, J^{-1});
  *   2. a contraction kernel: G_K tile built in LDS, A^0 tiles on the matrix cores
  *      (MFMA), cells x |alpha| times |alpha| x |i| -- the level-3 BLAS batching the
- *      paper proposes (Sec. 4.5, "Optimization");
+ *      paper proposes (Sec. 3.5, "Optimization");
  * and, as the in-GPU comparison, a plain quadrature kernel (pretabulated basis at the
  * points of a collapsed-coordinate Gauss-Jacobi rule exact for the integrand, Sec. 6).
  *
@@ -199,7 +199,7 @@ int ffc_apply_tensor(const ffc_form* form, int64_t cells, const double* coords, 
 int ffc_compute_geometry(int32_t dim, int64_t cells, const double* coords, double* affine_map, void* stream);
 
 /* Mixed batches (many meshes of uneven size, mixed forms and degrees; the level-3 BLAS
- * batching of Sec. 4.5 taken across meshes).  A batch is built from `n` (form, cells,
+ * batching of Sec. 3.5 taken across meshes).  A batch is built from `n` (form, cells,
  * coords, coeffs, out) items; all forms must share one precision and use the tensor
  * kernel.  ffc_batch_run enqueues a fixed, short sequence of launches on `stream` (fit
  * for graph capture; no memset, no allocation):
@@ -221,7 +221,7 @@ int ffc_batch_run(ffc_batch* batch);
 int ffc_batch_info(const ffc_batch* batch, int64_t* total_cells, int64_t* work_units, int32_t* launches);
 void ffc_batch_destroy(ffc_batch* batch);
 
-/* Global assembly (Sec. 2.3: the element-by-element algorithm, Algorithm 2's insertion
+/* Global assembly (Sec. 2.2: the element-by-element algorithm, Algorithm 2's insertion
  * step): A = sum over cells K of P_K^T A^K P_K into a CSR matrix, with the same
  * local-to-global map for test and trial functions.
  *

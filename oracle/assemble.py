@@ -1,7 +1,7 @@
 """Oracle for global assembly -- TEST INFRASTRUCTURE ONLY (tests, smoke() and the bench's
 CPU baseline use it; the library never does).
 
-The plain definition of the element-by-element algorithm (Sec. 2.3, Algorithms 1 and 2):
+The plain definition of the element-by-element algorithm (Sec. 2.2, Algorithms 1 and 2):
 A = sum over cells K of P_K^T A^K P_K, i.e. every element-tensor entry A^K_{ij} added to
 the global entry (iota(K, i), iota(K, j)).  Written as a coordinate list summed by
 scipy.sparse (a library primitive: duplicates are added on conversion to CSR)."""

@@ -1,5 +1,5 @@
 // Global assembly: the insertion step of the element-by-element assembly algorithm
-// (Sec. 2.3, Algorithm 2), A = sum over cells K of P_K^T A^K P_K, into a CSR matrix.
+// (Sec. 2.2, Algorithm 2), A = sum over cells K of P_K^T A^K P_K, into a CSR matrix.
 #pragma once
 
 #include <hip/hip_runtime.h>

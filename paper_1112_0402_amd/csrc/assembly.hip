@@ -1,4 +1,4 @@
-// Global assembly of element tensors into a CSR matrix (Sec. 2.3, Algorithm 2's insertion
+// Global assembly of element tensors into a CSR matrix (Sec. 2.2, Algorithm 2's insertion
 // step).  Symbolic phase once per mesh: the pattern and, per matrix row, the element-tensor
 // rows landing in it, on the host; every element entry's CSR index on the GPU.  Numeric
 // phase: a row gather (one wave per matrix row, no atomics, fixed summation order).

@@ -8,7 +8,7 @@
 //                      v_mfma_f64_16x16x4f64: M = 16 cells, N = 16 output entries,
 //                      K = the alpha columns of A^0 that are nonzero in those 16 rows
 //                      (zero entries of A^0 are skipped, Sec. 6; batching cells turns the
-//                      per-cell matrix-vector product into a matrix-matrix product, Sec. 4.5)
+//                      per-cell matrix-vector product into a matrix-matrix product, Sec. 3.5)
 //  contract_bf16       the same with G and A^0 split into BF16 pieces, concatenated along
 //                      K, on v_mfma_f32_16x16x32_bf16 with FP32 accumulation
 //  quadrature_kernel   plain quadrature (Sec. 4.3 / Sec. 6): per cell, physical basis
