@@ -127,3 +127,20 @@ def basis(dim: int, degree: int, X) -> tuple[np.ndarray, np.ndarray]:
     dphi = np.zeros((npts, nn, dim))
     lib().oracle_basis(dim, degree, npts, _dp(X), _dp(phi), _dp(dphi))
     return phi, dphi
+
+
+def source_vector(dim: int, degree: int, coords, f) -> np.ndarray:
+    """Element vectors of the linear form L(v) = int_K f v dx (the right-hand side of the
+    Poisson form file, Sec. 5.5), f in the same Lagrange P_q space as v given by its nodal
+    values f [cells, n] in the dof order: b[c, i] = sum_q w_q |det J| phi_i(X_q) f(X_q) on the
+    physical cell (affine map of Sec. 3.2), with a collapsed rule exact for degree 2q."""
+    coords = np.ascontiguousarray(coords, dtype=np.float64)
+    cells = coords.shape[1]
+    f = np.asarray(f, dtype=np.float64).reshape(cells, -1)
+    X = coords.reshape(dim + 1, dim, cells)          # [vertex][component][cell]
+    J = np.transpose(X[1:] - X[0], (2, 1, 0))        # [cell][k][b] = x^{b+1}_k - x^0_k
+    adet = np.abs(np.linalg.det(J))
+    pts, wts = simplex_rule(dim, degree + 2)
+    phi, _ = basis(dim, degree, pts)                 # [point][dof]
+    fq = f @ phi.T                                   # f at the points, [cell][point]
+    return adet[:, None] * ((fq * wts) @ phi)

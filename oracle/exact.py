@@ -280,3 +280,14 @@ def element_tensor(kind, verts, degree, coeffs=None, lam_=1, mu=1):
                     A[c1 * ns + s1][c1 * ns + s2] = val
         return A
     raise ValueError(kind)
+
+
+def source_vector(verts, degree, fvals):
+    """Exact element vector of L(v) = int_K f v dx for f = sum_a f_a phi_a in the same P_q
+    space (nodal values f_a in the dof order): b_i = int_K phi_i f, as Fractions."""
+    K = Cell(verts)
+    basis = basis_polys(K.d, degree)
+    fp = {}
+    for a, fa in enumerate(fvals):
+        fp = padd(fp, basis[a], Fraction(fa))
+    return [K.integrate(pmul(basis[i], fp)) for i in range(len(basis))]

@@ -190,6 +190,23 @@ class Batch:
             pass
 
 
+class SourceForm:
+    """The linear form L(v) = int f v dx with f in the same Lagrange P_q space as v (the
+    right-hand side of the Poisson form file, Sec. 5.5).  Its tensor representation is
+    b_K,i = A^0_{ia} G_K,a with A^0_{ia} = int_K0 Phi_i Phi_a and G_K,a = |det J| f_a: the mass
+    form's reference tensor contracted with the cell's f dofs, so b_K is the mass form's
+    operator action on f_K (ffc_apply_tensor), and the assembled load vector is
+    Assembly.apply(form.mass, coords, f)."""
+
+    def __init__(self, dim, degree, stream=None):
+        self.dim, self.degree = dim, degree
+        self.mass = Form("mass", dim, degree, stream=stream)
+
+    def tabulate(self, coords: torch.Tensor, f_local: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Element vectors [cells, n] from the nodal values of f on each cell [cells, n]."""
+        return self.mass.apply(coords, f_local, y=out)
+
+
 class Assembly:
     """Global assembly into CSR (the insertion step of Algorithm 2): the pattern and the
     CSR index of every element-tensor entry are built once from a local-to-global map."""
