@@ -67,8 +67,16 @@ typedef enum {
  *  FFC_WLAPLACE      int w grad v . grad u, w in P1       (variable-coefficient diffusion, Sec. 3.1)
  *  FFC_ELASTICITY    int sigma(u) : eps(v), sigma = 2 mu eps + lambda tr(eps) I, vector P_q
  *                    (test case 4; the paper's strain-strain term is mu = 1/2, lambda = 0)
- *  FFC_NS_CONVECTION int v . ((w . grad) u), u, v vector P_q, w vector P1 (test case 3) */
-typedef enum { FFC_MASS = 0, FFC_LAPLACE = 1, FFC_WLAPLACE = 2, FFC_ELASTICITY = 3, FFC_NS_CONVECTION = 4 } ffc_kind;
+ *  FFC_NS_CONVECTION int v . ((w . grad) u), u, v vector P_q, w vector P1 (test case 3)
+ *  FFC_PIOLA_MASS    int v . u for Raviart-Thomas functions of the lowest order mapped by
+ *                    the contravariant Piola transform (the H(div) example of Sec. 3.4):
+ *                    degree 1 only; d + 1 dofs, reference basis Psi_i = (X - V_i) / (d |K0|)
+ *                    (unit flux through the facet opposite vertex i); A^0 = int Psi_i,a1
+ *                    Psi_j,a2, G^{a1 a2} = (1 / |det J|) (J^T J)_{a1 a2}; tensor kernel only
+ *                    (no quadrature kernel, no batches) */
+typedef enum {
+    FFC_MASS = 0, FFC_LAPLACE = 1, FFC_WLAPLACE = 2, FFC_ELASTICITY = 3, FFC_NS_CONVECTION = 4, FFC_PIOLA_MASS = 5
+} ffc_kind;
 
 /* Arithmetic of the contraction.  FP64: FP64 MFMA, FP64 output.  Split modes: G and A^0
  * are split into BF16 pieces (hi = RN(x), lo = RN(x - hi), [lo2 = RN(x - hi - lo)]) with

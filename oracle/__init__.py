@@ -17,6 +17,7 @@ tensor of a multilinear form, Sec. 3.1):
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -144,3 +145,20 @@ def source_vector(dim: int, degree: int, coords, f) -> np.ndarray:
     phi, _ = basis(dim, degree, pts)                 # [point][dof]
     fq = f @ phi.T                                   # f at the points, [cell][point]
     return adet[:, None] * ((fq * wts) @ phi)
+
+
+def piola_mass(dim: int, coords) -> np.ndarray:
+    """Mass matrices [cells, d+1, d+1] of the lowest-order Raviart-Thomas space (the H(div)
+    example of Sec. 3.4), written on the physical cell: basis psi_i(x) = (x - x^i) / (d |K|),
+    the field of unit flux through the facet opposite vertex i, M_ij = int_K psi_i . psi_j dx
+    by a collapsed rule exact for degree 2, mapped to K (weights |det J|)."""
+    coords = np.ascontiguousarray(coords, dtype=np.float64)
+    cells = coords.shape[1]
+    X = coords.reshape(dim + 1, dim, cells)          # [vertex][component][cell]
+    J = np.transpose(X[1:] - X[0], (2, 1, 0))        # [cell][k][b] = x^{b+1}_k - x^0_k
+    adet = np.abs(np.linalg.det(J))
+    vol = adet / math.factorial(dim)
+    pts, wts = simplex_rule(dim, 3)
+    xq = X[0].T[:, None, :] + np.einsum("ckb,qb->cqk", J, pts)          # [cell][point][k]
+    psi = (xq[:, None, :, :] - np.transpose(X, (2, 0, 1))[:, :, None, :]) / (dim * vol)[:, None, None, None]
+    return np.einsum("ciqk,cjqk,q->cij", psi, psi, wts) * adet[:, None, None]

@@ -291,3 +291,26 @@ def source_vector(verts, degree, fvals):
     for a, fa in enumerate(fvals):
         fp = padd(fp, basis[a], Fraction(fa))
     return [K.integrate(pmul(basis[i], fp)) for i in range(len(basis))]
+
+
+def piola_mass(verts):
+    """Exact lowest-order Raviart-Thomas mass matrix on a rational cell: psi_i =
+    (x - x^i) / (d |K|) with x = sum_v lambda_v x^v, M_ij = int_K psi_i . psi_j, as Fractions."""
+    K = Cell(verts)
+    d = K.d
+    vol = K.absdet / factorial(d)
+    comp = [[{} for _ in range(d)] for _ in range(d + 1)]  # comp[i][k] = x_k - x^i_k
+    for i in range(d + 1):
+        for k in range(d):
+            p = {}
+            for v in range(d + 1):
+                p = padd(p, lam(d, v), K.verts[v][k] - K.verts[i][k])
+            comp[i][k] = p
+    M = [[Fraction(0)] * (d + 1) for _ in range(d + 1)]
+    for i in range(d + 1):
+        for j in range(d + 1):
+            s = Fraction(0)
+            for k in range(d):
+                s += K.integrate(pmul(comp[i][k], comp[j][k]))
+            M[i][j] = s / (d * vol) ** 2
+    return M

@@ -85,6 +85,8 @@ int check_desc(const ffc_form_desc* d, ffc::FormSpec* spec) {
         return fail(FFC_E_UNSUPPORTED, "unknown kernel");
     if (d->kernel == FFC_KERNEL_QUADRATURE && d->precision != FFC_FP64)
         return fail(FFC_E_UNSUPPORTED, "the quadrature kernel is FP64 only");
+    if (d->kernel == FFC_KERNEL_QUADRATURE && d->kind == FFC_PIOLA_MASS)
+        return fail(FFC_E_UNSUPPORTED, "the quadrature kernel evaluates Lagrange forms only");
     if (d->tile_cells != 0 && !valid_tile(d->tile_cells)) return fail(FFC_E_INVALID, "tile_cells must be 0, 16, 32 or 64");
     if (d->waves != 0 && !valid_waves(d->waves)) return fail(FFC_E_INVALID, "waves must be 0, 1, 2, 4, 8 or 16");
     if (d->geometry < 0 || d->geometry > FFC_GEOMETRY_FUSED) return fail(FFC_E_INVALID, "geometry must be 0, 1 or 2");
@@ -641,6 +643,7 @@ int ffc_batch_create(int32_t n, const ffc_form* const* forms, const int64_t* cel
         const ffc_form* f = forms[i];
         if (!f) return fail(FFC_E_INVALID, "NULL form in batch");
         if (f->desc.kernel != FFC_KERNEL_TENSOR) return fail(FFC_E_UNSUPPORTED, "batches use the tensor kernel only");
+        if (f->desc.kind == FFC_PIOLA_MASS) return fail(FFC_E_UNSUPPORTED, "batches take Lagrange forms only");
         const bool bf = f->desc.precision != FFC_FP64;
         if (i == 0) {
             bf16 = bf;

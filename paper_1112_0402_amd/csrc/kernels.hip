@@ -28,7 +28,7 @@ typedef double d2v __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-enum { K_MASS = 0, K_LAPLACE = 1, K_WLAPLACE = 2, K_ELASTICITY = 3, K_NS = 4 };
+enum { K_MASS = 0, K_LAPLACE = 1, K_WLAPLACE = 2, K_ELASTICITY = 3, K_NS = 4, K_PIOLA = 5 };
 
 // Launch with `lds` bytes of dynamic LDS; above 64 KiB the per-kernel limit is raised
 // first (gfx950 has 160 KiB per CU).
@@ -60,6 +60,7 @@ struct FormTraits {
                                  : KIND == K_LAPLACE ? D * (D + 1) / 2
                                  : KIND == K_WLAPLACE ? (D + 1) * D * (D + 1) / 2
                                  : KIND == K_ELASTICITY ? D * D * (D * D + 1) / 2
+                                 : KIND == K_PIOLA ? D * (D + 1) / 2
                                                         : D * (D + 1) * D;
     static constexpr int n_coeff = KIND == K_WLAPLACE ? D + 1 : KIND == K_NS ? D * (D + 1) : 0;
 };
@@ -165,6 +166,22 @@ __device__ __forceinline__ double g_entry(const double* am, const double* cf, in
 #pragma unroll
         for (int k = 0; k < D; ++k) s += g(a, k) * g(b, k);
         return cf[t * CT + c] * adet * s;
+    } else if constexpr (KIND == K_PIOLA) {  // alpha = pair (a, b), a <= b
+        // G = (J^T J)_ab / |det J| with J = g^{-1} = det J adj(g): G = |det J| sum_k adj_ka adj_kb
+        int a, b;
+        upper_pair<D>(alpha, a, b);
+        auto adj = [&](int k, int m) -> double {  // adj(g)_km = cofactor (m, k) of g
+            if constexpr (D == 2) {
+                return k == m ? g(1 - m, 1 - k) : -g(k, m);
+            } else {
+                const int m1 = (m + 1) % 3, m2 = (m + 2) % 3, k1 = (k + 1) % 3, k2 = (k + 2) % 3;
+                return g(m1, k1) * g(m2, k2) - g(m1, k2) * g(m2, k1);
+            }
+        };
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) s += adj(k, a) * adj(k, b);
+        return adet * s;
     } else if constexpr (KIND == K_ELASTICITY) {  // alpha = pair (a*D + j, b*D + l)
         int u, v;
         upper_pair<D * D>(alpha, u, v);
@@ -444,6 +461,7 @@ static hipError_t launch_f64_d(int kind, int tile_cells, int waves, size_t lds, 
     case K_LAPLACE: return launch_f64_mt<D, K_LAPLACE>(tile_cells, waves, lds, a, s);
     case K_WLAPLACE: return launch_f64_mt<D, K_WLAPLACE>(tile_cells, waves, lds, a, s);
     case K_ELASTICITY: return launch_f64_mt<D, K_ELASTICITY>(tile_cells, waves, lds, a, s);
+    case K_PIOLA: return launch_f64_mt<D, K_PIOLA>(tile_cells, waves, lds, a, s);
     default: return launch_f64_mt<D, K_NS>(tile_cells, waves, lds, a, s);
     }
 }
@@ -581,6 +599,7 @@ static hipError_t launch_bf16_d(int kind, int tile_cells, int waves, size_t lds,
     case K_LAPLACE: return launch_bf16_mt<D, K_LAPLACE, NSEG>(tile_cells, waves, lds, a, s);
     case K_WLAPLACE: return launch_bf16_mt<D, K_WLAPLACE, NSEG>(tile_cells, waves, lds, a, s);
     case K_ELASTICITY: return launch_bf16_mt<D, K_ELASTICITY, NSEG>(tile_cells, waves, lds, a, s);
+    case K_PIOLA: return launch_bf16_mt<D, K_PIOLA, NSEG>(tile_cells, waves, lds, a, s);
     default: return launch_bf16_mt<D, K_NS, NSEG>(tile_cells, waves, lds, a, s);
     }
 }
@@ -927,6 +946,7 @@ static hipError_t launch_persistent_d(int kind, int kmax, int waves, int grid, s
     case K_LAPLACE: return launch_persistent_k<D, K_LAPLACE, ACT>(kmax, waves, grid, lds, a, p, s);
     case K_WLAPLACE: return launch_persistent_k<D, K_WLAPLACE, ACT>(kmax, waves, grid, lds, a, p, s);
     case K_ELASTICITY: return launch_persistent_k<D, K_ELASTICITY, ACT>(kmax, waves, grid, lds, a, p, s);
+    case K_PIOLA: return hipErrorInvalidValue;  // tiny tensors: tile kernels only
     default: return launch_persistent_k<D, K_NS, ACT>(kmax, waves, grid, lds, a, p, s);
     }
 }
@@ -992,6 +1012,7 @@ static hipError_t launch_apply_d(int kind, int tile_cells, unsigned grid, unsign
     case K_LAPLACE: return launch_apply_k<D, K_LAPLACE>(tile_cells, grid, block, lds, a, s);
     case K_WLAPLACE: return launch_apply_k<D, K_WLAPLACE>(tile_cells, grid, block, lds, a, s);
     case K_ELASTICITY: return launch_apply_k<D, K_ELASTICITY>(tile_cells, grid, block, lds, a, s);
+    case K_PIOLA: return launch_apply_k<D, K_PIOLA>(tile_cells, grid, block, lds, a, s);
     default: return launch_apply_k<D, K_NS>(tile_cells, grid, block, lds, a, s);
     }
 }
@@ -1247,6 +1268,7 @@ static hipError_t launch_bf16_persistent_d(int kind, int mt, int ks, int grid, s
     case K_LAPLACE: return launch_bf16_persistent_k<D, K_LAPLACE, NSEG>(mt, ks, grid, lds, a, s);
     case K_WLAPLACE: return launch_bf16_persistent_k<D, K_WLAPLACE, NSEG>(mt, ks, grid, lds, a, s);
     case K_ELASTICITY: return launch_bf16_persistent_k<D, K_ELASTICITY, NSEG>(mt, ks, grid, lds, a, s);
+    case K_PIOLA: return hipErrorInvalidValue;
     default: return launch_bf16_persistent_k<D, K_NS, NSEG>(mt, ks, grid, lds, a, s);
     }
 }
@@ -1653,6 +1675,7 @@ static hipError_t launch_quad_d(int kind, const QuadArgs& a, hipStream_t s) {
 
 hipError_t launch_quadrature(int dim, int kind, const QuadArgs& a, hipStream_t stream) {
     if (a.cells <= 0) return hipSuccess;
+    if (kind == K_PIOLA) return hipErrorInvalidValue;  // Lagrange forms only
     return dim == 2 ? launch_quad_d<2>(kind, a, stream) : launch_quad_d<3>(kind, a, stream);
 }
 

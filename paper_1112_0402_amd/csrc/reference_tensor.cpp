@@ -197,6 +197,7 @@ int integrand_degree(int kind, int q) {
     case WLAPLACE: return 2 * q - 1;
     case ELASTICITY: return 2 * q - 2;
     case NS: return 2 * q;
+    case PIOLA: return 2;
     }
     return 2 * q;
 }
@@ -206,8 +207,12 @@ bool supported(const FormSpec& s, std::string* why) {
         *why = "dim must be 2 or 3";
         return false;
     }
-    if (s.kind < MASS || s.kind > NS) {
+    if (s.kind < MASS || s.kind > PIOLA) {
         *why = "unknown form kind";
+        return false;
+    }
+    if (s.kind == PIOLA && s.degree != 1) {
+        *why = "Raviart-Thomas elements of the lowest order only (degree 1)";
         return false;
     }
     int qmax = (s.kind == ELASTICITY || s.kind == NS) ? 3 : 4;
@@ -262,7 +267,7 @@ bool build_reference_tensor(const FormSpec& s, ReferenceTensor* rt, std::string*
     rt->spec = s;
     rt->ns = B.n;
     const bool vec = (s.kind == ELASTICITY || s.kind == NS);
-    rt->n = vec ? d * B.n : B.n;
+    rt->n = vec ? d * B.n : B.n;  // (PIOLA: the d + 1 vertices of P1 are also its d + 1 facets)
     rt->n_I = rt->n * rt->n;
     switch (s.kind) {
     case MASS: rt->n_alpha = 1; rt->n_coeff = 0; break;
@@ -270,6 +275,7 @@ bool build_reference_tensor(const FormSpec& s, ReferenceTensor* rt, std::string*
     case WLAPLACE: rt->n_alpha = (d + 1) * d * d; rt->n_coeff = d + 1; break;
     case ELASTICITY: rt->n_alpha = d * d * d * d; rt->n_coeff = 0; break;
     case NS: rt->n_alpha = d * (d + 1) * d; rt->n_coeff = d * (d + 1); break;
+    case PIOLA: rt->n_alpha = d * d; rt->n_coeff = 0; break;
     }
     const int ns = B.n, n = rt->n, na = rt->n_alpha;
     std::vector<ld> A(static_cast<size_t>(rt->n_I) * na, 0);
@@ -319,6 +325,22 @@ bool build_reference_tensor(const FormSpec& s, ReferenceTensor* rt, std::string*
                                         at(c1 * ns + s1, c2 * ns + s2, ((a * d + j) * d + b) * d + l) =
                                             c * L[((s1 * ns + s2) * d + a) * d + b];
                                     }
+    } else if (s.kind == PIOLA) {
+        // Psi_i = (X - V_i) / (d |K0|) = (d-1)! (X - V_i), V_0 = 0, V_k = e_k;
+        // A^0[(i,j)][(a1,a2)] = int_K0 Psi_i,a1 Psi_j,a2
+        auto psi = [&](int i, int a) {
+            Poly p;
+            std::array<int, 3> e{0, 0, 0};
+            e[a] = 1;
+            const ld c = factorial(d - 1);
+            p[key_of(e)] = c;
+            if (i > 0 && i - 1 == a) p[0] -= c;
+            return p;
+        };
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j)
+                for (int a1 = 0; a1 < d; ++a1)
+                    for (int a2 = 0; a2 < d; ++a2) at(i, j, a1 * d + a2) = integrate(mul(psi(i, a1), psi(j, a2)), d);
     } else if (s.kind == NS) {
         // A^0[(c1,s1),(c2,s2)][(k,t,a)] = delta_{c1 c2} int Phi_s1 psi_t dPhi_s2/dX_a
         for (int t = 0; t <= d; ++t) {
@@ -352,6 +374,7 @@ bool build_reference_tensor(const FormSpec& s, ReferenceTensor* rt, std::string*
 int folded_n_alpha(int kind, int d) {
     switch (kind) {
     case LAPLACE: return d * (d + 1) / 2;
+    case PIOLA: return d * (d + 1) / 2;
     case WLAPLACE: return (d + 1) * d * (d + 1) / 2;
     case ELASTICITY: return d * d * (d * d + 1) / 2;
     case MASS: return 1;
@@ -361,7 +384,7 @@ int folded_n_alpha(int kind, int d) {
 
 ReferenceTensor fold_symmetric_g(const ReferenceTensor& rt) {
     const int kind = rt.spec.kind, d = rt.spec.dim;
-    if (kind != LAPLACE && kind != WLAPLACE && kind != ELASTICITY) return rt;
+    if (kind != LAPLACE && kind != WLAPLACE && kind != ELASTICITY && kind != PIOLA) return rt;
     // pair index space: N indices per side, `outer` independent copies (weight dofs)
     const int N = kind == ELASTICITY ? d * d : d;
     const int outer = kind == WLAPLACE ? d + 1 : 1;

@@ -148,8 +148,8 @@ def compute_geometry(coords: torch.Tensor, dim: int, out: torch.Tensor | None = 
 
 class Batch:
     """Many (form, mesh) items evaluated by a short fixed sequence of launches: one
-    persistent launch for the large FP64 element tensors (after their geometry passes)
-    and one tile launch per group of the other items."""
+    persistent launch per form whose element tensors use a persistent kernel (after the
+    items' geometry passes) and one tile launch per group of the other items."""
 
     def __init__(self, forms, coords, coeffs, outs, stream=None):
         n = len(forms)
