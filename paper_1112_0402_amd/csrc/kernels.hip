@@ -873,23 +873,27 @@ __device__ __forceinline__ void persistent_tiles(const ContractArgs& A, const Pe
             }
         }
         lds_barrier();
-        if (ACT && tid >= io_begin) {  // y = A^K x for this tile, straight to global memory
+        if constexpr (ACT) {  // y = A^K x for this tile, by every wave, straight to global memory
+            // lanes 2t and 2t + 1 sum the two halves of output t's dot product
             const double* xb = xs + xbuf * CT * nd;
-#pragma unroll
-            for (int r = 0; r < 2; ++r) {
-                const int t = io_lane + r * 64 * kIoWaves;
+            const int half = (nd + 1) >> 1;
+            const int h = tid & 1;
+            for (int t0 = 0; t0 < cur_n; t0 += blockDim.x >> 1) {
+                const int t = t0 + (tid >> 1);
+                double s = 0.0;
                 if (t < cur_n) {
                     const int c = t / nd, i1 = t - c * nd;
                     const double* row = st + c * nI + i1 * nd;
                     const double* xc = xb + c * nd;
-                    double s = 0.0;
-#pragma unroll 4
-                    for (int i2 = 0; i2 < nd; ++i2) s = fma(row[i2], xc[i2], s);
-                    cur_out[t] = s;
+                    const int e = h ? nd : half;
+#pragma unroll 1
+                    for (int i2 = h * half; i2 < e; ++i2) s = fma(row[i2], xc[i2], s);
                 }
+                s += __shfl_xor(s, 1);
+                if (t < cur_n && h == 0) cur_out[t] = s;
             }
             xbuf ^= 1;
-        } else if (!ACT && tid >= io_begin) {  // take this tile's rows into registers; st is free after the next barrier
+        } else if (tid >= io_begin) {  // take this tile's rows into registers; st is free after the next barrier
             io_out = cur_out;
             io_n = cur_n;
             const int64_t nv = io_n / 2;
