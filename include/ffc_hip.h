@@ -73,9 +73,21 @@ typedef enum {
  *                    degree 1 only; d + 1 dofs, reference basis Psi_i = (X - V_i) / (d |K0|)
  *                    (unit flux through the facet opposite vertex i); A^0 = int Psi_i,a1
  *                    Psi_j,a2, G^{a1 a2} = (1 / |det J|) (J^T J)_{a1 a2}; tensor kernel only
- *                    (no quadrature kernel, no batches) */
+ *                    (no quadrature kernel, no batches)
+ *  FFC_CURVED_LAPLACE int grad u . grad v, u, v in P_q (q = 1, 2), on cells mapped by P2
+ *                    geometry (the curvilinear elements of Sec. 3.4): the Jacobian varies
+ *                    inside the cell, so the integral becomes a sum over the points X_p of a
+ *                    collapsed Gauss-Jacobi rule with q + 1 points per direction, contracted as
+ *                    A^0[(i1,i2)][(p,a,b)] = w_p dPhi_i1/dX_a dPhi_i2/dX_b (X_p) with
+ *                    G_K[(p,a,b)] = |det J(X_p)| (g g^T)_ab(X_p) (pairs a <= b, b's summed
+ *                    into A^0).  coords: SoA [n_geo * d][cells] with the n_geo = 6 (d = 2)
+ *                    or 10 (d = 3) P2 nodes of each cell in the P2 dof order below; a
+ *                    geometry kernel writes G per point into the form's workspace, then the
+ *                    FP64 tile contraction reads it.  FP64 tensor kernel only (no quadrature
+ *                    kernel, split modes, batches, operator action or affine-map entry). */
 typedef enum {
-    FFC_MASS = 0, FFC_LAPLACE = 1, FFC_WLAPLACE = 2, FFC_ELASTICITY = 3, FFC_NS_CONVECTION = 4, FFC_PIOLA_MASS = 5
+    FFC_MASS = 0, FFC_LAPLACE = 1, FFC_WLAPLACE = 2, FFC_ELASTICITY = 3, FFC_NS_CONVECTION = 4, FFC_PIOLA_MASS = 5,
+    FFC_CURVED_LAPLACE = 6
 } ffc_kind;
 
 /* Arithmetic of the contraction.  FP64: FP64 MFMA, FP64 output.  Split modes: G and A^0

@@ -162,3 +162,51 @@ def piola_mass(dim: int, coords) -> np.ndarray:
     xq = X[0].T[:, None, :] + np.einsum("ckb,qb->cqk", J, pts)          # [cell][point][k]
     psi = (xq[:, None, :, :] - np.transpose(X, (2, 0, 1))[:, :, None, :]) / (dim * vol)[:, None, None, None]
     return np.einsum("ciqk,cjqk,q->cij", psi, psi, wts) * adet[:, None, None]
+
+
+def collapsed_rule(dim: int, m: int):
+    """Collapsed Gauss-Jacobi rule on the reference simplex, m points per direction: the
+    direction collapsed k times carries the Jacobi weight (1 - s)^k on [0, 1] (scipy's
+    Gauss-Jacobi nodes on [-1, 1] mapped to [0, 1]).  Exact for degree 2m - 1."""
+    from scipy.special import roots_jacobi
+
+    rules = []
+    for a in range(dim):
+        t, w = roots_jacobi(m, a, 0)
+        rules.append(((1.0 + t) / 2.0, w / 2.0 ** (a + 1)))
+    pts, wts = [], []
+    if dim == 2:
+        for i in range(m):
+            for j in range(m):
+                s1, s2 = rules[0][0][i], rules[1][0][j]
+                pts.append((s1 * (1 - s2), s2))
+                wts.append(rules[0][1][i] * rules[1][1][j])
+    else:
+        for i in range(m):
+            for j in range(m):
+                for k in range(m):
+                    s1, s2, s3 = rules[0][0][i], rules[1][0][j], rules[2][0][k]
+                    pts.append((s1 * (1 - s2) * (1 - s3), s2 * (1 - s3), s3))
+                    wts.append(rules[0][1][i] * rules[1][1][j] * rules[2][1][k])
+    return np.array(pts), np.array(wts)
+
+
+def curved_laplace(dim: int, degree: int, coords, m: int | None = None) -> np.ndarray:
+    """Element matrices [cells, n, n] of int grad u . grad v on cells with P2 geometry (the
+    curvilinear elements of Sec. 3.4): x(X) = sum_k x_k Psi_k(X) over the P2 nodes, and the
+    integral taken as the sum over the points of the collapsed rule with m = degree + 1
+    points per direction, w_p |det J| (J^{-T} grad Phi_i) . (J^{-T} grad Phi_j) at X_p.
+    coords: SoA [n_geo * d][cells], nodes in the P2 dof order."""
+    coords = np.ascontiguousarray(coords, dtype=np.float64)
+    cells = coords.shape[1]
+    m = degree + 1 if m is None else m
+    pts, wts = collapsed_rule(dim, m)
+    _, dpsi = basis(dim, 2, pts)          # [p][k][b]
+    _, dphi = basis(dim, degree, pts)     # [p][i][b]
+    ng = dpsi.shape[1]
+    x = coords.reshape(ng, dim, cells)    # [k][j][c]
+    J = np.einsum("kjc,pkb->cpjb", x, dpsi)
+    det = np.linalg.det(J)                # [c][p]
+    Jinv = np.linalg.inv(J)               # [c][p][b][j]
+    grad = np.einsum("cpbj,pib->cpij", Jinv, dphi)   # physical gradients [c][p][i][j]
+    return np.einsum("cpij,cpkj,p,cp->cik", grad, grad, wts, np.abs(det))

@@ -85,8 +85,10 @@ int check_desc(const ffc_form_desc* d, ffc::FormSpec* spec) {
         return fail(FFC_E_UNSUPPORTED, "unknown kernel");
     if (d->kernel == FFC_KERNEL_QUADRATURE && d->precision != FFC_FP64)
         return fail(FFC_E_UNSUPPORTED, "the quadrature kernel is FP64 only");
-    if (d->kernel == FFC_KERNEL_QUADRATURE && d->kind == FFC_PIOLA_MASS)
-        return fail(FFC_E_UNSUPPORTED, "the quadrature kernel evaluates Lagrange forms only");
+    if (d->kernel == FFC_KERNEL_QUADRATURE && (d->kind == FFC_PIOLA_MASS || d->kind == FFC_CURVED_LAPLACE))
+        return fail(FFC_E_UNSUPPORTED, "the quadrature kernel evaluates Lagrange forms on affine cells only");
+    if (d->kind == FFC_CURVED_LAPLACE && d->precision != FFC_FP64)
+        return fail(FFC_E_UNSUPPORTED, "the curvilinear Laplacian is FP64 only");
     if (d->tile_cells != 0 && !valid_tile(d->tile_cells)) return fail(FFC_E_INVALID, "tile_cells must be 0, 16, 32 or 64");
     if (d->waves != 0 && !valid_waves(d->waves)) return fail(FFC_E_INVALID, "waves must be 0, 1, 2, 4, 8 or 16");
     if (d->geometry < 0 || d->geometry > FFC_GEOMETRY_FUSED) return fail(FFC_E_INVALID, "geometry must be 0, 1 or 2");
@@ -134,6 +136,7 @@ struct ffc_form {
     uint32_t* d_wave_word = nullptr;
     uint32_t* d_wave_mask = nullptr;
     int32_t* d_zero = nullptr;
+    double* d_geo_grad = nullptr;  // curvilinear cells: geometry basis gradients at the points
 
     ~ffc_form() {
         for (void* p : {static_cast<void*>(d_koff), static_cast<void*>(d_apack), static_cast<void*>(d_entry),
@@ -142,7 +145,7 @@ struct ffc_form {
                         static_cast<void*>(d_wts), static_cast<void*>(d_phi), static_cast<void*>(d_dphi),
                         static_cast<void*>(d_amap), static_cast<void*>(d_woff),
                         static_cast<void*>(d_wave_b), static_cast<void*>(d_wave_word), static_cast<void*>(d_wave_mask),
-                        static_cast<void*>(d_zero)})
+                        static_cast<void*>(d_zero), static_cast<void*>(d_geo_grad)})
             if (p) (void)hipFree(p);
     }
 };
@@ -189,8 +192,9 @@ int ffc_form_create(const ffc_form_desc* desc, ffc_form** out) {
     // tensor kernels contract symmetric geometry tensors over unordered index pairs
     if (desc->kernel == FFC_KERNEL_TENSOR) {
         f->rt = ffc::fold_symmetric_g(f->rt);
-        if (f->rt.n_alpha != ffc::folded_n_alpha(spec.kind, spec.dim))
+        if (spec.kind != FFC_CURVED_LAPLACE && f->rt.n_alpha != ffc::folded_n_alpha(spec.kind, spec.dim))
             return fail(FFC_E_UNSUPPORTED, "internal: G entry count does not match the kernels");
+        if (spec.kind == FFC_CURVED_LAPLACE && (rc = upload(f->rt.geo_grad, &f->d_geo_grad))) return rc;
     }
     const ffc::ReferenceTensor& rt = f->rt;
     if (desc->kernel == FFC_KERNEL_QUADRATURE) {
@@ -222,8 +226,8 @@ int ffc_form_create(const ffc_form_desc* desc, ffc_form** out) {
         // persistent workgroups: 16 waves with up to 16 register-resident k steps each, or
         // 8 waves with up to 32; the 16-cell output rows must be stageable in LDS
         const ffc::LdsPlan pl = ffc::plan_lds(spec.dim, spec.kind, 16, rt.n_I, rt.n_alpha, 0, false, ffc::kLdsBudget);
-        const bool want_persistent =
-            desc->persistent == 1 || (desc->persistent == 0 && rt.n_I >= kPersistentMinEntries);
+        const bool want_persistent = spec.kind != FFC_CURVED_LAPLACE &&
+            (desc->persistent == 1 || (desc->persistent == 0 && rt.n_I >= kPersistentMinEntries));
         if (want_persistent && pl.staged && (desc->tile_cells == 0 || desc->tile_cells == 16)) {
             ffc::WaveSchedule ws;
             for (int w : {16}) {
@@ -306,9 +310,12 @@ int ffc_form_create(const ffc_form_desc* desc, ffc_form** out) {
     }
     if (desc->kernel == FFC_KERNEL_TENSOR) {
         // geometry workspace (chunks of 2^21 cells), unless every tabulation is fused
-        f->amap_cap = int64_t(1) << 21;
-        const size_t bytes = static_cast<size_t>(f->amap_cap) * (1 + spec.dim * spec.dim) * sizeof(double);
-        f->fused = desc->geometry != FFC_GEOMETRY_PASS && f->pwaves == 0;
+        // (curvilinear cells: G itself, n_alpha rows, in chunks of the same byte size)
+        const int rows = spec.kind == FFC_CURVED_LAPLACE ? rt.n_alpha : 1 + spec.dim * spec.dim;
+        f->amap_cap = spec.kind == FFC_CURVED_LAPLACE ? ((int64_t(1) << 21) * (1 + spec.dim * spec.dim) / rows + 63) / 64 * 64
+                                                     : int64_t(1) << 21;
+        const size_t bytes = static_cast<size_t>(f->amap_cap) * rows * sizeof(double);
+        f->fused = desc->geometry != FFC_GEOMETRY_PASS && f->pwaves == 0 && spec.kind != FFC_CURVED_LAPLACE;
         if (!f->fused && hipMalloc(reinterpret_cast<void**>(&f->d_amap), bytes) != hipSuccess)
             return fail(FFC_E_NOMEM, "hipMalloc failed for the geometry workspace");
         // default launch shape when the persistent kernel does not apply
@@ -376,7 +383,7 @@ int ffc_form_get_info(const ffc_form* f, ffc_form_info* info) {
     info->n_alpha = f->n_alpha_form;
     info->nnz_a0 = f->nnz_form;
     info->g_entries = rt.n_alpha;
-    info->n_coords = (d + 1) * d;
+    info->n_coords = f->desc.kind == FFC_CURVED_LAPLACE ? f->rt.n_geo * d : (d + 1) * d;
     info->n_coeffs = rt.n_coeff;
     info->out_bytes = (f->desc.kernel == FFC_KERNEL_TENSOR && f->desc.precision != FFC_FP64) ? 4 : 8;
     info->mfma_k_per_tile = f->mfma_k;
@@ -458,6 +465,7 @@ int ffc_tabulate_tensor_affine(const ffc_form* f, int64_t cells, const double* a
                                void* out) {
     if (!f) return fail(FFC_E_INVALID, "form is NULL");
     if (f->desc.kernel != FFC_KERNEL_TENSOR) return fail(FFC_E_INVALID, "not a tensor-kernel form");
+    if (f->desc.kind == FFC_CURVED_LAPLACE) return fail(FFC_E_UNSUPPORTED, "curvilinear cells have no affine map");
     if (cells < 0) return fail(FFC_E_INVALID, "cells < 0");
     if (cells == 0) return FFC_OK;
     if (!affine_map || !out) return fail(FFC_E_INVALID, "affine_map / out is NULL");
@@ -487,8 +495,8 @@ bool apply_tile_shape(const ffc_form* f, int* tile_cells, int* waves) {
 int ffc_apply_tensor(const ffc_form* f, int64_t cells, const double* coords, const double* coeffs, const double* x,
                      double* y) {
     if (!f) return fail(FFC_E_INVALID, "form is NULL");
-    if (f->desc.kernel != FFC_KERNEL_TENSOR || f->desc.precision != FFC_FP64)
-        return fail(FFC_E_UNSUPPORTED, "the operator action needs an FP64 tensor-kernel form");
+    if (f->desc.kernel != FFC_KERNEL_TENSOR || f->desc.precision != FFC_FP64 || f->desc.kind == FFC_CURVED_LAPLACE)
+        return fail(FFC_E_UNSUPPORTED, "the operator action needs an FP64 tensor-kernel form on affine cells");
     if (cells < 0) return fail(FFC_E_INVALID, "cells < 0");
     if (cells == 0) return FFC_OK;
     if (!coords || !x || !y) return fail(FFC_E_INVALID, "coords / x / y is NULL");
@@ -568,7 +576,10 @@ int ffc_tabulate_tensor(const ffc_form* f, int64_t cells, const double* coords, 
     }
     for (int64_t c0 = 0; c0 < cells; c0 += f->amap_cap) {
         const int64_t n = std::min(f->amap_cap, cells - c0);
-        hipError_t e = ffc::launch_geometry(d, n, coords + c0, cells, f->d_amap, f->amap_cap, f->stream);
+        hipError_t e = kind == FFC_CURVED_LAPLACE
+                           ? ffc::launch_curved_geometry(d, n, coords + c0, cells, rt.n_pts, f->d_geo_grad, f->d_amap,
+                                                         f->amap_cap, f->stream)
+                           : ffc::launch_geometry(d, n, coords + c0, cells, f->d_amap, f->amap_cap, f->stream);
         if (e != hipSuccess) return hip_fail(e, "geometry kernel launch");
         int rc = contract_chunk(f, n, f->d_amap, f->amap_cap, coeffs ? coeffs + c0 : nullptr, cells,
                                 static_cast<char*>(out) + static_cast<size_t>(c0) * rt.n_I * obytes);
@@ -643,7 +654,8 @@ int ffc_batch_create(int32_t n, const ffc_form* const* forms, const int64_t* cel
         const ffc_form* f = forms[i];
         if (!f) return fail(FFC_E_INVALID, "NULL form in batch");
         if (f->desc.kernel != FFC_KERNEL_TENSOR) return fail(FFC_E_UNSUPPORTED, "batches use the tensor kernel only");
-        if (f->desc.kind == FFC_PIOLA_MASS) return fail(FFC_E_UNSUPPORTED, "batches take Lagrange forms only");
+        if (f->desc.kind == FFC_PIOLA_MASS || f->desc.kind == FFC_CURVED_LAPLACE)
+            return fail(FFC_E_UNSUPPORTED, "batches take Lagrange forms on affine cells only");
         const bool bf = f->desc.precision != FFC_FP64;
         if (i == 0) {
             bf16 = bf;

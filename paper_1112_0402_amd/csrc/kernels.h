@@ -65,6 +65,11 @@ struct QuadArgs {
 
 hipError_t launch_geometry(int dim, int64_t cells, const double* coords, int64_t cstride, double* amap,
                            int64_t astride, hipStream_t stream);
+// Cells with P2 geometry: coords SoA [n_geo * dim][cstride] (P2 nodes in the dof order), grad
+// [n_pts][n_geo][dim] reference gradients of the P2 basis at the quadrature points; writes
+// G SoA [n_pts * dim(dim+1)/2][gstride] (|det J| (g g^T)_ab at each point, pairs a <= b).
+hipError_t launch_curved_geometry(int dim, int64_t cells, const double* coords, int64_t cstride, int n_pts,
+                                  const double* grad, double* G, int64_t gstride, hipStream_t stream);
 hipError_t launch_contract(int dim, int kind, bool bf16, int tile_cells, int waves, ContractArgs a,
                            hipStream_t stream);
 

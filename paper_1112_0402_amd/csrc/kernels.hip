@@ -28,7 +28,7 @@ typedef double d2v __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-enum { K_MASS = 0, K_LAPLACE = 1, K_WLAPLACE = 2, K_ELASTICITY = 3, K_NS = 4, K_PIOLA = 5 };
+enum { K_MASS = 0, K_LAPLACE = 1, K_WLAPLACE = 2, K_ELASTICITY = 3, K_NS = 4, K_PIOLA = 5, K_CURVED = 6 };
 
 // Launch with `lds` bytes of dynamic LDS; above 64 KiB the per-kernel limit is raised
 // first (gfx950 has 160 KiB per CU).
@@ -61,19 +61,16 @@ struct FormTraits {
                                  : KIND == K_WLAPLACE ? (D + 1) * D * (D + 1) / 2
                                  : KIND == K_ELASTICITY ? D * D * (D * D + 1) / 2
                                  : KIND == K_PIOLA ? D * (D + 1) / 2
+                                 : KIND == K_CURVED ? 0  // per form (quadrature points x pairs), at run time
                                                         : D * (D + 1) * D;
     static constexpr int n_coeff = KIND == K_WLAPLACE ? D + 1 : KIND == K_NS ? D * (D + 1) : 0;
 };
 
 // ------------------------------------------------------------------ geometry ----
 
+// det J and g = J^{-1} (g_ab = dX_a / dx_b) of a Jacobian J_kb = dx_k / dX_b
 template <int D>
-__device__ __forceinline__ void affine_map(const double (&x)[D + 1][D], double& det, double (&g)[D][D]) {
-    double J[D][D];
-#pragma unroll
-    for (int k = 0; k < D; ++k)
-#pragma unroll
-        for (int b = 0; b < D; ++b) J[k][b] = x[b + 1][k] - x[0][k];
+__device__ __forceinline__ void invert_jacobian(const double (&J)[D][D], double& det, double (&g)[D][D]) {
     if constexpr (D == 2) {
         det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
         const double r = 1.0 / det;
@@ -100,6 +97,16 @@ __device__ __forceinline__ void affine_map(const double (&x)[D + 1][D], double& 
 }
 
 template <int D>
+__device__ __forceinline__ void affine_map(const double (&x)[D + 1][D], double& det, double (&g)[D][D]) {
+    double J[D][D];
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+#pragma unroll
+        for (int b = 0; b < D; ++b) J[k][b] = x[b + 1][k] - x[0][k];
+    invert_jacobian<D>(J, det, g);
+}
+
+template <int D>
 __global__ __launch_bounds__(256) void geometry_kernel(int64_t cells, const double* __restrict__ coords,
                                                        int64_t cstride, double* __restrict__ amap, int64_t astride) {
     const int64_t c = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
@@ -116,6 +123,64 @@ __global__ __launch_bounds__(256) void geometry_kernel(int64_t cells, const doub
     for (int a = 0; a < D; ++a)
 #pragma unroll
         for (int b = 0; b < D; ++b) amap[(1 + a * D + b) * astride + c] = g[a][b];
+}
+
+// Cells with P2 geometry (NG nodes): one lane per cell; at every quadrature point p,
+// J(X_p) = sum_k x_k (grad Psi_k(X_p))^T, then G[(p, a <= b)] = |det J| (g g^T)_ab, SoA
+// [n_pts * D(D+1)/2][gstride].  grad: [n_pts][NG][D] reference gradients of the geometry basis.
+template <int D>
+__global__ __launch_bounds__(256) void curved_geometry_kernel(int64_t cells, const double* __restrict__ coords,
+                                                              int64_t cstride, int n_pts,
+                                                              const double* __restrict__ grad, double* __restrict__ G,
+                                                              int64_t gstride) {
+    constexpr int NG = D == 2 ? 6 : 10;
+    constexpr int NP = D * (D + 1) / 2;
+    const int64_t c = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (c >= cells) return;
+    double x[NG][D];
+#pragma unroll
+    for (int k = 0; k < NG; ++k)
+#pragma unroll
+        for (int j = 0; j < D; ++j) x[k][j] = __builtin_nontemporal_load(&coords[(k * D + j) * cstride + c]);
+    for (int p = 0; p < n_pts; ++p) {
+        double J[D][D];
+#pragma unroll
+        for (int j = 0; j < D; ++j)
+#pragma unroll
+            for (int b = 0; b < D; ++b) J[j][b] = 0.0;
+#pragma unroll
+        for (int k = 0; k < NG; ++k)
+#pragma unroll
+            for (int b = 0; b < D; ++b) {
+                const double gk = grad[(p * NG + k) * D + b];
+#pragma unroll
+                for (int j = 0; j < D; ++j) J[j][b] = fma(x[k][j], gk, J[j][b]);
+            }
+        double det, g[D][D];
+        invert_jacobian<D>(J, det, g);
+        const double adet = fabs(det);
+        int pr = 0;
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int b = a; b < D; ++b, ++pr) {
+                double s = 0.0;
+#pragma unroll
+                for (int k = 0; k < D; ++k) s += g[a][k] * g[b][k];
+                G[(p * NP + pr) * gstride + c] = adet * s;
+            }
+    }
+}
+
+hipError_t launch_curved_geometry(int dim, int64_t cells, const double* coords, int64_t cstride, int n_pts,
+                                  const double* grad, double* G, int64_t gstride, hipStream_t stream) {
+    if (cells <= 0) return hipSuccess;
+    const unsigned grid = static_cast<unsigned>((cells + 255) / 256);
+    if (dim == 2)
+        curved_geometry_kernel<2><<<grid, 256, 0, stream>>>(cells, coords, cstride, n_pts, grad, G, gstride);
+    else
+        curved_geometry_kernel<3><<<grid, 256, 0, stream>>>(cells, coords, cstride, n_pts, grad, G, gstride);
+    return hipGetLastError();
 }
 
 hipError_t launch_geometry(int dim, int64_t cells, const double* coords, int64_t cstride, double* amap,
@@ -310,14 +375,24 @@ __device__ __forceinline__ void contract_tile_f64(const double* am, const double
                                                   int64_t c0, int64_t cells, int nI, int n_tiles,
                                                   const int32_t* __restrict__ koff, const uint32_t* __restrict__ apack,
                                                   const int32_t* __restrict__ entry, const double* __restrict__ bvals,
-                                                  double* __restrict__ out, int sym_n) {
+                                                  double* __restrict__ out, int sym_n, int na_rt = 0,
+                                                  const double* __restrict__ gmem = nullptr, int64_t gstride = 0) {
     using FT = FormTraits<KIND, D>;
     constexpr int CT = 16 * MT;
-    constexpr int NA = FT::n_alpha;
-    constexpr int GS = NA | 1;
-    for (int i = threadIdx.x; i < CT * NA; i += blockDim.x) {
-        const int c = i / NA, al = i - c * NA;
-        Gs[c * GS + al] = g_entry<KIND, D>(am, cf, CT, c, al);
+    // K_CURVED: G comes precomputed from memory (SoA [n_alpha][gstride]), n_alpha at run time
+    const int NA = KIND == K_CURVED ? na_rt : FT::n_alpha;
+    const int GS = NA | 1;
+    if constexpr (KIND == K_CURVED) {
+        for (int i = threadIdx.x; i < CT * NA; i += blockDim.x) {
+            const int al = i / CT, c = i - (i / CT) * CT;
+            const int64_t cell = c0 + c;
+            Gs[c * GS + al] = cell < cells ? gmem[al * gstride + cell] : 0.0;
+        }
+    } else {
+        for (int i = threadIdx.x; i < CT * NA; i += blockDim.x) {
+            const int c = i / NA, al = i - c * NA;
+            Gs[c * GS + al] = g_entry<KIND, D>(am, cf, CT, c, al);
+        }
     }
     __syncthreads();
     const int waves = blockDim.x >> 6;
@@ -395,13 +470,15 @@ __global__ __launch_bounds__(1024) void contract_f64_kernel(ContractArgs A) {
     double* cf = am + (1 + D * D) * CT;
     double* Gs = reinterpret_cast<double*>(smem_raw + A.stage_bytes + A.head_bytes);
     const int64_t c0 = static_cast<int64_t>(blockIdx.x) * CT;
-    if (A.coords)
-        stage_tile_from_coords<D, NC>(A.coords, A.coeffs, A.cells, c0, CT, am, cf);
-    else
-        stage_tile<D, NC>(A, c0, CT, am, cf);
-    __syncthreads();
+    if constexpr (KIND != K_CURVED) {
+        if (A.coords)
+            stage_tile_from_coords<D, NC>(A.coords, A.coeffs, A.cells, c0, CT, am, cf);
+        else
+            stage_tile<D, NC>(A, c0, CT, am, cf);
+        __syncthreads();
+    }
     contract_tile_f64<D, KIND, MT>(am, cf, Gs, st, c0, A.cells, A.n_I, A.n_tiles, A.koff, A.apack, A.entry, A.b,
-                                   static_cast<double*>(A.out), A.sym_n);
+                                   static_cast<double*>(A.out), A.sym_n, A.n_alpha, A.amap, A.astride);
 }
 
 // Operator action, one cell tile per workgroup: the tile's local vectors go to LDS beside
@@ -462,6 +539,7 @@ static hipError_t launch_f64_d(int kind, int tile_cells, int waves, size_t lds, 
     case K_WLAPLACE: return launch_f64_mt<D, K_WLAPLACE>(tile_cells, waves, lds, a, s);
     case K_ELASTICITY: return launch_f64_mt<D, K_ELASTICITY>(tile_cells, waves, lds, a, s);
     case K_PIOLA: return launch_f64_mt<D, K_PIOLA>(tile_cells, waves, lds, a, s);
+    case K_CURVED: return launch_f64_mt<D, K_CURVED>(tile_cells, waves, lds, a, s);
     default: return launch_f64_mt<D, K_NS>(tile_cells, waves, lds, a, s);
     }
 }
@@ -600,6 +678,7 @@ static hipError_t launch_bf16_d(int kind, int tile_cells, int waves, size_t lds,
     case K_WLAPLACE: return launch_bf16_mt<D, K_WLAPLACE, NSEG>(tile_cells, waves, lds, a, s);
     case K_ELASTICITY: return launch_bf16_mt<D, K_ELASTICITY, NSEG>(tile_cells, waves, lds, a, s);
     case K_PIOLA: return launch_bf16_mt<D, K_PIOLA, NSEG>(tile_cells, waves, lds, a, s);
+    case K_CURVED: return hipErrorInvalidValue;  // FP64 only
     default: return launch_bf16_mt<D, K_NS, NSEG>(tile_cells, waves, lds, a, s);
     }
 }
@@ -950,7 +1029,8 @@ static hipError_t launch_persistent_d(int kind, int kmax, int waves, int grid, s
     case K_LAPLACE: return launch_persistent_k<D, K_LAPLACE, ACT>(kmax, waves, grid, lds, a, p, s);
     case K_WLAPLACE: return launch_persistent_k<D, K_WLAPLACE, ACT>(kmax, waves, grid, lds, a, p, s);
     case K_ELASTICITY: return launch_persistent_k<D, K_ELASTICITY, ACT>(kmax, waves, grid, lds, a, p, s);
-    case K_PIOLA: return hipErrorInvalidValue;  // tiny tensors: tile kernels only
+    case K_PIOLA:
+    case K_CURVED: return hipErrorInvalidValue;  // tile kernels only
     default: return launch_persistent_k<D, K_NS, ACT>(kmax, waves, grid, lds, a, p, s);
     }
 }
@@ -1017,6 +1097,7 @@ static hipError_t launch_apply_d(int kind, int tile_cells, unsigned grid, unsign
     case K_WLAPLACE: return launch_apply_k<D, K_WLAPLACE>(tile_cells, grid, block, lds, a, s);
     case K_ELASTICITY: return launch_apply_k<D, K_ELASTICITY>(tile_cells, grid, block, lds, a, s);
     case K_PIOLA: return launch_apply_k<D, K_PIOLA>(tile_cells, grid, block, lds, a, s);
+    case K_CURVED: return hipErrorInvalidValue;
     default: return launch_apply_k<D, K_NS>(tile_cells, grid, block, lds, a, s);
     }
 }
@@ -1272,7 +1353,8 @@ static hipError_t launch_bf16_persistent_d(int kind, int mt, int ks, int grid, s
     case K_LAPLACE: return launch_bf16_persistent_k<D, K_LAPLACE, NSEG>(mt, ks, grid, lds, a, s);
     case K_WLAPLACE: return launch_bf16_persistent_k<D, K_WLAPLACE, NSEG>(mt, ks, grid, lds, a, s);
     case K_ELASTICITY: return launch_bf16_persistent_k<D, K_ELASTICITY, NSEG>(mt, ks, grid, lds, a, s);
-    case K_PIOLA: return hipErrorInvalidValue;
+    case K_PIOLA:
+    case K_CURVED: return hipErrorInvalidValue;
     default: return launch_bf16_persistent_k<D, K_NS, NSEG>(mt, ks, grid, lds, a, s);
     }
 }
@@ -1679,7 +1761,7 @@ static hipError_t launch_quad_d(int kind, const QuadArgs& a, hipStream_t s) {
 
 hipError_t launch_quadrature(int dim, int kind, const QuadArgs& a, hipStream_t stream) {
     if (a.cells <= 0) return hipSuccess;
-    if (kind == K_PIOLA) return hipErrorInvalidValue;  // Lagrange forms only
+    if (kind == K_PIOLA || kind == K_CURVED) return hipErrorInvalidValue;  // affine Lagrange forms only
     return dim == 2 ? launch_quad_d<2>(kind, a, stream) : launch_quad_d<3>(kind, a, stream);
 }
 

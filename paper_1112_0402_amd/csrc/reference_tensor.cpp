@@ -169,6 +169,18 @@ bool invert(std::vector<ld>& A, int n) {
     return true;
 }
 
+ld eval(const Poly& p, const std::array<ld, 3>& X) {
+    ld v = 0;
+    for (const auto& t : p) {
+        const auto e = exp_of(t.first);
+        ld m = t.second;
+        for (int b = 0; b < 3; ++b)
+            for (int k = 0; k < e[b]; ++k) m *= X[b];
+        v += m;
+    }
+    return v;
+}
+
 std::vector<Poly> basis_polys(const LagrangeBasis& B) {
     std::vector<Poly> out(B.n);
     const int nm = static_cast<int>(B.exps.size());
@@ -198,6 +210,7 @@ int integrand_degree(int kind, int q) {
     case ELASTICITY: return 2 * q - 2;
     case NS: return 2 * q;
     case PIOLA: return 2;
+    case CURVED: return 2 * q - 2;
     }
     return 2 * q;
 }
@@ -207,7 +220,7 @@ bool supported(const FormSpec& s, std::string* why) {
         *why = "dim must be 2 or 3";
         return false;
     }
-    if (s.kind < MASS || s.kind > PIOLA) {
+    if (s.kind < MASS || s.kind > CURVED) {
         *why = "unknown form kind";
         return false;
     }
@@ -215,7 +228,7 @@ bool supported(const FormSpec& s, std::string* why) {
         *why = "Raviart-Thomas elements of the lowest order only (degree 1)";
         return false;
     }
-    int qmax = (s.kind == ELASTICITY || s.kind == NS) ? 3 : 4;
+    int qmax = (s.kind == ELASTICITY || s.kind == NS) ? 3 : s.kind == CURVED ? 2 : 4;
     if (s.degree < 1 || s.degree > qmax) {
         *why = "degree out of range (1.." + std::to_string(qmax) + " for this form)";
         return false;
@@ -276,6 +289,28 @@ bool build_reference_tensor(const FormSpec& s, ReferenceTensor* rt, std::string*
     case ELASTICITY: rt->n_alpha = d * d * d * d; rt->n_coeff = 0; break;
     case NS: rt->n_alpha = d * (d + 1) * d; rt->n_coeff = d * (d + 1); break;
     case PIOLA: rt->n_alpha = d * d; rt->n_coeff = 0; break;
+    case CURVED: rt->n_alpha = 0; rt->n_coeff = 0; break;  // set below, with the rule
+    }
+    // CURVED: the Laplacian on cells mapped by P2 geometry (Sec. 3.4, curvilinear elements),
+    // integration replaced by a sum over the points X_p of a collapsed Gauss-Jacobi rule with
+    // m = q + 1 points per direction: A^K = sum_p w_p |det J(X_p)| grad(phi_i1) . grad(phi_i2),
+    // a contraction of A^0[(i1,i2)][(p, a, b)] = w_p dPhi_i1/dX_a dPhi_i2/dX_b (X_p) with
+    // G_K[(p, a, b)] = |det J(X_p)| (g g^T)_ab(X_p); the (a, b) pairs are kept once, a <= b.
+    std::vector<std::array<ld, 3>> cpts;
+    std::vector<ld> cwts;
+    if (s.kind == CURVED) {
+        collapsed_rule(d, q + 1, &cpts, &cwts);
+        rt->n_pts = static_cast<int>(cpts.size());
+        rt->n_alpha = rt->n_pts * d * (d + 1) / 2;
+        LagrangeBasis G2 = make_basis(d, 2);
+        std::vector<Poly> psi = basis_polys(G2);
+        rt->n_geo = G2.n;
+        rt->geo_grad.assign(static_cast<size_t>(rt->n_pts) * G2.n * d, 0.0);
+        for (int p = 0; p < rt->n_pts; ++p)
+            for (int k = 0; k < G2.n; ++k)
+                for (int b = 0; b < d; ++b)
+                    rt->geo_grad[(static_cast<size_t>(p) * G2.n + k) * d + b] =
+                        static_cast<double>(eval(diff(psi[k], b), cpts[p]));
     }
     const int ns = B.n, n = rt->n, na = rt->n_alpha;
     std::vector<ld> A(static_cast<size_t>(rt->n_I) * na, 0);
@@ -325,6 +360,19 @@ bool build_reference_tensor(const FormSpec& s, ReferenceTensor* rt, std::string*
                                         at(c1 * ns + s1, c2 * ns + s2, ((a * d + j) * d + b) * d + l) =
                                             c * L[((s1 * ns + s2) * d + a) * d + b];
                                     }
+    } else if (s.kind == CURVED) {
+        const int np = d * (d + 1) / 2;
+        for (int p = 0; p < rt->n_pts; ++p)
+            for (int i = 0; i < ns; ++i)
+                for (int j = 0; j < ns; ++j) {
+                    int pr = 0;
+                    for (int a = 0; a < d; ++a)
+                        for (int b = a; b < d; ++b, ++pr) {
+                            ld v = eval(dphi[i][a], cpts[p]) * eval(dphi[j][b], cpts[p]);
+                            if (a != b) v += eval(dphi[i][b], cpts[p]) * eval(dphi[j][a], cpts[p]);
+                            at(i, j, p * np + pr) = cwts[p] * v;
+                        }
+                }
     } else if (s.kind == PIOLA) {
         // Psi_i = (X - V_i) / (d |K0|) = (d-1)! (X - V_i), V_0 = 0, V_k = e_k;
         // A^0[(i,j)][(a1,a2)] = int_K0 Psi_i,a1 Psi_j,a2
@@ -414,9 +462,26 @@ ReferenceTensor fold_symmetric_g(const ReferenceTensor& rt) {
 
 namespace {
 
-using Mask = std::array<uint64_t, 2>;  // nonzero alpha columns of a row (n_alpha <= 128)
+using Mask = std::array<uint64_t, 4>;  // nonzero alpha columns of a row (n_alpha <= 256)
 
-int popcount(const Mask& m) { return __builtin_popcountll(m[0]) + __builtin_popcountll(m[1]); }
+int popcount(const Mask& m) {
+    int c = 0;
+    for (uint64_t w : m) c += __builtin_popcountll(w);
+    return c;
+}
+Mask mask_and_not(const Mask& a, const Mask& b) {
+    Mask r{};
+    for (int k = 0; k < 4; ++k) r[k] = a[k] & ~b[k];
+    return r;
+}
+Mask mask_and(const Mask& a, const Mask& b) {
+    Mask r{};
+    for (int k = 0; k < 4; ++k) r[k] = a[k] & b[k];
+    return r;
+}
+void mask_or(Mask& a, const Mask& b) {
+    for (int k = 0; k < 4; ++k) a[k] |= b[k];
+}
 
 // Greedy clustering of `rows` into groups of at most 16: seed = remaining row with the most
 // nonzero columns, then repeatedly add the row that grows the union least (ties: the row
@@ -436,8 +501,8 @@ std::vector<std::vector<int>> cluster_rows(const std::vector<int>& rows, const s
             int best_inc = 1 << 30, best_ov = -1;
             for (size_t i = 0; i < rem.size(); ++i) {
                 const Mask& m = mask[rem[i]];
-                const Mask inc{m[0] & ~u[0], m[1] & ~u[1]};
-                const Mask ov{m[0] & u[0], m[1] & u[1]};
+                const Mask inc = mask_and_not(m, u);
+                const Mask ov = mask_and(m, u);
                 const int ci = popcount(inc), co = popcount(ov);
                 if (ci < best_inc || (ci == best_inc && co > best_ov)) {
                     best = i;
@@ -445,9 +510,7 @@ std::vector<std::vector<int>> cluster_rows(const std::vector<int>& rows, const s
                     best_ov = co;
                 }
             }
-            const Mask& m = mask[rem[best]];
-            u[0] |= m[0];
-            u[1] |= m[1];
+            mask_or(u, mask[rem[best]]);
             g.push_back(rem[best]);
             rem.erase(rem.begin() + best);
         }
@@ -465,7 +528,9 @@ TilesF64 make_tiles_f64(const ReferenceTensor& rt, int window, bool sym) {
     T.window = window;
     T.sym = sym;
     T.n = rt.n;
-    std::vector<Mask> mask(nI, Mask{0, 0});
+    T.koff.assign(1, 0);
+    if (na > 256) return T;  // alpha indices are packed in one byte: no tiles (supported() keeps forms below)
+    std::vector<Mask> mask(nI, Mask{});
     for (int r = 0; r < nI; ++r)
         for (int a = 0; a < na; ++a)
             if (rt.A0[static_cast<size_t>(r) * na + a] != 0) mask[r][a >> 6] |= uint64_t(1) << (a & 63);
@@ -491,11 +556,10 @@ TilesF64 make_tiles_f64(const ReferenceTensor& rt, int window, bool sym) {
     T.entry.assign(static_cast<size_t>(T.n_tiles) * 16, -1);
     for (int t = 0; t < T.n_tiles; ++t) {
         const auto& g = groups[t];
-        Mask u{0, 0};
+        Mask u{};
         for (size_t e = 0; e < g.size(); ++e) {
             T.entry[static_cast<size_t>(t) * 16 + e] = g[e];
-            u[0] |= mask[g[e]][0];
-            u[1] |= mask[g[e]][1];
+            mask_or(u, mask[g[e]]);
         }
         std::vector<int> cols;
         for (int a = 0; a < na; ++a)
@@ -708,6 +772,31 @@ void gauss_jacobi01(int m, int a, std::vector<long double>* x, std::vector<long 
     }
 }
 
+void collapsed_rule(int d, int m, std::vector<std::array<ld, 3>>* pts, std::vector<ld>* wts) {
+    std::vector<ld> x0, w0, x1, w1, x2, w2;
+    gauss_jacobi01(m, 0, &x0, &w0);
+    gauss_jacobi01(m, 1, &x1, &w1);
+    gauss_jacobi01(m, 2, &x2, &w2);
+    pts->clear();
+    wts->clear();
+    if (d == 2) {
+        // X1 = s1 (1 - s2), X2 = s2, dX = (1 - s2) ds, the (1 - s2) factor in the
+        // Jacobi weight of the second direction
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j) {
+                pts->push_back({x0[i] * (1 - x1[j]), x1[j], 0});
+                wts->push_back(w0[i] * w1[j]);
+            }
+    } else {
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j)
+                for (int k = 0; k < m; ++k) {
+                    pts->push_back({x0[i] * (1 - x1[j]) * (1 - x2[k]), x1[j] * (1 - x2[k]), x2[k]});
+                    wts->push_back(w0[i] * w1[j] * w2[k]);
+                }
+    }
+}
+
 QuadTables make_quad_tables(const FormSpec& s) {
     QuadTables Q;
     const int d = s.dim;
@@ -716,28 +805,9 @@ QuadTables make_quad_tables(const FormSpec& s) {
     if (m < 1) m = 1;
     Q.m = m;
     Q.dim = d;
-    std::vector<ld> x0, w0, x1, w1, x2, w2;
-    gauss_jacobi01(m, 0, &x0, &w0);
-    gauss_jacobi01(m, 1, &x1, &w1);
-    gauss_jacobi01(m, 2, &x2, &w2);
     std::vector<std::array<ld, 3>> pts;
     std::vector<ld> wts;
-    if (d == 2) {
-        // X1 = s1 (1 - s2), X2 = s2, dX = (1 - s2) ds, the (1 - s2) factor in the
-        // Jacobi weight of the second direction
-        for (int i = 0; i < m; ++i)
-            for (int j = 0; j < m; ++j) {
-                pts.push_back({x0[i] * (1 - x1[j]), x1[j], 0});
-                wts.push_back(w0[i] * w1[j]);
-            }
-    } else {
-        for (int i = 0; i < m; ++i)
-            for (int j = 0; j < m; ++j)
-                for (int k = 0; k < m; ++k) {
-                    pts.push_back({x0[i] * (1 - x1[j]) * (1 - x2[k]), x1[j] * (1 - x2[k]), x2[k]});
-                    wts.push_back(w0[i] * w1[j] * w2[k]);
-                }
-    }
+    collapsed_rule(d, m, &pts, &wts);
     Q.npts = static_cast<int>(pts.size());
     LagrangeBasis B = make_basis(d, s.degree);
     Q.ns = B.n;

@@ -10,7 +10,7 @@
 
 namespace ffc {
 
-enum Kind { MASS = 0, LAPLACE = 1, WLAPLACE = 2, ELASTICITY = 3, NS = 4, PIOLA = 5 };
+enum Kind { MASS = 0, LAPLACE = 1, WLAPLACE = 2, ELASTICITY = 3, NS = 4, PIOLA = 5, CURVED = 6 };
 
 struct FormSpec {
     int kind = 0, dim = 2, degree = 1;
@@ -34,6 +34,11 @@ struct ReferenceTensor {
     int n_coeff = 0;  // coefficient doubles per cell
     int64_t nnz = 0;
     std::vector<double> A0;  // [n_I][n_alpha]
+    // CURVED (quadrature as contraction on cells with P2 geometry): quadrature points, the P2
+    // geometry nodes per cell, and the reference gradients of the P2 geometry basis at the
+    // points, [n_pts][n_geo][dim]
+    int n_pts = 0, n_geo = 0;
+    std::vector<double> geo_grad;
 };
 
 // Contraction tiles for 16 x 16 x 4 FP64 MFMA.  The n_I output entries are grouped into
@@ -74,6 +79,8 @@ struct QuadTables {
 };
 
 int n_scalar_dofs(int dim, int degree);
+// collapsed Gauss-Jacobi rule on K0 with m points per direction (exact for degree 2m - 1)
+void collapsed_rule(int dim, int m, std::vector<std::array<long double, 3>>* pts, std::vector<long double>* wts);
 int integrand_degree(int kind, int degree);
 bool supported(const FormSpec& s, std::string* why);
 

@@ -64,8 +64,9 @@ class Form:
         """Element tensors [cells, n, n] (row = test function), enqueued on the form's stream."""
         d = self.dim
         _check_tensor("coords", coords, torch.float64)
-        if coords.dim() != 2 or coords.shape[0] != (d + 1) * d:
-            raise ValueError(f"coords must be [(d+1)*d, cells] = [{(d + 1) * d}, cells]")
+        nc = self.info["n_coords"]
+        if coords.dim() != 2 or coords.shape[0] != nc:
+            raise ValueError(f"coords must be [{nc}, cells]")
         cells = coords.shape[1]
         if self.info["n_coeffs"]:
             if coeffs is None:
@@ -105,8 +106,9 @@ class Form:
         the element tensors; FP64 tensor-kernel forms."""
         d = self.dim
         _check_tensor("coords", coords, torch.float64)
-        if coords.dim() != 2 or coords.shape[0] != (d + 1) * d:
-            raise ValueError(f"coords must be [(d+1)*d, cells] = [{(d + 1) * d}, cells]")
+        nc = self.info["n_coords"]
+        if coords.dim() != 2 or coords.shape[0] != nc:
+            raise ValueError(f"coords must be [{nc}, cells]")
         cells, n = coords.shape[1], self.info["n_dofs"]
         if self.info["n_coeffs"]:
             if coeffs is None:

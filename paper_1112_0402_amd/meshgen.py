@@ -281,3 +281,51 @@ def config4(n_meshes: int = 64, lo: float = 1e3, hi: float = 5e5, seed: int = 4,
         out.append(make_workload(kind, dim, q, n, seed * 1000 + k, max_cells=size,
                                  name=f"mesh{k}_{kind}{dim}d_p{q}"))
     return out
+
+
+# ------------------------------------------------------------------ curved cells ---
+# P2 geometry: each cell carries its vertices and its edge midpoints, the midpoints moved by
+# a smooth displacement field that depends on the position only (so neighbours agree and
+# the mesh stays conforming).  Edge order = the P2 dof order: triangle (1,2), (0,2), (0,1);
+# tetrahedron (2,3), (1,3), (1,2), (0,3), (0,2), (0,1).
+
+P2_EDGES = {2: ((1, 2), (0, 2), (0, 1)), 3: ((2, 3), (1, 3), (1, 2), (0, 3), (0, 2), (0, 1))}
+
+
+def _bump(x: np.ndarray) -> np.ndarray:
+    """Smooth displacement direction field on the unit square / cube, |value| <= 1."""
+    d = x.shape[-1]
+    s = np.sin(np.pi * x)
+    base = np.prod(s, axis=-1)
+    out = np.empty_like(x)
+    for k in range(d):
+        out[..., k] = base * np.cos(np.pi * (k + 1) * x[..., (k + 1) % d])
+    return out
+
+
+def curved_workload(dim: int, degree: int, n: int, seed: int, amplitude: float = 0.1, straight: bool = False,
+                    max_cells: int | None = None, jitter: float = 0.1, name: str = "") -> Workload:
+    """A jittered mesh of side n with P2 geometry: coords SoA [n_geo * d][cells] (vertices
+    moved by up to jitter * h, then edge midpoints displaced by amplitude * h * bump(midpoint);
+    straight=True keeps the midpoints on the straight edges, i.e. affine cells).  The
+    defaults keep every Jacobian well conditioned (condition number below ~20 at every
+    quadrature point); the affine workloads' 0.2 h jitter combined with curved edges can
+    bring an occasional cell close to degenerate."""
+    if dim == 2:
+        verts, cells = unit_square(n, seed, jitter)
+        if max_cells is not None:
+            cells = cells[:max_cells]
+    else:
+        verts, cells = unit_cube(n, seed, jitter, max_cells=max_cells)
+    h = 1.0 / n
+    X = verts[cells]  # [nc, d+1, d]
+    nodes = [X[:, v, :] for v in range(dim + 1)]
+    for a, b in P2_EDGES[dim]:
+        m = 0.5 * (X[:, a, :] + X[:, b, :])
+        if not straight:
+            m = m + amplitude * h * _bump(m)
+        nodes.append(m)
+    P = np.stack(nodes, axis=1)  # [nc, n_geo, d]
+    coords = np.ascontiguousarray(P.reshape(P.shape[0], -1).T)
+    return Workload("curved", dim, degree, coords, None, name=name,
+                    meta={"cells": cells, "n_vertices": int(verts.shape[0])})

@@ -1,0 +1,51 @@
+"""GPU parity of the curvilinear Laplacian (P2 geometry, quadrature as contraction, Sec. 3.4)
+against the oracle's quadrature on the physical cells."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1112_0402_amd import capi, meshgen
+from paper_1112_0402_amd.forms import Form
+from tests.gpu_util import rel_fro, require_gpu, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("dim,q,n", [(2, 1, 13), (2, 2, 11), (3, 1, 5), (3, 2, 5)])
+@pytest.mark.parametrize("launch", [dict(), dict(tile_cells=16), dict(tile_cells=64, waves=4), dict(symmetry=-1)])
+def test_curved_laplace_matches_oracle(dim, q, n, launch):
+    require_gpu()
+    wl = meshgen.curved_workload(dim, q, n, 3)
+    f = Form("curved", dim, q, **launch)
+    got = f.tabulate(to_dev(wl.coords)).cpu().numpy()
+    ref = oracle.curved_laplace(dim, q, wl.coords)
+    emax, _ = rel_fro(got, ref)
+    say(f"[curved] d={dim} q={q} {launch}: {wl.cells} cells, G entries {f.info['g_entries']}, max {emax:.2e}")
+    assert emax <= 1e-12
+    # straight midpoints: the affine Laplacian
+    ws = meshgen.curved_workload(dim, q, n, 3, straight=True, jitter=meshgen.JITTER)
+    a = f.tabulate(to_dev(ws.coords)).cpu().numpy()
+    b = Form("laplace", dim, q).tabulate(to_dev(meshgen.make_workload("laplace", dim, q, n, 3).coords)).cpu().numpy()
+    assert rel_fro(a, b)[0] <= 1e-12
+
+
+def test_curved_chunks_and_edges():
+    """A mesh longer than the form's G workspace (several chunks) on sampled cells; one cell;
+    the paths this form does not take are refused."""
+    require_gpu()
+    wl = meshgen.curved_workload(3, 2, 30, 4)  # 162,000 cells
+    f = Form("curved", 3, 2)
+    got = f.tabulate(to_dev(wl.coords)).cpu().numpy()
+    rng = np.random.default_rng(0)
+    idx = np.unique(np.concatenate([[0, wl.cells - 1], rng.choice(wl.cells, 1500, replace=False)]))
+    ref = oracle.curved_laplace(3, 2, np.ascontiguousarray(wl.coords[:, idx]))
+    assert rel_fro(got[idx], ref)[0] <= 1e-12
+    one = meshgen.curved_workload(2, 2, 2, 5, max_cells=1)
+    assert rel_fro(Form("curved", 2, 2).tabulate(to_dev(one.coords)).cpu().numpy(),
+                   oracle.curved_laplace(2, 2, one.coords))[0] <= 1e-12
+    for kw in (dict(kernel="quadrature"), dict(precision="bf16x3")):
+        with pytest.raises(capi.FFCError):
+            Form("curved", 3, 2, **kw)
+    with pytest.raises(capi.FFCError):
+        f.apply(to_dev(wl.coords[:, :1].copy()), torch.zeros((1, 10), dtype=torch.float64, device="cuda"))
