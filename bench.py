@@ -526,8 +526,8 @@ def bench_action(args, torch, np):
 
 def bench_curved(args, torch, np):
     """Curvilinear Laplacian (P2 geometry, P2 functions, 3D): 6 * 50^3 = 750,000 cells with
-    curved edges; a step is the per-point geometry kernel (G at the 27 quadrature points)
-    plus the tile contraction reading G."""
+    curved edges; a step is one launch: each cell tile builds G at the 27 quadrature points
+    from its P2 nodes in LDS (FP64 vector work) and contracts it on the FP64 matrix cores."""
     from paper_1112_0402_amd import meshgen
     from paper_1112_0402_amd.forms import Form
 
@@ -545,8 +545,13 @@ def bench_curved(args, torch, np):
         ms = timed(lambda: form.tabulate(X, out=out), args.steps, stream, torch)
     n_I, ga = info["n_entries"], info["g_entries"]
     byt = cells * (info["n_coords"] * 8 + n_I * 8)           # coordinates in, element tensors out
-    g_byt = cells * 2 * ga * 8                                # the G round trip between the two kernels
     gbs = byt / (ms * 1e-3) / 1e9
+    # algorithmic FP64 flops per cell: per quadrature point the Jacobian from 10 nodes
+    # (2 * 10 * 3 * 3), its inverse by cofactors (~45) and 6 pair products (6 * 7); then the
+    # contraction over the nonzeros of A^0 (2 per nonzero)
+    npts = ga // 6
+    flops = cells * (npts * (2 * 10 * 9 + 45 + 6 * 7) + 2 * info["nnz_a0"])
+    tf = flops / (ms * 1e-3) / 1e12
     result = {
         "metric": METRIC,
         "value": cells / (ms * 1e-3),
@@ -561,12 +566,12 @@ def bench_curved(args, torch, np):
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "curved_laplace3d_p2_750k", "cells": cells, "n_entries": n_I, "g_entries": ga,
-                   "quadrature_points": ga // 6, "tile_cells": info["tile_cells"],
-                   "step": "curved geometry kernel (G per point) + tile contraction"},
-        "roofline": {"kernel": "curved_geometry_kernel + contract_f64_kernel", "bound": "hbm", "achieved": gbs,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": None,
-                     "algorithmic_bytes_per_launch": byt, "g_round_trip_bytes": g_byt,
-                     "achieved_gbs_with_g": (byt + g_byt) / (ms * 1e-3) / 1e9, "ms_per_launch": ms},
+                   "quadrature_points": npts, "tile_cells": info["tile_cells"],
+                   "geometry": "G built per tile in LDS" if info["fused_geometry"] else "separate G pass"},
+        "roofline": {"kernel": "contract_f64_kernel (curvilinear)", "bound": "fp64", "achieved": tf,
+                     "peak": FP64_MFMA_PEAK_TF, "unit": "TFLOP/s", "frac": tf / FP64_MFMA_PEAK_TF, "traffic": None,
+                     "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": byt,
+                     "achieved_gbs": gbs, "ms_per_launch": ms},
     }
     if not args.no_cpu_baseline:
         import oracle

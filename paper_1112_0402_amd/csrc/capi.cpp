@@ -315,7 +315,7 @@ int ffc_form_create(const ffc_form_desc* desc, ffc_form** out) {
         f->amap_cap = spec.kind == FFC_CURVED_LAPLACE ? ((int64_t(1) << 21) * (1 + spec.dim * spec.dim) / rows + 63) / 64 * 64
                                                      : int64_t(1) << 21;
         const size_t bytes = static_cast<size_t>(f->amap_cap) * rows * sizeof(double);
-        f->fused = desc->geometry != FFC_GEOMETRY_PASS && f->pwaves == 0 && spec.kind != FFC_CURVED_LAPLACE;
+        f->fused = desc->geometry != FFC_GEOMETRY_PASS && f->pwaves == 0;
         if (!f->fused && hipMalloc(reinterpret_cast<void**>(&f->d_amap), bytes) != hipSuccess)
             return fail(FFC_E_NOMEM, "hipMalloc failed for the geometry workspace");
         // default launch shape when the persistent kernel does not apply
@@ -439,6 +439,8 @@ ffc::ContractArgs contract_args(const ffc_form* f, int64_t n, const double* amap
     a.kpad = f->kpad;
     a.n_seg = f->n_seg;
     a.sym_n = f->sym_n;
+    a.geo_grad = f->d_geo_grad;
+    a.n_pts = rt.n_pts;
     std::copy(f->gpiece, f->gpiece + 6, a.gpiece);
     return a;
 }

@@ -33,6 +33,10 @@ struct ContractArgs {
     // operator action (y_K = A^K x_K): local vectors x [cells][n_dof]; out = y [cells][n_dof]
     const double* xloc;
     int n_dof;
+    // curvilinear cells with coords (G built in the tile): geometry basis gradients at the
+    // quadrature points [n_pts][n_geo][dim]
+    const double* geo_grad;
+    int n_pts;
     // LDS plan, filled by launch_contract
     int staged;
     size_t stage_bytes, head_bytes;

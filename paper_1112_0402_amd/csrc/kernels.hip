@@ -330,7 +330,9 @@ LdsPlan plan_lds(int dim, int kind, int tile_cells, int n_I, int n_alpha, int kp
     LdsPlan p{};
     const size_t ob = bf16 ? sizeof(float) : sizeof(double);
     p.stage_bytes = align16(static_cast<size_t>(tile_cells) * n_I * ob);
-    const size_t head = align16(static_cast<size_t>(1 + dim * dim + n_coeff_of(dim, kind)) * tile_cells * sizeof(double));
+    // head rows: affine map and coefficients, or (curvilinear cells) the P2 node coordinates
+    const int rows = kind == K_CURVED ? (dim == 2 ? 12 : 30) : 1 + dim * dim + n_coeff_of(dim, kind);
+    const size_t head = align16(static_cast<size_t>(rows) * tile_cells * sizeof(double));
     const size_t g = bf16 ? static_cast<size_t>(tile_cells) * (kpad + 8) * sizeof(uint16_t)
                           : static_cast<size_t>(tile_cells) * (n_alpha | 1) * sizeof(double);
     p.head_bytes = head;
@@ -382,11 +384,13 @@ __device__ __forceinline__ void contract_tile_f64(const double* am, const double
     // K_CURVED: G comes precomputed from memory (SoA [n_alpha][gstride]), n_alpha at run time
     const int NA = KIND == K_CURVED ? na_rt : FT::n_alpha;
     const int GS = NA | 1;
-    if constexpr (KIND == K_CURVED) {
-        for (int i = threadIdx.x; i < CT * NA; i += blockDim.x) {
-            const int al = i / CT, c = i - (i / CT) * CT;
-            const int64_t cell = c0 + c;
-            Gs[c * GS + al] = cell < cells ? gmem[al * gstride + cell] : 0.0;
+    if constexpr (KIND == K_CURVED) {  // (gmem == nullptr: the caller has built the G tile)
+        if (gmem) {
+            for (int i = threadIdx.x; i < CT * NA; i += blockDim.x) {
+                const int al = i / CT, c = i - (i / CT) * CT;
+                const int64_t cell = c0 + c;
+                Gs[c * GS + al] = cell < cells ? gmem[al * gstride + cell] : 0.0;
+            }
         }
     } else {
         for (int i = threadIdx.x; i < CT * NA; i += blockDim.x) {
@@ -476,9 +480,58 @@ __global__ __launch_bounds__(1024) void contract_f64_kernel(ContractArgs A) {
         else
             stage_tile<D, NC>(A, c0, CT, am, cf);
         __syncthreads();
+    } else if (A.coords) {
+        // curvilinear cells, G built in the tile: the P2 nodes to LDS ([k*D + j][CT]), then
+        // one lane per (point, cell): J(X_p) = sum_k x_k (grad Psi_k(X_p))^T, det J, g = J^{-1},
+        // G[(p, a <= b)] = |det J| (g g^T)_ab
+        constexpr int NG = D == 2 ? 6 : 10;
+        constexpr int NP = D * (D + 1) / 2;
+        for (int i = threadIdx.x; i < NG * D * CT; i += blockDim.x) {
+            const int r = i / CT, c = i - (i / CT) * CT;
+            const int64_t cell = c0 + c;
+            am[i] = cell < A.cells ? A.coords[r * A.cells + cell] : 0.0;
+        }
+        __syncthreads();
+        const int GS = A.n_alpha | 1;
+        for (int i = threadIdx.x; i < CT * A.n_pts; i += blockDim.x) {
+            const int p = i / CT, c = i - (i / CT) * CT;
+            double* gr = Gs + c * GS + p * NP;
+            if (c0 + c >= A.cells) {
+#pragma unroll
+                for (int q = 0; q < NP; ++q) gr[q] = 0.0;
+                continue;
+            }
+            double J[D][D];
+#pragma unroll
+            for (int j = 0; j < D; ++j)
+#pragma unroll
+                for (int b = 0; b < D; ++b) J[j][b] = 0.0;
+#pragma unroll
+            for (int k = 0; k < NG; ++k)
+#pragma unroll
+                for (int b = 0; b < D; ++b) {
+                    const double gk = A.geo_grad[(p * NG + k) * D + b];
+#pragma unroll
+                    for (int j = 0; j < D; ++j) J[j][b] = fma(am[(k * D + j) * CT + c], gk, J[j][b]);
+                }
+            double det, g[D][D];
+            invert_jacobian<D>(J, det, g);
+            const double adet = fabs(det);
+            int pr = 0;
+#pragma unroll
+            for (int a = 0; a < D; ++a)
+#pragma unroll
+                for (int b = a; b < D; ++b, ++pr) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int k = 0; k < D; ++k) s += g[a][k] * g[b][k];
+                    gr[pr] = adet * s;
+                }
+        }
     }
     contract_tile_f64<D, KIND, MT>(am, cf, Gs, st, c0, A.cells, A.n_I, A.n_tiles, A.koff, A.apack, A.entry, A.b,
-                                   static_cast<double*>(A.out), A.sym_n, A.n_alpha, A.amap, A.astride);
+                                   static_cast<double*>(A.out), A.sym_n, A.n_alpha,
+                                   KIND == K_CURVED && A.coords ? nullptr : A.amap, A.astride);
 }
 
 // Operator action, one cell tile per workgroup: the tile's local vectors go to LDS beside

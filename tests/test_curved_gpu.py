@@ -13,7 +13,8 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("dim,q,n", [(2, 1, 13), (2, 2, 11), (3, 1, 5), (3, 2, 5)])
-@pytest.mark.parametrize("launch", [dict(), dict(tile_cells=16), dict(tile_cells=64, waves=4), dict(symmetry=-1)])
+@pytest.mark.parametrize("launch", [dict(), dict(tile_cells=16), dict(tile_cells=64, waves=4), dict(symmetry=-1),
+                                    dict(geometry="pass"), dict(geometry="pass", tile_cells=16)])
 def test_curved_laplace_matches_oracle(dim, q, n, launch):
     require_gpu()
     wl = meshgen.curved_workload(dim, q, n, 3)
@@ -35,7 +36,7 @@ def test_curved_chunks_and_edges():
     the paths this form does not take are refused."""
     require_gpu()
     wl = meshgen.curved_workload(3, 2, 30, 4)  # 162,000 cells
-    f = Form("curved", 3, 2)
+    f = Form("curved", 3, 2, geometry="pass")  # G through the form's workspace, in chunks
     got = f.tabulate(to_dev(wl.coords)).cpu().numpy()
     rng = np.random.default_rng(0)
     idx = np.unique(np.concatenate([[0, wl.cells - 1], rng.choice(wl.cells, 1500, replace=False)]))
