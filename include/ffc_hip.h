@@ -81,10 +81,11 @@ typedef enum {
  *                    A^0[(i1,i2)][(p,a,b)] = w_p dPhi_i1/dX_a dPhi_i2/dX_b (X_p) with
  *                    G_K[(p,a,b)] = |det J(X_p)| (g g^T)_ab(X_p) (pairs a <= b, b's summed
  *                    into A^0).  coords: SoA [n_geo * d][cells] with the n_geo = 6 (d = 2)
- *                    or 10 (d = 3) P2 nodes of each cell in the P2 dof order below; a
- *                    geometry kernel writes G per point into the form's workspace, then the
- *                    FP64 tile contraction reads it.  FP64 tensor kernel only (no quadrature
- *                    kernel, split modes, batches, operator action or affine-map entry). */
+ *                    or 10 (d = 3) P2 nodes of each cell in the P2 dof order below; each
+ *                    cell tile builds its G at the points in LDS (with geometry = PASS, a
+ *                    geometry kernel writes G into the form's workspace first).  FP64 tensor
+ *                    kernel only (no quadrature kernel, split modes, batches, operator action
+ *                    or affine-map entry). */
 typedef enum {
     FFC_MASS = 0, FFC_LAPLACE = 1, FFC_WLAPLACE = 2, FFC_ELASTICITY = 3, FFC_NS_CONVECTION = 4, FFC_PIOLA_MASS = 5,
     FFC_CURVED_LAPLACE = 6
