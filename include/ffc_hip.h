@@ -74,6 +74,13 @@ typedef enum {
  *                    (unit flux through the facet opposite vertex i); A^0 = int Psi_i,a1
  *                    Psi_j,a2, G^{a1 a2} = (1 / |det J|) (J^T J)_{a1 a2}; tensor kernel only
  *                    (no quadrature kernel, no batches)
+ *  FFC_NEDELEC_MASS  int v . u for Nedelec (Whitney edge) functions of the lowest order
+ *                    mapped by the covariant Piola transform (the H(curl) side of Sec. 3.4):
+ *                    degree 1 only; one dof per edge, edges in the P2 edge order below,
+ *                    oriented from the lower to the higher vertex, reference basis
+ *                    Psi_(a,b) = lambda_a grad lambda_b - lambda_b grad lambda_a; A^0 =
+ *                    int Psi_i,a1 Psi_j,a2 and G = |det J| (g g^T) -- the Laplacian's G; tensor
+ *                    kernel only (no quadrature kernel, no batches)
  *  FFC_CURVED_LAPLACE int grad u . grad v, u, v in P_q (q = 1, 2), on cells mapped by P2
  *                    geometry (the curvilinear elements of Sec. 3.4): the Jacobian varies
  *                    inside the cell, so the integral becomes a sum over the points X_p of a
@@ -88,7 +95,7 @@ typedef enum {
  *                    or affine-map entry). */
 typedef enum {
     FFC_MASS = 0, FFC_LAPLACE = 1, FFC_WLAPLACE = 2, FFC_ELASTICITY = 3, FFC_NS_CONVECTION = 4, FFC_PIOLA_MASS = 5,
-    FFC_CURVED_LAPLACE = 6
+    FFC_CURVED_LAPLACE = 6, FFC_NEDELEC_MASS = 7
 } ffc_kind;
 
 /* Arithmetic of the contraction.  FP64: FP64 MFMA, FP64 output.  Split modes: G and A^0

@@ -210,3 +210,25 @@ def curved_laplace(dim: int, degree: int, coords, m: int | None = None) -> np.nd
     Jinv = np.linalg.inv(J)               # [c][p][b][j]
     grad = np.einsum("cpbj,pib->cpij", Jinv, dphi)   # physical gradients [c][p][i][j]
     return np.einsum("cpij,cpkj,p,cp->cik", grad, grad, wts, np.abs(det))
+
+
+NEDELEC_EDGES = {2: ((1, 2), (0, 2), (0, 1)), 3: ((2, 3), (1, 3), (1, 2), (0, 3), (0, 2), (0, 1))}
+
+
+def nedelec_mass(dim: int, coords) -> np.ndarray:
+    """Mass matrices [cells, n_edges, n_edges] of the lowest-order Nedelec (Whitney edge)
+    space (the H(curl) side of Sec. 3.4), written on the physical cell: edge (a, b), a < b,
+    carries phi = lambda_a grad lambda_b - lambda_b grad lambda_a with the physical
+    barycentric coordinates; M_ij = int_K phi_i . phi_j by a collapsed rule exact for degree 3,
+    mapped to K (weights |det J|)."""
+    coords = np.ascontiguousarray(coords, dtype=np.float64)
+    cells = coords.shape[1]
+    X = np.transpose(coords.reshape(dim + 1, dim, cells), (2, 0, 1))   # [c][v][k]
+    T = np.concatenate([np.transpose(X, (0, 2, 1)), np.ones((cells, 1, dim + 1))], axis=1)  # [x; 1]
+    gl = np.linalg.inv(T)[:, :, :dim]                                    # [c][v][k] = d lambda_v / d x_k
+    adet = np.abs(np.linalg.det(X[:, 1:, :] - X[:, :1, :]))
+    pts, wts = collapsed_rule(dim, 2)
+    lam = np.concatenate([1.0 - pts.sum(axis=1, keepdims=True), pts], axis=1)  # [p][v] (affine: same in K)
+    phi = np.stack([lam[None, :, a, None] * gl[:, None, b, :] - lam[None, :, b, None] * gl[:, None, a, :]
+                    for a, b in NEDELEC_EDGES[dim]], axis=1)                 # [c][e][p][k]
+    return np.einsum("cipk,cjpk,p->cij", phi, phi, wts) * adet[:, None, None]

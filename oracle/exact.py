@@ -314,3 +314,17 @@ def piola_mass(verts):
                 s += K.integrate(pmul(comp[i][k], comp[j][k]))
             M[i][j] = s / (d * vol) ** 2
     return M
+
+
+def nedelec_mass(verts):
+    """Exact lowest-order Nedelec (Whitney edge) mass matrix on a rational cell: edge (a, b)
+    in the P2 edge order carries lambda_a grad lambda_b - lambda_b grad lambda_a, as Fractions."""
+    K = Cell(verts)
+    d = K.d
+    edges = ((1, 2), (0, 2), (0, 1)) if d == 2 else ((2, 3), (1, 3), (1, 2), (0, 3), (0, 2), (0, 1))
+    comps = []
+    for a, b in edges:
+        comps.append([padd(pscale(lam(d, a), K.dlam[b][k]), pscale(lam(d, b), -K.dlam[a][k])) for k in range(d)])
+    n = len(edges)
+    return [[sum((K.integrate(pmul(comps[i][k], comps[j][k])) for k in range(d)), Fraction(0)) for j in range(n)]
+            for i in range(n)]

@@ -14,7 +14,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libffc_hip.so")
 
-KINDS = {"mass": 0, "laplace": 1, "wlaplace": 2, "elasticity": 3, "ns": 4, "piola": 5, "curved": 6}
+KINDS = {"mass": 0, "laplace": 1, "wlaplace": 2, "elasticity": 3, "ns": 4, "piola": 5, "curved": 6, "nedelec": 7}
 PRECISIONS = {"fp64": 0, "bf16x3": 1, "bf16x6": 2}
 KERNELS = {"tensor": 1, "quadrature": 2}
 GEOMETRY = {"default": 0, "pass": 1, "fused": 2}

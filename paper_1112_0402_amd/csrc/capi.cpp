@@ -85,7 +85,8 @@ int check_desc(const ffc_form_desc* d, ffc::FormSpec* spec) {
         return fail(FFC_E_UNSUPPORTED, "unknown kernel");
     if (d->kernel == FFC_KERNEL_QUADRATURE && d->precision != FFC_FP64)
         return fail(FFC_E_UNSUPPORTED, "the quadrature kernel is FP64 only");
-    if (d->kernel == FFC_KERNEL_QUADRATURE && (d->kind == FFC_PIOLA_MASS || d->kind == FFC_CURVED_LAPLACE))
+    if (d->kernel == FFC_KERNEL_QUADRATURE &&
+        (d->kind == FFC_PIOLA_MASS || d->kind == FFC_CURVED_LAPLACE || d->kind == FFC_NEDELEC_MASS))
         return fail(FFC_E_UNSUPPORTED, "the quadrature kernel evaluates Lagrange forms on affine cells only");
     if (d->kind == FFC_CURVED_LAPLACE && d->precision != FFC_FP64)
         return fail(FFC_E_UNSUPPORTED, "the curvilinear Laplacian is FP64 only");
@@ -656,7 +657,7 @@ int ffc_batch_create(int32_t n, const ffc_form* const* forms, const int64_t* cel
         const ffc_form* f = forms[i];
         if (!f) return fail(FFC_E_INVALID, "NULL form in batch");
         if (f->desc.kernel != FFC_KERNEL_TENSOR) return fail(FFC_E_UNSUPPORTED, "batches use the tensor kernel only");
-        if (f->desc.kind == FFC_PIOLA_MASS || f->desc.kind == FFC_CURVED_LAPLACE)
+        if (f->desc.kind == FFC_PIOLA_MASS || f->desc.kind == FFC_CURVED_LAPLACE || f->desc.kind == FFC_NEDELEC_MASS)
             return fail(FFC_E_UNSUPPORTED, "batches take Lagrange forms on affine cells only");
         const bool bf = f->desc.precision != FFC_FP64;
         if (i == 0) {

@@ -28,7 +28,7 @@ typedef double d2v __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-enum { K_MASS = 0, K_LAPLACE = 1, K_WLAPLACE = 2, K_ELASTICITY = 3, K_NS = 4, K_PIOLA = 5, K_CURVED = 6 };
+enum { K_MASS = 0, K_LAPLACE = 1, K_WLAPLACE = 2, K_ELASTICITY = 3, K_NS = 4, K_PIOLA = 5, K_CURVED = 6, K_NEDELEC = 7 };
 
 // Launch with `lds` bytes of dynamic LDS; above 64 KiB the per-kernel limit is raised
 // first (gfx950 has 160 KiB per CU).
@@ -57,7 +57,7 @@ template <int KIND, int D>
 struct FormTraits {
     // G entries per cell; the symmetric geometry tensors keep each unordered index pair once
     static constexpr int n_alpha = KIND == K_MASS ? 1
-                                 : KIND == K_LAPLACE ? D * (D + 1) / 2
+                                 : KIND == K_LAPLACE || KIND == K_NEDELEC ? D * (D + 1) / 2
                                  : KIND == K_WLAPLACE ? (D + 1) * D * (D + 1) / 2
                                  : KIND == K_ELASTICITY ? D * D * (D * D + 1) / 2
                                  : KIND == K_PIOLA ? D * (D + 1) / 2
@@ -215,7 +215,8 @@ __device__ __forceinline__ double g_entry(const double* am, const double* cf, in
     auto g = [&](int a, int b) { return am[(1 + a * D + b) * CT + c]; };
     if constexpr (KIND == K_MASS) {
         return adet;
-    } else if constexpr (KIND == K_LAPLACE) {  // alpha = pair (a, b), a <= b
+    } else if constexpr (KIND == K_LAPLACE || KIND == K_NEDELEC) {  // alpha = pair (a, b), a <= b
+        // (Nedelec under the covariant Piola map: the same |det J| (g g^T)_ab)
         int a, b;
         upper_pair<D>(alpha, a, b);
         double s = 0.0;
@@ -593,6 +594,7 @@ static hipError_t launch_f64_d(int kind, int tile_cells, int waves, size_t lds, 
     case K_ELASTICITY: return launch_f64_mt<D, K_ELASTICITY>(tile_cells, waves, lds, a, s);
     case K_PIOLA: return launch_f64_mt<D, K_PIOLA>(tile_cells, waves, lds, a, s);
     case K_CURVED: return launch_f64_mt<D, K_CURVED>(tile_cells, waves, lds, a, s);
+    case K_NEDELEC: return launch_f64_mt<D, K_NEDELEC>(tile_cells, waves, lds, a, s);
     default: return launch_f64_mt<D, K_NS>(tile_cells, waves, lds, a, s);
     }
 }
@@ -732,6 +734,7 @@ static hipError_t launch_bf16_d(int kind, int tile_cells, int waves, size_t lds,
     case K_ELASTICITY: return launch_bf16_mt<D, K_ELASTICITY, NSEG>(tile_cells, waves, lds, a, s);
     case K_PIOLA: return launch_bf16_mt<D, K_PIOLA, NSEG>(tile_cells, waves, lds, a, s);
     case K_CURVED: return hipErrorInvalidValue;  // FP64 only
+    case K_NEDELEC: return launch_bf16_mt<D, K_NEDELEC, NSEG>(tile_cells, waves, lds, a, s);
     default: return launch_bf16_mt<D, K_NS, NSEG>(tile_cells, waves, lds, a, s);
     }
 }
@@ -1083,7 +1086,8 @@ static hipError_t launch_persistent_d(int kind, int kmax, int waves, int grid, s
     case K_WLAPLACE: return launch_persistent_k<D, K_WLAPLACE, ACT>(kmax, waves, grid, lds, a, p, s);
     case K_ELASTICITY: return launch_persistent_k<D, K_ELASTICITY, ACT>(kmax, waves, grid, lds, a, p, s);
     case K_PIOLA:
-    case K_CURVED: return hipErrorInvalidValue;  // tile kernels only
+    case K_CURVED:
+    case K_NEDELEC: return hipErrorInvalidValue;  // tile kernels only
     default: return launch_persistent_k<D, K_NS, ACT>(kmax, waves, grid, lds, a, p, s);
     }
 }
@@ -1151,6 +1155,7 @@ static hipError_t launch_apply_d(int kind, int tile_cells, unsigned grid, unsign
     case K_ELASTICITY: return launch_apply_k<D, K_ELASTICITY>(tile_cells, grid, block, lds, a, s);
     case K_PIOLA: return launch_apply_k<D, K_PIOLA>(tile_cells, grid, block, lds, a, s);
     case K_CURVED: return hipErrorInvalidValue;
+    case K_NEDELEC: return launch_apply_k<D, K_NEDELEC>(tile_cells, grid, block, lds, a, s);
     default: return launch_apply_k<D, K_NS>(tile_cells, grid, block, lds, a, s);
     }
 }
@@ -1407,7 +1412,8 @@ static hipError_t launch_bf16_persistent_d(int kind, int mt, int ks, int grid, s
     case K_WLAPLACE: return launch_bf16_persistent_k<D, K_WLAPLACE, NSEG>(mt, ks, grid, lds, a, s);
     case K_ELASTICITY: return launch_bf16_persistent_k<D, K_ELASTICITY, NSEG>(mt, ks, grid, lds, a, s);
     case K_PIOLA:
-    case K_CURVED: return hipErrorInvalidValue;
+    case K_CURVED:
+    case K_NEDELEC: return hipErrorInvalidValue;
     default: return launch_bf16_persistent_k<D, K_NS, NSEG>(mt, ks, grid, lds, a, s);
     }
 }
@@ -1814,7 +1820,7 @@ static hipError_t launch_quad_d(int kind, const QuadArgs& a, hipStream_t s) {
 
 hipError_t launch_quadrature(int dim, int kind, const QuadArgs& a, hipStream_t stream) {
     if (a.cells <= 0) return hipSuccess;
-    if (kind == K_PIOLA || kind == K_CURVED) return hipErrorInvalidValue;  // affine Lagrange forms only
+    if (kind == K_PIOLA || kind == K_CURVED || kind == K_NEDELEC) return hipErrorInvalidValue;  // affine Lagrange forms only
     return dim == 2 ? launch_quad_d<2>(kind, a, stream) : launch_quad_d<3>(kind, a, stream);
 }
 

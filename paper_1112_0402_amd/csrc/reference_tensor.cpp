@@ -211,6 +211,7 @@ int integrand_degree(int kind, int q) {
     case NS: return 2 * q;
     case PIOLA: return 2;
     case CURVED: return 2 * q - 2;
+    case NEDELEC: return 2;
     }
     return 2 * q;
 }
@@ -220,12 +221,12 @@ bool supported(const FormSpec& s, std::string* why) {
         *why = "dim must be 2 or 3";
         return false;
     }
-    if (s.kind < MASS || s.kind > CURVED) {
+    if (s.kind < MASS || s.kind > NEDELEC) {
         *why = "unknown form kind";
         return false;
     }
-    if (s.kind == PIOLA && s.degree != 1) {
-        *why = "Raviart-Thomas elements of the lowest order only (degree 1)";
+    if ((s.kind == PIOLA || s.kind == NEDELEC) && s.degree != 1) {
+        *why = "Raviart-Thomas and Nedelec elements of the lowest order only (degree 1)";
         return false;
     }
     int qmax = (s.kind == ELASTICITY || s.kind == NS) ? 3 : s.kind == CURVED ? 2 : 4;
@@ -281,6 +282,7 @@ bool build_reference_tensor(const FormSpec& s, ReferenceTensor* rt, std::string*
     rt->ns = B.n;
     const bool vec = (s.kind == ELASTICITY || s.kind == NS);
     rt->n = vec ? d * B.n : B.n;  // (PIOLA: the d + 1 vertices of P1 are also its d + 1 facets)
+    if (s.kind == NEDELEC) rt->n = d * (d + 1) / 2;  // one dof per edge
     rt->n_I = rt->n * rt->n;
     switch (s.kind) {
     case MASS: rt->n_alpha = 1; rt->n_coeff = 0; break;
@@ -290,6 +292,7 @@ bool build_reference_tensor(const FormSpec& s, ReferenceTensor* rt, std::string*
     case NS: rt->n_alpha = d * (d + 1) * d; rt->n_coeff = d * (d + 1); break;
     case PIOLA: rt->n_alpha = d * d; rt->n_coeff = 0; break;
     case CURVED: rt->n_alpha = 0; rt->n_coeff = 0; break;  // set below, with the rule
+    case NEDELEC: rt->n_alpha = d * d; rt->n_coeff = 0; break;
     }
     // CURVED: the Laplacian on cells mapped by P2 geometry (Sec. 3.4, curvilinear elements),
     // integration replaced by a sum over the points X_p of a collapsed Gauss-Jacobi rule with
@@ -373,6 +376,23 @@ bool build_reference_tensor(const FormSpec& s, ReferenceTensor* rt, std::string*
                             at(i, j, p * np + pr) = cwts[p] * v;
                         }
                 }
+    } else if (s.kind == NEDELEC) {
+        // Psi_(a,b) = lambda_a grad lambda_b - lambda_b grad lambda_a, edges in the P2 edge order;
+        // A^0[(i,j)][(a1,a2)] = int_K0 Psi_i,a1 Psi_j,a2
+        static const int E2[3][2] = {{1, 2}, {0, 2}, {0, 1}};
+        static const int E3[6][2] = {{2, 3}, {1, 3}, {1, 2}, {0, 3}, {0, 2}, {0, 1}};
+        auto dlam = [&](int v, int a) -> ld { return v == 0 ? -1 : (v - 1 == a ? 1 : 0); };
+        auto psi = [&](int e, int a) {
+            const int va = d == 2 ? E2[e][0] : E3[e][0], vb = d == 2 ? E2[e][1] : E3[e][1];
+            Poly p;
+            for (const auto& t : p1(d, va)) p[t.first] += t.second * dlam(vb, a);
+            for (const auto& t : p1(d, vb)) p[t.first] -= t.second * dlam(va, a);
+            return p;
+        };
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j)
+                for (int a1 = 0; a1 < d; ++a1)
+                    for (int a2 = 0; a2 < d; ++a2) at(i, j, a1 * d + a2) = integrate(mul(psi(i, a1), psi(j, a2)), d);
     } else if (s.kind == PIOLA) {
         // Psi_i = (X - V_i) / (d |K0|) = (d-1)! (X - V_i), V_0 = 0, V_k = e_k;
         // A^0[(i,j)][(a1,a2)] = int_K0 Psi_i,a1 Psi_j,a2
@@ -423,6 +443,7 @@ int folded_n_alpha(int kind, int d) {
     switch (kind) {
     case LAPLACE: return d * (d + 1) / 2;
     case PIOLA: return d * (d + 1) / 2;
+    case NEDELEC: return d * (d + 1) / 2;
     case WLAPLACE: return (d + 1) * d * (d + 1) / 2;
     case ELASTICITY: return d * d * (d * d + 1) / 2;
     case MASS: return 1;
@@ -432,7 +453,7 @@ int folded_n_alpha(int kind, int d) {
 
 ReferenceTensor fold_symmetric_g(const ReferenceTensor& rt) {
     const int kind = rt.spec.kind, d = rt.spec.dim;
-    if (kind != LAPLACE && kind != WLAPLACE && kind != ELASTICITY && kind != PIOLA) return rt;
+    if (kind != LAPLACE && kind != WLAPLACE && kind != ELASTICITY && kind != PIOLA && kind != NEDELEC) return rt;
     // pair index space: N indices per side, `outer` independent copies (weight dofs)
     const int N = kind == ELASTICITY ? d * d : d;
     const int outer = kind == WLAPLACE ? d + 1 : 1;

@@ -10,7 +10,7 @@
 
 namespace ffc {
 
-enum Kind { MASS = 0, LAPLACE = 1, WLAPLACE = 2, ELASTICITY = 3, NS = 4, PIOLA = 5, CURVED = 6 };
+enum Kind { MASS = 0, LAPLACE = 1, WLAPLACE = 2, ELASTICITY = 3, NS = 4, PIOLA = 5, CURVED = 6, NEDELEC = 7 };
 
 struct FormSpec {
     int kind = 0, dim = 2, degree = 1;

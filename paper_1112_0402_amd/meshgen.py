@@ -123,7 +123,7 @@ def p1_vector_coeffs(cells: np.ndarray, vertex_values: np.ndarray) -> np.ndarray
 
 # --------------------------------------------------------------------------- forms ---
 
-FORM_KINDS = ("mass", "laplace", "wlaplace", "elasticity", "ns", "piola")
+FORM_KINDS = ("mass", "laplace", "wlaplace", "elasticity", "ns", "piola", "nedelec")
 
 
 @dataclass

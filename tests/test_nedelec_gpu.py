@@ -1,0 +1,65 @@
+"""GPU parity of the H(curl) example: lowest-order Nedelec (Whitney edge) mass matrices under the
+covariant Piola map (Sec. 3.4), tensor representation on MFMA against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1112_0402_amd import capi, meshgen
+from paper_1112_0402_amd.forms import Batch, Form
+from tests.gpu_util import rel_fro, require_gpu, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("dim,n", [(2, 23), (3, 7)])
+@pytest.mark.parametrize("launch", [dict(), dict(tile_cells=16), dict(tile_cells=32, waves=8, geometry="pass"),
+                                    dict(symmetry=-1)])
+def test_nedelec_mass_fp64_matches_oracle(dim, n, launch):
+    require_gpu()
+    wl = meshgen.make_workload("nedelec", dim, 1, n, 29)
+    f = Form("nedelec", dim, 1, **launch)
+    got = f.tabulate(to_dev(wl.coords)).cpu().numpy()
+    ref = oracle.nedelec_mass(dim, wl.coords)
+    emax, _ = rel_fro(got, ref)
+    say(f"[nedelec] d={dim} {launch}: {wl.cells} cells, max {emax:.2e}")
+    assert emax <= 1e-12
+    ne = dim * (dim + 1) // 2
+    m = got.reshape(-1, ne, ne)
+    if f.info["symmetric"]:
+        assert np.array_equal(m, m.transpose(0, 2, 1))
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_nedelec_split_bf16_action_and_orientation(dim):
+    require_gpu()
+    wl = meshgen.make_workload("nedelec", dim, 1, 9 if dim == 2 else 5, 31)
+    ref = oracle.nedelec_mass(dim, wl.coords)
+    e6 = rel_fro(Form("nedelec", dim, 1, precision="bf16x6").tabulate(to_dev(wl.coords)).cpu().numpy(), ref)[0]
+    e3 = rel_fro(Form("nedelec", dim, 1, precision="bf16x3").tabulate(to_dev(wl.coords)).cpu().numpy(), ref)[0]
+    say(f"[nedelec split] d={dim}: x6 {e6:.2e}, x3 {e3:.2e}")
+    assert e6 <= 1e-6 and e3 <= 1e-4
+    f = Form("nedelec", dim, 1)
+    x = np.random.default_rng(1).normal(size=(wl.cells, dim * (dim + 1) // 2))
+    y = f.apply(to_dev(wl.coords), to_dev(x)).cpu().numpy()
+    yr = np.einsum("cij,cj->ci", ref, x)
+    assert np.abs(y - yr).max() <= 1e-12 * np.abs(yr).max()
+    # two vertices swapped (reversed orientation; edge directions follow the vertex order)
+    cells = wl.cells
+    X = wl.coords.T.reshape(cells, dim + 1, dim).copy()
+    X[:, [1, 2]] = X[:, [2, 1]]
+    cr = np.ascontiguousarray(X.reshape(cells, -1).T)
+    got = f.tabulate(to_dev(cr)).cpu().numpy()
+    assert rel_fro(got, oracle.nedelec_mass(dim, cr))[0] <= 1e-12
+
+
+def test_nedelec_unsupported_paths():
+    require_gpu()
+    with pytest.raises(capi.FFCError):
+        Form("nedelec", 2, 1, kernel="quadrature")
+    with pytest.raises(capi.FFCError):
+        Form("nedelec", 3, 2)
+    wl = meshgen.make_workload("nedelec", 2, 1, 3, 1)
+    f = Form("nedelec", 2, 1)
+    with pytest.raises(capi.FFCError):
+        Batch([f], [to_dev(wl.coords)], [None], [f.empty_out(wl.cells)])
