@@ -333,7 +333,8 @@ LdsPlan plan_lds(int dim, int kind, int tile_cells, int n_I, int n_alpha, int kp
     p.stage_bytes = align16(static_cast<size_t>(tile_cells) * n_I * ob);
     // head rows: affine map and coefficients, or (curvilinear cells) the P2 node coordinates
     const int rows = kind == K_CURVED ? (dim == 2 ? 12 : 30) : 1 + dim * dim + n_coeff_of(dim, kind);
-    const size_t head = align16(static_cast<size_t>(rows) * tile_cells * sizeof(double));
+    // (tile_cells + 1 per row: the persistent kernels pad the row stride)
+    const size_t head = align16(static_cast<size_t>(rows) * (tile_cells + 1) * sizeof(double));
     const size_t g = bf16 ? static_cast<size_t>(tile_cells) * (kpad + 8) * sizeof(uint16_t)
                           : static_cast<size_t>(tile_cells) * (n_alpha | 1) * sizeof(double);
     p.head_bytes = head;
@@ -848,8 +849,11 @@ __device__ __forceinline__ void persistent_tiles(const ContractArgs& A, const Pe
     // flight must wait for them before reusing their source registers, so keeping stores
     // out of the compute waves lets the write-out of one tile overlap the next contraction.
     double* st = reinterpret_cast<double*>(smem_raw);
-    double* am = reinterpret_cast<double*>(smem_raw + A.stage_bytes);  // [ROWS][CT]: map rows, then coefficients
-    double* cf = am + (1 + D * D) * CT;
+    // [ROWS][AS]: map rows, then coefficients; the odd row stride AS = CT + 1 spreads the rows
+    // of one cell over the LDS banks (the G build reads several rows of one cell per wave)
+    constexpr int AS = CT + 1;
+    double* am = reinterpret_cast<double*>(smem_raw + A.stage_bytes);
+    double* cf = am + (1 + D * D) * AS;
     double* Gs = reinterpret_cast<double*>(smem_raw + A.stage_bytes + A.head_bytes);
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -945,7 +949,7 @@ __device__ __forceinline__ void persistent_tiles(const ContractArgs& A, const Pe
         const bool more = ct + step < ct_end;
         double* nxt_out = nullptr;
         int64_t nxt_n = 0;
-        if (tid < ROWS * CT) am[tid] = pre;
+        if (tid < ROWS * CT) am[(tid / CT) * AS + tid % CT] = pre;
         if constexpr (ACT) {
             if (tid >= io_begin) {
                 double* xb = xs + xbuf * CT * nd;
@@ -965,7 +969,7 @@ __device__ __forceinline__ void persistent_tiles(const ContractArgs& A, const Pe
         lds_barrier();
         for (int i = tid; i < CT * NA; i += blockDim.x) {
             const int c = i / NA, al = i - c * NA;
-            Gs[c * GS + al] = g_entry<KIND, D>(am, cf, CT, c, al);
+            Gs[c * GS + al] = g_entry<KIND, D>(am, cf, AS, c, al);
         }
         for (int i = tid; i < CT * P.n_zero && tid < io_begin; i += io_begin) {
             const int c = i / P.n_zero;
@@ -1207,8 +1211,9 @@ __device__ __forceinline__ void persistent_tiles_bf16(const ContractArgs& A, Src
     // tile in R[4j .. 4j+3]
     constexpr int NR = KS > IOS ? 4 * KS : 4 * IOS;
     float* st = reinterpret_cast<float*>(smem_raw);
+    constexpr int AS = CT + 1;  // odd row stride of the map/coefficient rows (LDS banks)
     double* am = reinterpret_cast<double*>(smem_raw + A.stage_bytes);
-    double* cf = am + (1 + D * D) * CT;
+    double* cf = am + (1 + D * D) * AS;
     unsigned short* Gp = reinterpret_cast<unsigned short*>(smem_raw + A.stage_bytes + A.head_bytes);
     const int kpad = A.kpad;
     const int GK = kpad + 8;  // row stride of the G pieces (BF16 values)
@@ -1292,7 +1297,7 @@ __device__ __forceinline__ void persistent_tiles_bf16(const ContractArgs& A, Src
         const bool more = ct + step < ct_end;
         float* nxt_out = nullptr;
         int64_t nxt_n = 0;
-        if (tid < ROWS * CT) am[tid] = pre;
+        if (tid < ROWS * CT) am[(tid / CT) * AS + tid % CT] = pre;
         if (more) {
             const MeshTile t = src.at(ct + step);
             out_run(t, nxt_out, nxt_n);
@@ -1301,7 +1306,7 @@ __device__ __forceinline__ void persistent_tiles_bf16(const ContractArgs& A, Src
         lds_barrier();
         for (int i = tid; i < CT * NA; i += blockDim.x) {
             const int c = i / NA, al = i - c * NA;
-            const double gv = g_entry<KIND, D>(am, cf, CT, c, al);
+            const double gv = g_entry<KIND, D>(am, cf, AS, c, al);
             double piece[3];
             piece[0] = rn_bf16(gv);
             piece[1] = rn_bf16(gv - piece[0]);
