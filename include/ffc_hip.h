@@ -15,6 +15,11 @@
  *      paper proposes (Sec. 3.5, "Optimization");
  * and, as the in-GPU comparison, a plain quadrature kernel (pretabulated basis at the
  * points of a collapsed-coordinate Gauss-Jacobi rule exact for the integrand, Sec. 6).
+ * Also here: split-BF16 contraction modes, mixed batches in a short fixed launch sequence
+ * (ffc_batch_*), global assembly into CSR (ffc_assembly_*, ffc_assemble; Algorithm 2),
+ * the operator action without writing element tensors (ffc_apply_tensor,
+ * ffc_operator_apply), the H(div) / H(curl) and curvilinear extensions of Sec. 3.4 as
+ * form kinds, and the kernel selector network's kernels (ffc_mlp_*, ffc_adam_step).
  *
  * Conventions shared by every entry point
  *  - Reference simplex K0: vertex 0 at the origin, vertex k at the k-th unit vector
@@ -29,7 +34,7 @@
  *    argument of a(v, u)), n = element dofs.
  *  - |det J| is used (the paper's det F'_K for positively oriented cells).
  *  - coords (device, FP64, SoA): coords[(v * d + k) * cells + c] = coordinate k of local
- *    vertex v of cell c.
+ *    vertex v of cell c (FFC_CURVED_LAPLACE: v runs over the cell's P2 nodes).
  *  - coeffs (device, FP64, SoA): coeffs[j * cells + c]; weighted Laplacian: j = vertex
  *    (w in P1); Navier-Stokes: j = comp * (d + 1) + vertex (w in vector P1).  NULL for
  *    forms without coefficients.
