@@ -613,6 +613,8 @@ def main() -> int:
                     help="FP64 symmetric forms: 0 computes the entries i1 <= i2 only, -1 every entry")
     ap.add_argument("--tile-window", type=int, default=0,
                     help="grouping of output entries into MFMA tiles (0 = library default)")
+    ap.add_argument("--write-ceiling", action="store_true",
+                    help="measure a plain 5.4 GB fill and copy (torch kernels): the practical streaming ceilings")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -636,6 +638,24 @@ def main() -> int:
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_read": src.numel() * 8, "bytes_written": dst.numel() * 8}))
+        return 0
+    if args.write_ceiling:
+        # practical HBM ceilings for streaming kernels: a plain fill (writes only) and a copy
+        # (reads + writes) of the elasticity workload's output size, torch's own kernels
+        n = 675_000_000  # 5.4 GB of FP64
+        dst = torch.empty(n, dtype=torch.float64, device="cuda")
+        src = torch.empty(n // 2, dtype=torch.float64, device="cuda").fill_(1.0)
+        half = dst[: n // 2]
+        for _ in range(3):
+            dst.fill_(0.5)
+            half.copy_(src)
+        torch.cuda.synchronize()
+        s = torch.cuda.current_stream()
+        fill_ms = timed(lambda: dst.fill_(0.5), args.steps, s, torch)
+        copy_ms = timed(lambda: half.copy_(src), args.steps, s, torch)
+        print(json.dumps({"fill_write_tbs": n * 8 / (fill_ms * 1e-3) / 1e12, "fill_ms": fill_ms,
+                          "copy_read_plus_write_tbs": n * 8 / (copy_ms * 1e-3) / 1e12, "copy_ms": copy_ms,
+                          "bytes_written_fill": n * 8}))
         return 0
     if args.workload == "batch":
         result = bench_batch(args, torch, np)
