@@ -845,8 +845,9 @@ __device__ __forceinline__ void persistent_tiles(const ContractArgs& A, const Pe
     constexpr int NR = (ACT || 3 * KMAX > 4 * IOS) ? 3 * KMAX : 4 * IOS;
     // Wave roles: the first blockDim/64 - kIoWaves waves ("compute waves") prefetch the next
     // tile's affine map and coefficients and run the MFMA steps; the last kIoWaves waves
-    // move the staged output to global memory and nothing else.  A wave that has stores in
-    // flight must wait for them before reusing their source registers, so keeping stores
+    // move the staged output to global memory and nothing else.  On this architecture one
+    // counter (vmcnt) tracks a wave's loads and stores in issue order, so a wave waiting for
+    // its prefetched map would also wait for every store it issued before; keeping stores
     // out of the compute waves lets the write-out of one tile overlap the next contraction.
     double* st = reinterpret_cast<double*>(smem_raw);
     // [ROWS][AS]: map rows, then coefficients; the odd row stride AS = CT + 1 spreads the rows
