@@ -82,8 +82,10 @@ def timed(fn, steps, stream, torch):
     return float(sum(a.elapsed_time(b) for a, b in ev) / steps)
 
 
-def cpu_baseline(wl, out_fn, seconds, np):
-    """The oracle on the host cores over a bounded prefix of the same mesh."""
+def cpu_baseline(wl, out_fn, seconds, np, quad_head=None):
+    """The oracle on the host cores over a bounded prefix of the same mesh; quad_head: the
+    quadrature kernel's element tensors of the first cells, checked against the same oracle
+    values."""
     import oracle
 
     threads = oracle.max_threads()
@@ -111,7 +113,13 @@ def cpu_baseline(wl, out_fn, seconds, np):
         "sample": f"first {sample} cells of the same {wl.cells}-cell mesh, FP64 quadrature on the physical "
                   f"cell, OpenMP over cells ({threads} threads), {dt:.1f} s wall",
     }
-    return base, {"max": float(err.max()), "median": float(np.median(err)), "cells": sample}
+    errs = {"max": float(err.max()), "median": float(np.median(err)), "cells": sample}
+    if quad_head is not None:
+        k = min(len(quad_head), sample)
+        q = quad_head[:k].reshape(k, -1)
+        qe = np.linalg.norm(q - r[:k], axis=1) / np.linalg.norm(r[:k], axis=1)
+        errs["quadrature_kernel"] = {"max": float(qe.max()), "median": float(np.median(qe)), "cells": k}
+    return base, errs
 
 
 def bench_single(args, torch, np):
@@ -276,21 +284,36 @@ def bench_single(args, torch, np):
             qform.tabulate(X, C, out=qout)
         torch.cuda.synchronize()
         q_ms = timed(lambda: qform.tabulate(X, C, out=qout), args.steps, stream, torch)
+        npts = qform.info["quad_points"]
+        # the paper's operation count for quadrature (Sec. 4.4): per entry and point, one
+        # product per coefficient function and per derivative direction, plus the weight
+        n_f, n_D = {"mass": (0, 0), "laplace": (0, 2), "wlaplace": (1, 2), "elasticity": (0, 2), "ns": (1, 1)}[wl.kind]
+        q_flops = n_I * npts * (n_f + n_D * d + 1)
+        q_bytes = cells * (ncoord * 8 + nco * 8 + n_I * 8)
         result["quadrature_kernel"] = {
             "value": cells / (q_ms * 1e-3),
             "unit": "element tensors/s",
             "dtype": "f64",
             "ms_per_launch": q_ms,
-            "quad_points": qform.info["quad_points"],
+            "quad_points": npts,
             "speedup_tensor_over_quadrature": q_ms / ms_step,
-            "achieved_gbs": cells * (ncoord * 8 + nco * 8 + n_I * 8) / (q_ms * 1e-3) / 1e9,
+            "achieved_gbs": q_bytes / (q_ms * 1e-3) / 1e9,
+            "hbm_frac": q_bytes / (q_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "model_flops_per_cell": q_flops,
+            "model_tflops": cells * q_flops / (q_ms * 1e-3) / 1e12,
+            "fp64_frac": cells * q_flops / (q_ms * 1e-3) / 1e12 / FP64_MFMA_PEAK_TF,
         }
+        if not args.no_cpu_baseline:
+            quad_head = qout[: min(cells, 4096)].cpu().numpy()
         del qout, qform
 
     if not args.no_cpu_baseline:
-        base, err = cpu_baseline(wl, lambda n: out[:n].cpu().numpy(), args.cpu_seconds, np)
+        base, err = cpu_baseline(wl, lambda n: out[:n].cpu().numpy(), args.cpu_seconds, np,
+                                 None if args.no_quadrature else quad_head)
         result["cpu_baseline"] = base
         err["tol"] = 1e-12 if not bf16 else (1e-6 if precision == "bf16x6" else None)
+        if "quadrature_kernel" in err:
+            err["quadrature_kernel"]["tol"] = 1e-12
         result["rel_err_vs_oracle"] = err
     return result
 
