@@ -71,6 +71,14 @@ def load_traffic(workload: str, cells: int):
         return None
 
 
+def quadrature_model_flops(kind: str, n_I: int, n_pts: int, dim: int) -> int:
+    """The paper's operation count for quadrature (Sec. 4.4) per cell: for each element-tensor
+    entry and quadrature point, one product per coefficient function and per derivative
+    direction, plus one for the weight."""
+    n_f, n_D = {"mass": (0, 0), "laplace": (0, 2), "wlaplace": (1, 2), "elasticity": (0, 2), "ns": (1, 1)}[kind]
+    return n_I * n_pts * (n_f + n_D * dim + 1)
+
+
 def timed(fn, steps, stream, torch):
     """Mean milliseconds of fn() over `steps` launches, HIP events on the launch stream."""
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
@@ -285,10 +293,7 @@ def bench_single(args, torch, np):
         torch.cuda.synchronize()
         q_ms = timed(lambda: qform.tabulate(X, C, out=qout), args.steps, stream, torch)
         npts = qform.info["quad_points"]
-        # the paper's operation count for quadrature (Sec. 4.4): per entry and point, one
-        # product per coefficient function and per derivative direction, plus the weight
-        n_f, n_D = {"mass": (0, 0), "laplace": (0, 2), "wlaplace": (1, 2), "elasticity": (0, 2), "ns": (1, 1)}[wl.kind]
-        q_flops = n_I * npts * (n_f + n_D * d + 1)
+        q_flops = quadrature_model_flops(wl.kind, n_I, npts, d)
         q_bytes = cells * (ncoord * 8 + nco * 8 + n_I * 8)
         result["quadrature_kernel"] = {
             "value": cells / (q_ms * 1e-3),
