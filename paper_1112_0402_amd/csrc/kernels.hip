@@ -1762,50 +1762,97 @@ __global__ __launch_bounds__(256) void quadrature_kernel(QuadArgs A) {
         }
     }
     __syncthreads();
-    // entries
-    for (int i = tid; i < QC * nI; i += nthr) {
-        const int c = i / nI, e = i - c * nI;
+    // entries: each thread takes a run of up to QE consecutive entries of one row (test
+    // function i1), so that row's values at a point are read from LDS once for the run
+    constexpr int QE = 4;
+    const int runs = (n + QE - 1) / QE;  // runs per row
+    for (int i = tid; i < QC * n * runs; i += nthr) {
+        const int c = i / (n * runs), r = i - c * (n * runs);
+        const int i1 = r / runs, j0 = (r - i1 * runs) * QE;
+        const int jn = n - j0 < QE ? n - j0 : QE;
         const int64_t cell = c0 + c;
         if (cell >= A.cells) continue;
         const double* geo = slots + c * slot;
         const double* W = geo + 1 + D * D;
         const double* grad = W + NQ;
-        const int i1 = e / n, i2 = e - i1 * n;
-        double acc = 0.0;
+        double acc[QE];
+#pragma unroll
+        for (int j = 0; j < QE; ++j) acc[j] = 0.0;
         if constexpr (KIND == K_MASS) {
-            for (int q = 0; q < NQ; ++q) acc += W[q] * phis[q * ns + i1] * phis[q * ns + i2];
+            for (int q = 0; q < NQ; ++q) {
+                const double wi = W[q] * phis[q * ns + i1];
+#pragma unroll
+                for (int j = 0; j < QE; ++j)
+                    if (j < jn) acc[j] += wi * phis[q * ns + j0 + j];
+            }
         } else if constexpr (KIND == K_LAPLACE || KIND == K_WLAPLACE) {
             for (int q = 0; q < NQ; ++q) {
-                const double* gi = grad + (q * ns + i1) * D;
-                const double* gj = grad + (q * ns + i2) * D;
-                double dot = 0.0;
+                double gi[D];
 #pragma unroll
-                for (int k = 0; k < D; ++k) dot += gi[k] * gj[k];
-                acc += W[q] * dot;
+                for (int k = 0; k < D; ++k) gi[k] = grad[(q * ns + i1) * D + k];
+#pragma unroll
+                for (int j = 0; j < QE; ++j) {
+                    if (j < jn) {
+                        const double* gj = grad + (q * ns + j0 + j) * D;
+                        double dot = 0.0;
+#pragma unroll
+                        for (int k = 0; k < D; ++k) dot += gi[k] * gj[k];
+                        acc[j] += W[q] * dot;
+                    }
+                }
             }
         } else if constexpr (KIND == K_ELASTICITY) {
-            const int c1 = i1 / ns, s1 = i1 - c1 * ns, c2 = i2 / ns, s2 = i2 - c2 * ns;
+            const int c1 = i1 / ns, s1 = i1 - c1 * ns;
             const double mu = A.mu, lam = A.lambda;
-            for (int q = 0; q < NQ; ++q) {
-                const double* gi = grad + (q * ns + s1) * D;
-                const double* gj = grad + (q * ns + s2) * D;
-                double v = mu * gi[c2] * gj[c1] + lam * gi[c1] * gj[c2];
-                if (c1 == c2) {
-                    double dot = 0.0;
+            int c2[QE], s2[QE];  // component and scalar dof of each entry's trial function
 #pragma unroll
-                    for (int k = 0; k < D; ++k) dot += gi[k] * gj[k];
-                    v += mu * dot;
+            for (int j = 0; j < QE; ++j) {
+                c2[j] = (j0 + j) / ns;
+                s2[j] = j0 + j - c2[j] * ns;
+            }
+            for (int q = 0; q < NQ; ++q) {
+                double gi[D];
+#pragma unroll
+                for (int k = 0; k < D; ++k) gi[k] = grad[(q * ns + s1) * D + k];
+                const double gi1 = c1 == 0 ? gi[0] : c1 == 1 ? gi[1] : gi[D - 1];
+#pragma unroll
+                for (int j = 0; j < QE; ++j) {
+                    if (j < jn) {
+                        const double* gj = grad + (q * ns + s2[j]) * D;
+                        const double gi2 = c2[j] == 0 ? gi[0] : c2[j] == 1 ? gi[1] : gi[D - 1];
+                        double v = mu * gi2 * gj[c1] + lam * gi1 * gj[c2[j]];
+                        if (c1 == c2[j]) {
+                            double dot = 0.0;
+#pragma unroll
+                            for (int k = 0; k < D; ++k) dot += gi[k] * gj[k];
+                            v += mu * dot;
+                        }
+                        acc[j] += W[q] * v;
+                    }
                 }
-                acc += W[q] * v;
             }
         } else {  // NS
-            const int c1 = i1 / ns, s1 = i1 - c1 * ns, c2 = i2 / ns, s2 = i2 - c2 * ns;
-            if (c1 == c2) {
-                const double* conv = grad + NQ * ns * D;
-                for (int q = 0; q < NQ; ++q) acc += W[q] * phis[q * ns + s1] * conv[q * ns + s2];
+            const int c1 = i1 / ns, s1 = i1 - c1 * ns;
+            const double* conv = grad + NQ * ns * D;
+            int s2[QE];
+            bool on[QE];  // the entry couples equal components
+#pragma unroll
+            for (int j = 0; j < QE; ++j) {
+                const int c2 = (j0 + j) / ns;
+                s2[j] = j0 + j - c2 * ns;
+                on[j] = j < jn && c2 == c1;
+            }
+            for (int q = 0; q < NQ; ++q) {
+                const double wi = W[q] * phis[q * ns + s1];
+#pragma unroll
+                for (int j = 0; j < QE; ++j)
+                    if (on[j]) acc[j] += wi * conv[q * ns + s2[j]];
             }
         }
-        A.out[cell * nI + e] = acc;
+        double* o = A.out + cell * nI + i1 * n + j0;
+#pragma unroll
+        for (int j = 0; j < QE; ++j)
+            if (j < jn) o[j] = acc[j];
     }
 }
 
