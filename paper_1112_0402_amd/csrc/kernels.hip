@@ -1661,10 +1661,180 @@ int quad_cells_per_block(int dim, int kind, int ns, int npts) {
     return qc;
 }
 
+// Entries of the quadrature kernel: each thread takes a block of QR rows (test functions) by
+// QE consecutive columns (trial functions), so each function's values at a point are read
+// from LDS once for the block (mass, Laplacian, weighted Laplacian, NS convection).  slots:
+// per cell |det|, g, then per point the weight, the physical gradients [point][function][D]
+// and (NS) the convection term [point][function].
+template <int D, int KIND, int QR, int QE>
+__device__ __forceinline__ void quad_entries(const QuadArgs& A, const double* phis, const double* slots, int slot,
+                                             int64_t c0) {
+    const int ns = A.ns, n = A.n, nI = A.n_I, NQ = A.npts, QC = A.cells_per_block;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int rblocks = (n + QR - 1) / QR, runs = (n + QE - 1) / QE;
+    for (int i = tid; i < QC * rblocks * runs; i += nthr) {
+        const int c = i / (rblocks * runs), r = i - c * (rblocks * runs);
+        const int rb = r / runs, j0 = (r - rb * runs) * QE, i0 = rb * QR;
+        const int64_t cell = c0 + c;
+        if (cell >= A.cells) continue;
+        const double* geo = slots + c * slot;
+        const double* W = geo + 1 + D * D;
+        const double* grad = W + NQ;
+        // rows and columns past n repeat the last function (computed, never stored)
+        int fr[QR], fc[QE];  // scalar basis function of each row / column
+        int cr[QR], cc[QE];  // vector component (vector forms)
+#pragma unroll
+        for (int a = 0; a < QR; ++a) {
+            const int i1 = i0 + a < n ? i0 + a : n - 1;
+            cr[a] = i1 / ns;
+            fr[a] = i1 - cr[a] * ns;
+        }
+#pragma unroll
+        for (int j = 0; j < QE; ++j) {
+            const int i2 = j0 + j < n ? j0 + j : n - 1;
+            cc[j] = i2 / ns;
+            fc[j] = i2 - cc[j] * ns;
+        }
+        double acc[QR][QE];
+#pragma unroll
+        for (int a = 0; a < QR; ++a)
+#pragma unroll
+            for (int j = 0; j < QE; ++j) acc[a][j] = 0.0;
+        for (int q = 0; q < NQ; ++q) {
+            const double wq = W[q];
+            if constexpr (KIND == K_MASS || KIND == K_NS) {
+                const double* conv = grad + NQ * ns * D;  // NS: (w . grad) phi at the points
+                double rv[QR], cv[QE];
+#pragma unroll
+                for (int a = 0; a < QR; ++a) rv[a] = wq * phis[q * ns + fr[a]];
+#pragma unroll
+                for (int j = 0; j < QE; ++j) cv[j] = KIND == K_MASS ? phis[q * ns + fc[j]] : conv[q * ns + fc[j]];
+#pragma unroll
+                for (int a = 0; a < QR; ++a)
+#pragma unroll
+                    for (int j = 0; j < QE; ++j)
+                        if (KIND == K_MASS || cr[a] == cc[j]) acc[a][j] += rv[a] * cv[j];
+            } else {
+                double rv[QR][D], cv[QE][D];
+#pragma unroll
+                for (int a = 0; a < QR; ++a)
+#pragma unroll
+                    for (int k = 0; k < D; ++k) rv[a][k] = grad[(q * ns + fr[a]) * D + k];
+#pragma unroll
+                for (int j = 0; j < QE; ++j)
+#pragma unroll
+                    for (int k = 0; k < D; ++k) cv[j][k] = grad[(q * ns + fc[j]) * D + k];
+#pragma unroll
+                for (int a = 0; a < QR; ++a) {
+#pragma unroll
+                    for (int j = 0; j < QE; ++j) {
+                        double dot = 0.0;
+#pragma unroll
+                        for (int k = 0; k < D; ++k) dot += rv[a][k] * cv[j][k];
+                        acc[a][j] += wq * dot;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < QR; ++a) {
+            if (i0 + a >= n) break;
+            double* o = A.out + cell * nI + (i0 + a) * n + j0;
+#pragma unroll
+            for (int j = 0; j < QE; ++j)
+                if (j0 + j < n) o[j] = acc[a][j];
+        }
+    }
+}
+
+// Elasticity entries: a thread takes ER x EC pairs of scalar functions (s1, s2) and forms all
+// D x D component pairs of each from one table of products of their gradients.
+template <int D>
+__device__ __forceinline__ void quad_entries_elasticity(const QuadArgs& A, const double* slots, int slot,
+                                                        int64_t c0) {
+    constexpr int ER = 2, EC = 2;
+    const int ns = A.ns, n = A.n, nI = A.n_I, NQ = A.npts, QC = A.cells_per_block;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int sb = (ns + ER - 1) / ER, sr = (ns + EC - 1) / EC;
+    const double mu = A.mu, lam = A.lambda;
+    for (int i = tid; i < QC * sb * sr; i += nthr) {
+        const int c = i / (sb * sr), r = i - c * (sb * sr);
+        const int s10 = (r / sr) * ER, s20 = (r - (r / sr) * sr) * EC;
+        const int64_t cell = c0 + c;
+        if (cell >= A.cells) continue;
+        const double* geo = slots + c * slot;
+        const double* W = geo + 1 + D * D;
+        const double* grad = W + NQ;
+        int f1[ER], f2[EC];  // functions past ns repeat the last one (computed, never stored)
+#pragma unroll
+        for (int a = 0; a < ER; ++a) f1[a] = s10 + a < ns ? s10 + a : ns - 1;
+#pragma unroll
+        for (int b = 0; b < EC; ++b) f2[b] = s20 + b < ns ? s20 + b : ns - 1;
+        double acc[ER][EC][D][D];
+#pragma unroll
+        for (int a = 0; a < ER; ++a)
+#pragma unroll
+            for (int b = 0; b < EC; ++b)
+#pragma unroll
+                for (int k = 0; k < D; ++k)
+#pragma unroll
+                    for (int l = 0; l < D; ++l) acc[a][b][k][l] = 0.0;
+        for (int q = 0; q < NQ; ++q) {
+            const double wq = W[q];
+            double g1[ER][D], g2[EC][D];
+#pragma unroll
+            for (int a = 0; a < ER; ++a)
+#pragma unroll
+                for (int k = 0; k < D; ++k) g1[a][k] = grad[(q * ns + f1[a]) * D + k];
+#pragma unroll
+            for (int b = 0; b < EC; ++b)
+#pragma unroll
+                for (int k = 0; k < D; ++k) g2[b][k] = grad[(q * ns + f2[b]) * D + k];
+#pragma unroll
+            for (int a = 0; a < ER; ++a) {
+#pragma unroll
+                for (int b = 0; b < EC; ++b) {
+                    double P[D][D];  // P[k][l] = d phi_s1 / dx_k * d phi_s2 / dx_l
+                    double dot = 0.0;
+#pragma unroll
+                    for (int k = 0; k < D; ++k) {
+#pragma unroll
+                        for (int l = 0; l < D; ++l) P[k][l] = g1[a][k] * g2[b][l];
+                        dot += P[k][k];
+                    }
+                    // entry ((c1, s1), (c2, s2)): mu d_c2 phi_s1 d_c1 phi_s2 + lambda d_c1 phi_s1
+                    // d_c2 phi_s2, plus mu grad phi_s1 . grad phi_s2 when c1 = c2
+#pragma unroll
+                    for (int c1 = 0; c1 < D; ++c1)
+#pragma unroll
+                        for (int c2 = 0; c2 < D; ++c2) {
+                            double v = mu * P[c2][c1] + lam * P[c1][c2];
+                            if (c1 == c2) v += mu * dot;
+                            acc[a][b][c1][c2] += wq * v;
+                        }
+                }
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < ER; ++a) {
+            if (s10 + a >= ns) break;
+#pragma unroll
+            for (int c1 = 0; c1 < D; ++c1) {
+                double* o = A.out + cell * nI + static_cast<int64_t>(c1 * ns + s10 + a) * n;
+#pragma unroll
+                for (int c2 = 0; c2 < D; ++c2)
+#pragma unroll
+                    for (int b = 0; b < EC; ++b)
+                        if (s20 + b < ns) o[c2 * ns + s20 + b] = acc[a][b][c1][c2];
+            }
+        }
+    }
+}
+
 template <int D, int KIND>
 __global__ __launch_bounds__(256) void quadrature_kernel(QuadArgs A) {
     extern __shared__ double smem[];
-    const int ns = A.ns, n = A.n, nI = A.n_I, NQ = A.npts, QC = A.cells_per_block;
+    const int ns = A.ns, n = A.n, NQ = A.npts, QC = A.cells_per_block;
     const int slot = quad_slot_doubles(D, KIND, ns, NQ);
     double* phis = smem;                 // [NQ][ns]
     double* slots = smem + NQ * ns;      // [QC][slot]
@@ -1762,98 +1932,9 @@ __global__ __launch_bounds__(256) void quadrature_kernel(QuadArgs A) {
         }
     }
     __syncthreads();
-    // entries: each thread takes a run of up to QE consecutive entries of one row (test
-    // function i1), so that row's values at a point are read from LDS once for the run
-    constexpr int QE = 4;
-    const int runs = (n + QE - 1) / QE;  // runs per row
-    for (int i = tid; i < QC * n * runs; i += nthr) {
-        const int c = i / (n * runs), r = i - c * (n * runs);
-        const int i1 = r / runs, j0 = (r - i1 * runs) * QE;
-        const int jn = n - j0 < QE ? n - j0 : QE;
-        const int64_t cell = c0 + c;
-        if (cell >= A.cells) continue;
-        const double* geo = slots + c * slot;
-        const double* W = geo + 1 + D * D;
-        const double* grad = W + NQ;
-        double acc[QE];
-#pragma unroll
-        for (int j = 0; j < QE; ++j) acc[j] = 0.0;
-        if constexpr (KIND == K_MASS) {
-            for (int q = 0; q < NQ; ++q) {
-                const double wi = W[q] * phis[q * ns + i1];
-#pragma unroll
-                for (int j = 0; j < QE; ++j)
-                    if (j < jn) acc[j] += wi * phis[q * ns + j0 + j];
-            }
-        } else if constexpr (KIND == K_LAPLACE || KIND == K_WLAPLACE) {
-            for (int q = 0; q < NQ; ++q) {
-                double gi[D];
-#pragma unroll
-                for (int k = 0; k < D; ++k) gi[k] = grad[(q * ns + i1) * D + k];
-#pragma unroll
-                for (int j = 0; j < QE; ++j) {
-                    if (j < jn) {
-                        const double* gj = grad + (q * ns + j0 + j) * D;
-                        double dot = 0.0;
-#pragma unroll
-                        for (int k = 0; k < D; ++k) dot += gi[k] * gj[k];
-                        acc[j] += W[q] * dot;
-                    }
-                }
-            }
-        } else if constexpr (KIND == K_ELASTICITY) {
-            const int c1 = i1 / ns, s1 = i1 - c1 * ns;
-            const double mu = A.mu, lam = A.lambda;
-            int c2[QE], s2[QE];  // component and scalar dof of each entry's trial function
-#pragma unroll
-            for (int j = 0; j < QE; ++j) {
-                c2[j] = (j0 + j) / ns;
-                s2[j] = j0 + j - c2[j] * ns;
-            }
-            for (int q = 0; q < NQ; ++q) {
-                double gi[D];
-#pragma unroll
-                for (int k = 0; k < D; ++k) gi[k] = grad[(q * ns + s1) * D + k];
-                const double gi1 = c1 == 0 ? gi[0] : c1 == 1 ? gi[1] : gi[D - 1];
-#pragma unroll
-                for (int j = 0; j < QE; ++j) {
-                    if (j < jn) {
-                        const double* gj = grad + (q * ns + s2[j]) * D;
-                        const double gi2 = c2[j] == 0 ? gi[0] : c2[j] == 1 ? gi[1] : gi[D - 1];
-                        double v = mu * gi2 * gj[c1] + lam * gi1 * gj[c2[j]];
-                        if (c1 == c2[j]) {
-                            double dot = 0.0;
-#pragma unroll
-                            for (int k = 0; k < D; ++k) dot += gi[k] * gj[k];
-                            v += mu * dot;
-                        }
-                        acc[j] += W[q] * v;
-                    }
-                }
-            }
-        } else {  // NS
-            const int c1 = i1 / ns, s1 = i1 - c1 * ns;
-            const double* conv = grad + NQ * ns * D;
-            int s2[QE];
-            bool on[QE];  // the entry couples equal components
-#pragma unroll
-            for (int j = 0; j < QE; ++j) {
-                const int c2 = (j0 + j) / ns;
-                s2[j] = j0 + j - c2 * ns;
-                on[j] = j < jn && c2 == c1;
-            }
-            for (int q = 0; q < NQ; ++q) {
-                const double wi = W[q] * phis[q * ns + s1];
-#pragma unroll
-                for (int j = 0; j < QE; ++j)
-                    if (on[j]) acc[j] += wi * conv[q * ns + s2[j]];
-            }
-        }
-        double* o = A.out + cell * nI + i1 * n + j0;
-#pragma unroll
-        for (int j = 0; j < QE; ++j)
-            if (j < jn) o[j] = acc[j];
-    }
+    if constexpr (KIND == K_ELASTICITY) quad_entries_elasticity<D>(A, slots, slot, c0);
+    else if (n >= 8) quad_entries<D, KIND, 4, 4>(A, phis, slots, slot, c0);
+    else quad_entries<D, KIND, 1, 1>(A, phis, slots, slot, c0);
 }
 
 template <int D>
