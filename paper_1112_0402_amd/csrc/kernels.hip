@@ -1932,9 +1932,13 @@ __global__ __launch_bounds__(256) void quadrature_kernel(QuadArgs A) {
         }
     }
     __syncthreads();
+    // entry blocks, shapes measured on P2-P4 meshes: 2 x 4 for the gradient forms (their
+    // per-cell gradient tables leave few cells per block, so smaller blocks keep more lanes
+    // busy), 4 x 4 for mass and convection, one entry per thread below 8 dofs
     if constexpr (KIND == K_ELASTICITY) quad_entries_elasticity<D>(A, slots, slot, c0);
-    else if (n >= 8) quad_entries<D, KIND, 4, 4>(A, phis, slots, slot, c0);
-    else quad_entries<D, KIND, 1, 1>(A, phis, slots, slot, c0);
+    else if (n < 8) quad_entries<D, KIND, 1, 1>(A, phis, slots, slot, c0);
+    else if constexpr (KIND == K_LAPLACE || KIND == K_WLAPLACE) quad_entries<D, KIND, 2, 4>(A, phis, slots, slot, c0);
+    else quad_entries<D, KIND, 4, 4>(A, phis, slots, slot, c0);
 }
 
 template <int D>
