@@ -11,9 +11,15 @@
 //                      per-cell matrix-vector product into a matrix-matrix product, Sec. 3.5)
 //  contract_bf16       the same with G and A^0 split into BF16 pieces, concatenated along
 //                      K, on v_mfma_f32_16x16x32_bf16 with FP32 accumulation
-//  quadrature_kernel   plain quadrature (Sec. 4.3 / Sec. 6): per cell, physical basis
-//                      gradients at the points of a collapsed Gauss-Jacobi rule, then every
-//                      entry summed over the points
+//  contract_*_persistent  one 1024-thread workgroup per CU walking cell tiles: each compute
+//                      wave keeps its share of the A^0 tiles in registers, dedicated I/O
+//                      waves write the staged rows of one tile during the next tile's MFMA
+//                      steps (also the operator action y_K = A^K x_K, and mixed batches)
+//  curved_geometry_kernel  cells with P2 geometry: |det J| g g^T at every quadrature point
+//                      (Sec. 3.4: the integral becomes a sum over points, still a contraction)
+//  quadrature_kernel   the quadrature comparison (Sec. 4.3 / Sec. 6): per cell, physical
+//                      basis gradients at the points of a collapsed Gauss-Jacobi rule, then
+//                      every entry summed over the points, register-blocked over entries
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
