@@ -5,9 +5,10 @@ Default workload (--workload elasticity): 3D linear elasticity int sigma(u):eps(
 lambda = mu = 1, vector P2 tetrahedra (30 dofs), 6 * 50^3 = 750,000 cells of a jittered unit
 cube (seed 2), FP64.  A step is one pass of the hot path over the mesh, inputs resident in
 HBM: geometry kernel (coords -> det J, J^{-1}, one lane per cell) + contraction kernel
-(G_K tile in LDS, A^0 tiles on FP64 MFMA, 900 x 81 per cell).  The plain GPU quadrature
-kernel is timed beside it on the same mesh, and the FP64 oracle is timed on the host
-cores on a bounded sample of the same mesh.
+(G_K tile in LDS, A^0 tiles on FP64 MFMA, 900 x 81 per cell).  The GPU quadrature kernel
+(the comparison; register-blocked over entries) is timed beside it on the same mesh with
+its own roofline and error, and the FP64 oracle is timed on the host cores on a bounded
+sample of the same mesh.
 
 Other workloads (same JSON line layout):
   poisson2d   2D Poisson, P1 triangles, 8192 cells (launch-latency bound), FP64
@@ -23,7 +24,8 @@ Forms that do not use the persistent kernel compute the affine map inside the co
 captured once in a graph and replayed; per-kernel durations come from eager steps with HIP
 events on the launch stream.
 
-Prints one JSON line.  Options: --gpus (1 only), --steps, --warmup.
+Prints one JSON line.  Options: --gpus (1 only), --steps, --warmup; --write-ceiling and
+--copy-calibration time plain fills and copies for the ceilings and counter calibration.
 """
 from __future__ import annotations
 
