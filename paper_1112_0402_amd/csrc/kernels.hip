@@ -1662,7 +1662,13 @@ int quad_cells_per_block(int dim, int kind, int ns, int npts) {
     const size_t shared = static_cast<size_t>(npts) * ns * sizeof(double);
     const size_t slot = static_cast<size_t>(quad_slot_doubles(dim, kind, ns, npts)) * sizeof(double);
     int qc = static_cast<int>((budget - std::min(budget / 2, shared)) / slot);
-    if (qc > 8) qc = 8;
+    // elasticity: enough cells that the 256 threads all get a 2 x 2 block of function pairs
+    int cap = 8;
+    if (kind == K_ELASTICITY) {
+        const int pairs = ((ns + 1) / 2) * ((ns + 1) / 2);
+        cap = std::max(8, (256 + pairs - 1) / pairs);
+    }
+    if (qc > cap) qc = cap;
     if (qc < 1) qc = 1;
     return qc;
 }
