@@ -112,6 +112,14 @@ def cpu_baseline(wl, out_fn, seconds, np, quad_head=None):
     t = time.perf_counter()
     ref = oracle.tabulate(wl.kind, wl.dim, wl.degree, sub, coeffs(sample))
     dt = time.perf_counter() - t
+    runs = 1
+    if dt < 2.0:  # a short sample (the whole small mesh): median of 3 runs
+        times = [dt]
+        for _ in range(2):
+            t = time.perf_counter()
+            oracle.tabulate(wl.kind, wl.dim, wl.degree, sub, coeffs(sample))
+            times.append(time.perf_counter() - t)
+        dt, runs = float(np.median(times)), 3
     got = out_fn(sample).reshape(sample, -1).astype(np.float64)
     r = ref.reshape(sample, -1)
     err = np.linalg.norm(got - r, axis=1) / np.linalg.norm(r, axis=1)
@@ -121,7 +129,8 @@ def cpu_baseline(wl, out_fn, seconds, np, quad_head=None):
         "cores": threads,
         "kind": "oracle",
         "sample": f"first {sample} cells of the same {wl.cells}-cell mesh, FP64 quadrature on the physical "
-                  f"cell, OpenMP over cells ({threads} threads), {dt:.1f} s wall",
+                  f"cell, OpenMP over cells ({threads} threads), {dt:.3g} s wall"
+                  + (" (median of 3 runs)" if runs == 3 else ""),
     }
     errs = {"max": float(err.max()), "median": float(np.median(err)), "cells": sample}
     if quad_head is not None:
