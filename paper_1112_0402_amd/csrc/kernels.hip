@@ -1662,11 +1662,15 @@ int quad_cells_per_block(int dim, int kind, int ns, int npts) {
     const size_t shared = static_cast<size_t>(npts) * ns * sizeof(double);
     const size_t slot = static_cast<size_t>(quad_slot_doubles(dim, kind, ns, npts)) * sizeof(double);
     int qc = static_cast<int>((budget - std::min(budget / 2, shared)) / slot);
-    // elasticity: enough cells that the 256 threads all get a 2 x 2 block of function pairs
+    // elasticity: enough cells that the 256 threads all get a 2 x 2 block of function pairs;
+    // below 8 dofs (one entry per thread): enough cells for one entry per thread
     int cap = 8;
+    const int n = kind == K_ELASTICITY || kind == K_NS ? dim * ns : ns;
     if (kind == K_ELASTICITY) {
         const int pairs = ((ns + 1) / 2) * ((ns + 1) / 2);
         cap = std::max(8, (256 + pairs - 1) / pairs);
+    } else if (n < 8) {
+        cap = std::max(8, (256 + n * n - 1) / (n * n));
     }
     if (qc > cap) qc = cap;
     if (qc < 1) qc = 1;
