@@ -74,7 +74,7 @@ def load_traffic(workload: str, cells: int):
 
 
 def quadrature_model_flops(kind: str, n_I: int, n_pts: int, dim: int) -> int:
-    """The paper's operation count for quadrature (Sec. 4.4) per cell: for each element-tensor
+    """The paper's operation count for quadrature (Sec. 4.3) per cell: for each element-tensor
     entry and quadrature point, one product per coefficient function and per derivative
     direction, plus one for the weight."""
     n_f, n_D = {"mass": (0, 0), "laplace": (0, 2), "wlaplace": (1, 2), "elasticity": (0, 2), "ns": (1, 1)}[kind]

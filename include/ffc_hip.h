@@ -207,7 +207,7 @@ int ffc_tabulate_tensor(const ffc_form* form, int64_t cells, const double* coord
 /* The contraction alone (kernel 2 above) from a precomputed affine map: affine_map is
  * the device SoA [1 + d*d][cells] that ffc_compute_geometry writes (row 0 = det J, row
  * 1 + a*d + b = g_ab).  Lets several forms on one mesh share one geometry pass (the
- * paper's eval reads the same AffineMap for every form, Sec. 5.4).  Tensor kernel only
+ * paper's eval reads the same AffineMap for every form, Sec. 5.5).  Tensor kernel only
  * (FFC_E_INVALID for a quadrature form).  Same asynchrony and layouts as
  * ffc_tabulate_tensor. */
 int ffc_tabulate_tensor_affine(const ffc_form* form, int64_t cells, const double* affine_map, const double* coeffs,

@@ -30,20 +30,27 @@ def _run(cmd):
 
 
 def build(verbose: bool = True) -> str:
+    """Compile every source (in parallel: the objects are independent), then link."""
     objdir = os.path.join(ROOT, "_build")
     os.makedirs(objdir, exist_ok=True)
-    objs = []
+    jobs = []
     # host-only compile step
     o = os.path.join(objdir, "reference_tensor.o")
-    _run(["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-c", os.path.join(CSRC, "reference_tensor.cpp"), "-o", o])
-    objs.append(o)
+    jobs.append((["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-c", os.path.join(CSRC, "reference_tensor.cpp"),
+                  "-o", o], o))
     for src in ("kernels.hip", "mlp.hip", "assembly.hip", "capi.cpp"):
         o = os.path.join(objdir, src.split(".")[0] + ".o")
         extra = ["-x", "hip"] if src.endswith(".cpp") else []
-        _run([HIPCC, *HIP_FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", o])
-        objs.append(o)
+        jobs.append(([HIPCC, *HIP_FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", o], o))
+    procs = []
+    for cmd, _ in jobs:
+        print("+", " ".join(cmd), flush=True)
+        procs.append(subprocess.Popen(cmd))
+    failed = [cmd for (cmd, _), p in zip(jobs, procs) if p.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, failed[0])
     tmp = LIB + ".tmp"
-    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs])
+    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *[o for _, o in jobs]])
     os.replace(tmp, LIB)
     return LIB
 

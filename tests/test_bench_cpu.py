@@ -28,7 +28,7 @@ def test_traffic_summary_reader():
 
 
 def test_quadrature_operation_count():
-    # Sec. 4.4's count for the three benchmarked forms: elasticity P2 3D (30 dofs, 8 points),
+    # Sec. 4.3's count for the three benchmarked forms: elasticity P2 3D (30 dofs, 8 points),
     # weighted Laplace P3 3D (20 dofs, 27 points), P1 Laplacian on triangles (1 point)
     assert bench.quadrature_model_flops("elasticity", 900, 8, 3) == 50_400
     assert bench.quadrature_model_flops("wlaplace", 400, 27, 3) == 86_400

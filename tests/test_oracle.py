@@ -354,3 +354,24 @@ def test_orientation_reversal_unchanged():
     B = oracle.tabulate("laplace", 3, 1, _soa(rev))
     perm = [0, 2, 1, 3]
     assert np.allclose(B, A[:, perm][:, :, perm], atol=1e-13 * np.abs(A).max())
+
+
+# --------------------------------------------------------- badly shaped cells ---
+
+@pytest.mark.parametrize("shape", ["needle", "sliver"])
+@pytest.mark.parametrize("kind,dim,q", [("mass", 3, 1), ("laplace", 3, 2), ("laplace", 2, 2)])
+def test_oracle_accuracy_on_badly_shaped_cells(kind, dim, q, shape):
+    """The oracle against exact rationals of the same binary coordinates on needles and
+    slivers: within 1e-12 up to Jacobian condition number 100, and within 1e-11 at 1000
+    (its cofactor inverse loses digits on 3D needles, ~4e-12 measured).  This is why the GPU
+    tests on such cells compare with exact arithmetic rather than with the oracle."""
+    from paper_1112_0402_amd import meshgen
+
+    for aspect, tol in ((10.0, 1e-12), (100.0, 1e-12), (1000.0, 1e-11)):
+        c = meshgen.badly_shaped(dim, 12, aspect, shape, seed=5)
+        O = oracle.tabulate(kind, dim, q, c)
+        E = np.array([[[float(x) for x in r] for r in exact.element_tensor(
+            kind, [[Fraction(float(c[v * dim + k, i])) for k in range(dim)] for v in range(dim + 1)], q)]
+            for i in range(c.shape[1])])
+        err = np.linalg.norm((O - E).reshape(len(E), -1), axis=1) / np.linalg.norm(E.reshape(len(E), -1), axis=1)
+        assert err.max() <= tol, (aspect, err.max())
