@@ -54,10 +54,11 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(workload: str, cells: int):
-    """HBM bytes per launch of the contraction kernel from the committed rocprofv3 PMC
-    summary of this workload, if it was taken on the current kernel source; else None."""
-    path = os.path.join(PROFILES, f"contract_{workload}_traffic.txt")
+def load_traffic(workload: str, cells: int, prefix: str = "contract"):
+    """HBM bytes per launch of the dominant kernel (or, for a batch, of the whole launch
+    sequence) from the committed rocprofv3 PMC summary of this workload, if it was taken on
+    the current kernel source; else None."""
+    path = os.path.join(PROFILES, f"{prefix}_{workload}_traffic.txt")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -92,67 +93,62 @@ def timed(fn, steps, stream, torch):
     return float(sum(a.elapsed_time(b) for a, b in ev) / steps)
 
 
-def cpu_baseline(wl, out_fn, seconds, np, quad_head=None):
-    """The oracle on the host cores over a bounded prefix of the same mesh; quad_head: the
-    quadrature kernel's element tensors of the first cells, checked against the same oracle
-    values."""
+def oracle_pass(wl, outputs, np, cells=None, repeats=1, chunk=32768):
+    """The oracle on the host cores over the first `cells` cells (default: the whole mesh),
+    chunk by chunk; `outputs` maps a name to a function (c0, c1) -> host array of that output's
+    element tensors.  Returns the baseline (oracle wall time of the oracle calls only; median of
+    `repeats` passes) and, per output, the per-cell relative Frobenius error against it."""
     import oracle
 
     threads = oracle.max_threads()
-    calib = min(4096, wl.cells)
-
-    def coeffs(n):
-        return None if wl.coeffs is None else np.ascontiguousarray(wl.coeffs[:, :n])
-
-    t = time.perf_counter()
-    oracle.tabulate(wl.kind, wl.dim, wl.degree, wl.coords[:, :calib], coeffs(calib))
-    dt = time.perf_counter() - t
-    sample = int(min(wl.cells, max(calib, calib * seconds / max(dt, 1e-6))))
-    sub = np.ascontiguousarray(wl.coords[:, :sample])
-    t = time.perf_counter()
-    ref = oracle.tabulate(wl.kind, wl.dim, wl.degree, sub, coeffs(sample))
-    dt = time.perf_counter() - t
-    runs = 1
-    if dt < 2.0:  # a short sample (the whole small mesh): median of 3 runs
-        times = [dt]
-        for _ in range(2):
+    n = wl.cells if cells is None else min(cells, wl.cells)
+    errs = {k: np.empty(n) for k in outputs}
+    times = []
+    for rep in range(repeats):
+        dt = 0.0
+        for c0 in range(0, n, chunk):
+            c1 = min(n, c0 + chunk)
+            co = None if wl.coeffs is None else np.ascontiguousarray(wl.coeffs[:, c0:c1])
+            sub = np.ascontiguousarray(wl.coords[:, c0:c1])
             t = time.perf_counter()
-            oracle.tabulate(wl.kind, wl.dim, wl.degree, sub, coeffs(sample))
-            times.append(time.perf_counter() - t)
-        dt, runs = float(np.median(times)), 3
-    got = out_fn(sample).reshape(sample, -1).astype(np.float64)
-    r = ref.reshape(sample, -1)
-    err = np.linalg.norm(got - r, axis=1) / np.linalg.norm(r, axis=1)
+            ref = oracle.tabulate(wl.kind, wl.dim, wl.degree, sub, co, lam=wl.lam, mu=wl.mu)
+            dt += time.perf_counter() - t
+            if rep == 0:
+                r = ref.reshape(c1 - c0, -1)
+                den = np.linalg.norm(r, axis=1)
+                for k, fn in outputs.items():
+                    got = fn(c0, c1).reshape(c1 - c0, -1).astype(np.float64)
+                    errs[k][c0:c1] = np.linalg.norm(got - r, axis=1) / den
+        times.append(dt)
+    dt = float(np.median(times))
     base = {
-        "value": sample / dt,
+        "value": n / dt,
         "unit": "element tensors/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": f"first {sample} cells of the same {wl.cells}-cell mesh, FP64 quadrature on the physical "
-                  f"cell, OpenMP over cells ({threads} threads), {dt:.3g} s wall"
-                  + (" (median of 3 runs)" if runs == 3 else ""),
+        "sample": (f"every cell of the {wl.cells}-cell mesh" if n == wl.cells else
+                   f"first {n} cells of the {wl.cells}-cell mesh") +
+                  f", FP64 quadrature on the physical cell, OpenMP over cells ({threads} threads), {dt:.3g} s wall"
+                  + (f" (median of {repeats} passes)" if repeats > 1 else ""),
     }
-    errs = {"max": float(err.max()), "median": float(np.median(err)), "cells": sample}
-    if quad_head is not None:
-        k = min(len(quad_head), sample)
-        q = quad_head[:k].reshape(k, -1)
-        qe = np.linalg.norm(q - r[:k], axis=1) / np.linalg.norm(r[:k], axis=1)
-        errs["quadrature_kernel"] = {"max": float(qe.max()), "median": float(np.median(qe)), "cells": k}
-    return base, errs
+    return base, {k: {"max": float(e.max()), "median": float(np.median(e)), "cells": n} for k, e in errs.items()}
 
 
-def bench_single(args, torch, np):
+def bench_single(args, torch, np, workload=None, precision=None, oracle_repeats=1):
+    """One single-form workload: the hot path timed as a captured graph, its dominant
+    kernel's roofline, the quadrature kernel beside it, and the oracle over every cell."""
     from paper_1112_0402_amd import meshgen
     from paper_1112_0402_amd.forms import Form, compute_geometry
 
-    if args.workload == "elasticity":
+    workload = workload or args.workload
+    if workload == "elasticity":
         wl, precision, name = meshgen.config2(), "fp64", "elasticity3d_p2_750k"
         desc = "int sigma(u):eps(v), lambda=mu=1, vector P2 tetrahedra, 6*50^3 cells of the unit cube"
-    elif args.workload == "poisson2d":
+    elif workload == "poisson2d":
         wl, precision, name = meshgen.config1(), "fp64", "poisson2d_p1_8192"
         desc = "int grad u . grad v, P1 triangles, 64x64 squares of the unit square"
     else:
-        wl, precision = meshgen.config3(), args.precision
+        wl, precision = meshgen.config3(), precision or args.precision
         name = "wlaplace3d_p3_1.5M"
         desc = "int w grad u . grad v, w in P1 ~ U(0.5,2), P3 tetrahedra, 6*63^3 cells of the unit cube"
     cells, d = wl.cells, wl.dim
@@ -252,7 +248,7 @@ def bench_single(args, torch, np):
             "n_entries": n_I,
             "n_alpha": n_alpha,
             "precision": precision,
-            "mesh_seed": {"elasticity": 2, "poisson2d": 1, "wlaplace": 3}[args.workload],
+            "mesh_seed": {"elasticity": 2, "poisson2d": 1, "wlaplace": 3}[workload],
             "tile_cells": info["tile_cells"],
             "waves": info["persistent_waves"] or info["waves"],
             "persistent": bool(info["persistent_waves"]),
@@ -269,7 +265,7 @@ def bench_single(args, torch, np):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": con_gbs / HBM_PEAK_GBS,
-            "traffic": load_traffic(name, cells),
+            "traffic": load_traffic(name if not bf16 else f"{name}_{precision}", cells),
             "algorithmic_bytes_per_launch": con_bytes,
             "ms_per_launch": con_ms,
         },
@@ -319,38 +315,40 @@ def bench_single(args, torch, np):
             "model_tflops": cells * q_flops / (q_ms * 1e-3) / 1e12,
             "fp64_frac": cells * q_flops / (q_ms * 1e-3) / 1e12 / FP64_MFMA_PEAK_TF,
         }
-        if not args.no_cpu_baseline:
-            quad_head = qout[: min(cells, 4096)].cpu().numpy()
-        del qout, qform
 
     if not args.no_cpu_baseline:
-        base, err = cpu_baseline(wl, lambda n: out[:n].cpu().numpy(), args.cpu_seconds, np,
-                                 None if args.no_quadrature else quad_head)
+        outputs = {"tensor": lambda c0, c1: out[c0:c1].cpu().numpy()}
+        if not args.no_quadrature:
+            outputs["quadrature_kernel"] = lambda c0, c1: qout[c0:c1].cpu().numpy()
+        base, errs = oracle_pass(wl, outputs, np, repeats=oracle_repeats)
         result["cpu_baseline"] = base
+        err = errs["tensor"]
         err["tol"] = 1e-12 if not bf16 else (1e-6 if precision == "bf16x6" else None)
-        if "quadrature_kernel" in err:
-            err["quadrature_kernel"]["tol"] = 1e-12
+        if "quadrature_kernel" in errs:
+            err["quadrature_kernel"] = dict(errs["quadrature_kernel"], tol=1e-12)
         result["rel_err_vs_oracle"] = err
     return result
 
 
-def bench_batch(args, torch, np):
-    from paper_1112_0402_amd import meshgen
-    from paper_1112_0402_amd.forms import Batch, Form
+def bench_batch(args, torch, np, precision=None, launch=None, oracle_cells_per_mesh=8192, per_mesh=True):
+    """The mixed batch (64 meshes, 16 form variants): its fixed launch sequence captured in a
+    graph and replayed; per-mesh launch choice from the library defaults, the exhaustive
+    autotuner, or the selector network the library's FFC_KERNEL_AUTO forms use; the oracle on
+    the first cells of every mesh."""
+    from paper_1112_0402_amd import meshgen, tune
+    from paper_1112_0402_amd.forms import Batch
 
-    from paper_1112_0402_amd import tune
-
-    precision = args.precision
+    precision = precision or args.precision
+    launch = launch or args.launch
     wls = meshgen.config4()
     sel = None
-    if args.launch == "selector":
+    if launch == "selector":
         if precision != "fp64":
             raise SystemExit("the selector is trained on the FP64 sweep; use --launch autotune for split modes")
         from paper_1112_0402_amd import selector as selmod
 
-        sel = selmod.Selector(seed=0)
-        sel.fit(tune.load_sweep(os.path.join(ROOT, "paper_1112_0402_amd", "data", "sweep_mi355x_fp64.jsonl")))
-    fl, picks = tune.batch_forms(wls, precision, args.launch, db=tune.TuneDB(None), selector=sel)
+        sel = selmod.Selector.load(selmod.DEFAULT_FILE)
+    fl, picks = tune.batch_forms(wls, precision, launch, db=tune.TuneDB(None), selector=sel)
     forms = {id(f): f for f in fl}
     X = [torch.from_numpy(w.coords).cuda() for w in wls]
     C = [None if w.coeffs is None else torch.from_numpy(w.coeffs).cuda() for w in wls]
@@ -373,15 +371,9 @@ def bench_batch(args, torch, np):
         ms = timed(g.replay, args.steps, s, torch)
     byt = sum(w.cells * ((w.dim + 1) * w.dim * 8 + (0 if w.coeffs is None else w.coeffs.shape[0] * 8)
                          + f.n_I * f.info["out_bytes"]) for w, f in zip(wls, fl))
-    # the same meshes as one geometry + contraction launch pair per mesh, for comparison
-    stream = torch.cuda.current_stream()
-    for f, x, c, o in zip(fl, X, C, outs):
-        f.tabulate(x, c, out=o)
-    torch.cuda.synchronize()
-    ms_single = timed(lambda: [f.tabulate(x, c, out=o) for f, x, c, o in zip(fl, X, C, outs)], args.steps,
-                      stream, torch)
     gbs = byt / (ms * 1e-3) / 1e9
-    return {
+    name = f"batch64_mixed_{precision}" + ("" if launch == "default" else f"_{launch}")
+    result = {
         "metric": METRIC,
         "value": cells / (ms * 1e-3),
         "unit": "element tensors/s",
@@ -396,14 +388,45 @@ def bench_batch(args, torch, np):
         "data": "synthetic",
         "config": {"workload": "batch64_mixed", "meshes": len(wls), "cells": cells, "precision": precision,
                    "variants": len({(w.kind, w.dim, w.degree) for w in wls}), "forms": len(forms),
-                   "launch_choice": args.launch, "candidates_picked": {str(k): picks.count(k) for k in sorted(set(picks))},
+                   "launch_choice": launch, "candidates_picked": {str(k): picks.count(k) for k in sorted(set(picks))},
                    "work_units": b.work_units, "launches": b.launches},
-        "roofline": {"kernel": "batch_persistent_kernel + batch_tiles_kernel", "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": gbs / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes_per_launch": byt,
+        "roofline": {"kernel": "batch launches (persistent + tile kernels, one graph)", "bound": "hbm",
+                     "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                     "traffic": load_traffic(name, cells, prefix="batch"), "algorithmic_bytes_per_launch": byt,
                      "ms_per_launch": ms},
-        "per_mesh_launches": {"ms": ms_single, "value": cells / (ms_single * 1e-3),
-                              "speedup_batch_over_per_mesh": ms_single / ms},
     }
+    if per_mesh:
+        # the same meshes as one tabulation call per mesh, for comparison
+        stream = torch.cuda.current_stream()
+        for f, x, c, o in zip(fl, X, C, outs):
+            f.tabulate(x, c, out=o)
+        torch.cuda.synchronize()
+        ms_single = timed(lambda: [f.tabulate(x, c, out=o) for f, x, c, o in zip(fl, X, C, outs)], args.steps,
+                          stream, torch)
+        result["per_mesh_launches"] = {"ms": ms_single, "value": cells / (ms_single * 1e-3),
+                                       "speedup_batch_over_per_mesh": ms_single / ms}
+        with torch.cuda.stream(s):
+            b.run()  # the outputs the oracle is compared with come from the batch
+        torch.cuda.synchronize()
+    if not args.no_cpu_baseline:
+        n_or, dt, worst, meds = 0, 0.0, 0.0, []
+        for w, o in zip(wls, outs):
+            k = min(w.cells, oracle_cells_per_mesh)
+            base, errs = oracle_pass(w, {"batch": lambda c0, c1, o=o: o[c0:c1].cpu().numpy()}, np, cells=k)
+            n_or += k
+            dt += k / base["value"]
+            worst = max(worst, errs["batch"]["max"])
+            meds.append(errs["batch"]["median"])
+        import oracle
+
+        result["cpu_baseline"] = {"value": n_or / dt, "unit": "element tensors/s", "cores": oracle.max_threads(),
+                                  "kind": "oracle", "sample": f"first {oracle_cells_per_mesh} cells of each of the "
+                                  f"{len(wls)} meshes ({n_or} cells, the same form mix), FP64 quadrature on the "
+                                  f"physical cell, {dt:.3g} s wall"}
+        result["rel_err_vs_oracle"] = {"max": worst, "median_of_mesh_medians": float(np.median(meds)),
+                                       "cells": n_or,
+                                       "tol": 1e-12 if precision == "fp64" else (1e-6 if precision == "bf16x6" else None)}
+    return result
 
 
 def bench_assembly(args, torch, np):
@@ -628,6 +651,58 @@ def bench_curved(args, torch, np):
     return result
 
 
+def compact(r):
+    """The figures of a nested workload line that a reader compares across configurations."""
+    out = {k: r[k] for k in ("value", "unit", "ms_per_step", "dtype") if k in r}
+    rf = r.get("roofline", {})
+    out["roofline"] = {k: rf.get(k) for k in ("kernel", "bound", "achieved", "peak", "unit", "frac", "traffic",
+                                              "ms_per_launch")}
+    for k in ("quadrature_kernel", "per_mesh_launches", "cpu_baseline", "rel_err_vs_oracle"):
+        if k in r:
+            out[k] = r[k]
+    if "quadrature_kernel" in out:
+        q = out["quadrature_kernel"]
+        out["quadrature_kernel"] = {k: q[k] for k in ("value", "ms_per_launch", "speedup_tensor_over_quadrature",
+                                                      "fp64_frac", "hbm_frac")}
+    c = r.get("config", {})
+    out["config"] = {k: c[k] for k in ("workload", "cells", "precision", "launch_choice", "candidates_picked",
+                                       "launches", "persistent", "geometry", "tile_cells") if k in c}
+    return out
+
+
+def other_configs(args, torch, np):
+    """The remaining configurations, each on one GPU, nested in the default line:
+    2D Poisson P1 (8192 cells, launch latency), the 1.5M-cell weighted Laplacian P3 in the split
+    modes (x6 meets the 1e-6 target; x3 does not and is labelled so), and the 64-mesh mixed
+    batch in FP64 with the library default launches, the exhaustive autotuner's and the
+    selector's (whose end-to-end rate is the selector's figure of merit), and in x6."""
+    out = {}
+    out["poisson2d_p1_8192"] = compact(bench_single(args, torch, np, workload="poisson2d", oracle_repeats=3))
+    torch.cuda.empty_cache()
+    w = {}
+    for prec in ("bf16x6", "bf16x3"):
+        r = compact(bench_single(args, torch, np, workload="wlaplace", precision=prec))
+        r["meets_1e-6"] = prec == "bf16x6" and r.get("rel_err_vs_oracle", {}).get("max", 1.0) <= 1e-6
+        w[prec] = r
+        torch.cuda.empty_cache()
+    w["note"] = ("x6 (6 BF16 products) is the split mode that meets the 1e-6 target; x3 (3 products) is faster "
+                 "and misses it (about 1e-5)")
+    out["wlaplace3d_p3_1.5M"] = w
+    bt = {}
+    for prec, launch in (("fp64", "default"), ("fp64", "autotune"), ("fp64", "selector"), ("bf16x6", "default")):
+        r = compact(bench_batch(args, torch, np, precision=prec, launch=launch, per_mesh=launch == "default"))
+        bt[f"{prec}_{launch}"] = r
+        torch.cuda.empty_cache()
+    bt["selector_end_to_end"] = {
+        "value": bt["fp64_selector"]["value"], "unit": "element tensors/s",
+        "vs_default": bt["fp64_selector"]["value"] / bt["fp64_default"]["value"],
+        "vs_autotune": bt["fp64_selector"]["value"] / bt["fp64_autotune"]["value"],
+        "note": "mixed 64-mesh batch with each mesh's launch picked by the selector network that "
+                "FFC_KERNEL_AUTO forms load; mesh sizes not in the sweep it was trained on"}
+    out["batch64_mixed"] = bt
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -656,6 +731,10 @@ def main() -> int:
                     help="measure a plain 5.4 GB fill and copy (torch kernels): the practical streaming ceilings")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (HBM counter calibration)")
+    ap.add_argument("--no-per-mesh", action="store_true",
+                    help="batch: skip the per-mesh comparison launches (counter runs of the batch alone)")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="default workload: skip the other configurations nested under 'configs'")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -697,7 +776,7 @@ def main() -> int:
                           "bytes_written_fill": n * 8}))
         return 0
     if args.workload == "batch":
-        result = bench_batch(args, torch, np)
+        result = bench_batch(args, torch, np, per_mesh=not args.no_per_mesh)
     elif args.workload == "assembly":
         result = bench_assembly(args, torch, np)
     elif args.workload == "action":
@@ -706,6 +785,8 @@ def main() -> int:
         result = bench_curved(args, torch, np)
     else:
         result = bench_single(args, torch, np)
+        if args.workload == "elasticity" and not args.headline_only:
+            result["configs"] = other_configs(args, torch, np)
     print(json.dumps(result), flush=True)
     return 0
 

@@ -110,8 +110,22 @@ typedef enum {
  * hi*lo2 + lo*lo + lo2*hi. */
 typedef enum { FFC_FP64 = 0, FFC_SPLIT_BF16_3 = 1, FFC_SPLIT_BF16_6 = 2 } ffc_precision;
 
-/* Which kernel evaluates A^K.  QUADRATURE is FP64 only. */
-typedef enum { FFC_KERNEL_TENSOR = 1, FFC_KERNEL_QUADRATURE = 2 } ffc_kernel;
+/* Which kernel evaluates A^K.  QUADRATURE is FP64 only.
+ * AUTO: the automatic choice between tensor representation and quadrature (and among the
+ * tensor kernel's launch shapes) that Sec. 4.4 leaves open, made by the learned selector
+ * network (ffc_mlp_* below; it predicts each candidate launch's run time relative to the
+ * library default from the form's rank, degree, |i|, |alpha|, dimension and the cell
+ * count).  ffc_form_create reads the trained network from the file named by the
+ * environment variable FFC_SELECTOR ("none": no file), else from
+ * data/selector_mi355x_fp64.txt in the directory of this library; evaluates it on the host
+ * for every cell count 2^0 .. 2^40; and creates one internal form per launch it picks, so
+ * ffc_tabulate_tensor only dispatches (to the pick for round(log2 cells)) and still never
+ * allocates.  The network decides for FP64 Lagrange forms (FFC_MASS .. FFC_NS_CONVECTION),
+ * the forms it was trained on; elsewhere, and when no file is found, every cell count takes
+ * the library default tensor launch.  A file named by FFC_SELECTOR that cannot be read is
+ * an error (FFC_E_INVALID).  Entry points other than ffc_tabulate_tensor, and
+ * ffc_form_get_info, use the default tensor launch. */
+typedef enum { FFC_KERNEL_AUTO = 0, FFC_KERNEL_TENSOR = 1, FFC_KERNEL_QUADRATURE = 2 } ffc_kernel;
 typedef enum { FFC_GEOMETRY_PASS = 1, FFC_GEOMETRY_FUSED = 2 } ffc_geometry;
 
 typedef struct {
@@ -175,6 +189,9 @@ typedef struct {
     int64_t symmetric;        /* 1: the FP64 tiles hold the entries i1 <= i2 only, each result
                                  written at (i1, i2) and (i2, i1) -- the element matrices are
                                  exactly symmetric; 0: every entry computed */
+    int64_t auto_launches;    /* FFC_KERNEL_AUTO forms: distinct launches the selector uses over
+                                 all cell counts (the other fields describe the default tensor
+                                 launch); 0 for other forms */
 } ffc_form_info;
 
 /* Compile step only, host only, touches no device: the reference tensor A^0 of the form
@@ -197,6 +214,12 @@ int ffc_compile_reference_tensor(const ffc_form_desc* desc, int64_t* n_I, int64_
 int ffc_form_create(const ffc_form_desc* desc, ffc_form** form);
 int ffc_form_get_info(const ffc_form* form, ffc_form_info* info);
 void ffc_form_destroy(ffc_form* form);
+
+/* FFC_KERNEL_AUTO forms: the candidate launch that ffc_tabulate_tensor uses for `cells`
+ * cells -- its index in the selector file's candidate list (0 = the library default tensor
+ * launch) -- and whether a selector file was loaded (1) or the default is used for lack of
+ * one (0; from_selector may be NULL).  FFC_E_INVALID for other forms. */
+int ffc_form_select(const ffc_form* form, int64_t cells, int32_t* candidate, int32_t* from_selector);
 
 /* Enqueue the evaluation of `cells` element tensors on the form's stream and return
  * (asynchronous).  coords: device SoA as above; coeffs: device SoA or NULL; out: device

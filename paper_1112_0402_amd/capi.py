@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libffc_hip.so")
 
 KINDS = {"mass": 0, "laplace": 1, "wlaplace": 2, "elasticity": 3, "ns": 4, "piola": 5, "curved": 6, "nedelec": 7}
 PRECISIONS = {"fp64": 0, "bf16x3": 1, "bf16x6": 2}
-KERNELS = {"tensor": 1, "quadrature": 2}
+KERNELS = {"auto": 0, "tensor": 1, "quadrature": 2}
 GEOMETRY = {"default": 0, "pass": 1, "fused": 2}
 
 FFC_OK = 0
@@ -49,7 +49,7 @@ class FormInfo(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in (
         "n_dofs", "n_entries", "n_alpha", "nnz_a0", "n_coords", "n_coeffs", "out_bytes",
         "mfma_k_per_tile", "n_tiles", "quad_points", "persistent_waves", "persistent_kmax", "tile_cells",
-        "waves", "fused_geometry", "g_entries", "symmetric")]
+        "waves", "fused_geometry", "g_entries", "symmetric", "auto_launches")]
 
 
 class FFCError(RuntimeError):
@@ -77,6 +77,7 @@ def lib():
     L.ffc_compile_reference_tensor.argtypes = [ctypes.POINTER(FormDesc), ctypes.POINTER(i64), ctypes.POINTER(i64), vp]
     L.ffc_form_create.argtypes = [ctypes.POINTER(FormDesc), ctypes.POINTER(vp)]
     L.ffc_form_get_info.argtypes = [vp, ctypes.POINTER(FormInfo)]
+    L.ffc_form_select.argtypes = [vp, i64, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.ffc_form_destroy.argtypes = [vp]
     L.ffc_form_destroy.restype = None
     L.ffc_tabulate_tensor.argtypes = [vp, i64, vp, vp, vp]
@@ -108,7 +109,8 @@ def lib():
     L.ffc_adam_step.argtypes = [i64, vp, vp, vp, vp, fp, fp, fp, fp, fp, i32, vp]
     for name in ("ffc_mlp_forward", "ffc_mlp_backward", "ffc_mlp_mse", "ffc_adam_step"):
         getattr(L, name).restype = ctypes.c_int
-    for name in ("ffc_compile_reference_tensor", "ffc_form_create", "ffc_form_get_info", "ffc_tabulate_tensor",
+    for name in ("ffc_compile_reference_tensor", "ffc_form_create", "ffc_form_get_info", "ffc_form_select",
+                 "ffc_tabulate_tensor",
                  "ffc_tabulate_tensor_affine", "ffc_apply_tensor",
                  "ffc_compute_geometry", "ffc_batch_create", "ffc_batch_run", "ffc_batch_info"):
         getattr(L, name).restype = ctypes.c_int

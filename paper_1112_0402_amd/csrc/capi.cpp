@@ -2,7 +2,12 @@
 // and kernel dispatch.  Declarations and conventions: include/ffc_hip.h.
 #include <hip/hip_runtime.h>
 
+#include <dlfcn.h>
+
 #include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -81,7 +86,7 @@ int check_desc(const ffc_form_desc* d, ffc::FormSpec* spec) {
     if (!ffc::supported(*spec, &why)) return fail(FFC_E_UNSUPPORTED, why);
     if (d->precision < FFC_FP64 || d->precision > FFC_SPLIT_BF16_6)
         return fail(FFC_E_UNSUPPORTED, "unknown precision");
-    if (d->kernel != FFC_KERNEL_TENSOR && d->kernel != FFC_KERNEL_QUADRATURE)
+    if (d->kernel != FFC_KERNEL_AUTO && d->kernel != FFC_KERNEL_TENSOR && d->kernel != FFC_KERNEL_QUADRATURE)
         return fail(FFC_E_UNSUPPORTED, "unknown kernel");
     if (d->kernel == FFC_KERNEL_QUADRATURE && d->precision != FFC_FP64)
         return fail(FFC_E_UNSUPPORTED, "the quadrature kernel is FP64 only");
@@ -98,6 +103,116 @@ int check_desc(const ffc_form_desc* d, ffc::FormSpec* spec) {
     if (d->tile_window != 0 && d->tile_window != -1 && (d->tile_window < 16 || d->tile_window % 16 != 0))
         return fail(FFC_E_INVALID, "tile_window must be 0, -1 or a positive multiple of 16");
     return FFC_OK;
+}
+
+constexpr int kAutoBuckets = 41;  // cell counts 2^0 .. 2^40
+
+int auto_bucket(int64_t cells) {
+    const double l = cells > 0 ? std::log2(static_cast<double>(cells)) : 0.0;
+    return static_cast<int>(std::min<double>(kAutoBuckets - 1, std::max(0.0, std::floor(l + 0.5))));
+}
+
+// ------------------------------------------------------------------ selector file ----
+// The learned kernel choice (the automatic tensor-vs-quadrature decision of Sec. 4.4): a
+// multilayer perceptron trained on timings of every candidate launch predicts
+// log(t_candidate / t_default) from seven features of the form and the cell count; the
+// argmin is taken.  The text file holds: "ffc_selector 1", the sizes, the feature means and
+// deviations, the target offset, the flat FP32 parameters (W1 [n_in][h], b1, W2 [h][h], b2,
+// W3 [h][n_out], b3) and one line per candidate launch.
+struct SelectorNet {
+    int n_in = 0, h = 0, n_out = 0;
+    std::vector<double> mu, sd;
+    double tmu = 0.0;
+    std::vector<float> params;
+    struct Cand {
+        int kernel, tile_cells, waves, persistent, tile_window, geometry;
+    };
+    std::vector<Cand> cands;
+
+    bool load(const std::string& path, std::string* err) {
+        FILE* fp = std::fopen(path.c_str(), "r");
+        if (!fp) {
+            *err = "cannot open " + path;
+            return false;
+        }
+        auto word = [&](const char* want) {
+            char buf[64] = {0};
+            return std::fscanf(fp, "%63s", buf) == 1 && std::strcmp(buf, want) == 0;
+        };
+        int version = 0;
+        bool ok = word("ffc_selector") && std::fscanf(fp, "%d", &version) == 1 && version == 1 && word("n_in") &&
+                  std::fscanf(fp, "%d", &n_in) == 1 && word("n_hidden") && std::fscanf(fp, "%d", &h) == 1 &&
+                  word("n_out") && std::fscanf(fp, "%d", &n_out) == 1 && n_in == 7 && h > 0 && h <= 4096 &&
+                  n_out > 0 && n_out <= 64;
+        if (ok) {
+            mu.resize(n_in);
+            sd.resize(n_in);
+            ok = word("mu");
+            for (int i = 0; ok && i < n_in; ++i) ok = std::fscanf(fp, "%lf", &mu[i]) == 1;
+            ok = ok && word("sd");
+            for (int i = 0; ok && i < n_in; ++i) ok = std::fscanf(fp, "%lf", &sd[i]) == 1 && sd[i] > 0.0;
+            ok = ok && word("tmu") && std::fscanf(fp, "%lf", &tmu) == 1;
+        }
+        long long np = 0;
+        if (ok) ok = word("params") && std::fscanf(fp, "%lld", &np) == 1 &&
+                     np == static_cast<long long>(n_in) * h + h + static_cast<long long>(h) * h + h +
+                               static_cast<long long>(h) * n_out + n_out;
+        if (ok) {
+            params.resize(static_cast<size_t>(np));
+            for (long long i = 0; ok && i < np; ++i) ok = std::fscanf(fp, "%f", &params[i]) == 1;
+        }
+        int nc = 0;
+        ok = ok && word("candidates") && std::fscanf(fp, "%d", &nc) == 1 && nc == n_out;
+        for (int i = 0; ok && i < nc; ++i) {
+            Cand c{};
+            ok = std::fscanf(fp, "%d %d %d %d %d %d", &c.kernel, &c.tile_cells, &c.waves, &c.persistent,
+                             &c.tile_window, &c.geometry) == 6 &&
+                 (c.kernel == FFC_KERNEL_TENSOR || c.kernel == FFC_KERNEL_QUADRATURE);
+            cands.push_back(c);
+        }
+        std::fclose(fp);
+        if (!ok) *err = "malformed selector file " + path;
+        return ok;
+    }
+
+    // predicted log(t_c / t_default) of every candidate for one feature vector
+    std::vector<double> predict(const double* x_raw) const {
+        std::vector<double> x(n_in), h1(h), h2(h), y(n_out);
+        for (int i = 0; i < n_in; ++i) x[i] = (x_raw[i] - mu[i]) / sd[i];
+        const float* W1 = params.data();
+        const float* b1 = W1 + n_in * h;
+        const float* W2 = b1 + h;
+        const float* b2 = W2 + h * h;
+        const float* W3 = b2 + h;
+        const float* b3 = W3 + h * n_out;
+        for (int j = 0; j < h; ++j) {
+            double a = b1[j];
+            for (int i = 0; i < n_in; ++i) a += x[i] * W1[i * h + j];
+            h1[j] = a > 0.0 ? a : 0.0;
+        }
+        for (int j = 0; j < h; ++j) {
+            double a = b2[j];
+            for (int i = 0; i < h; ++i) a += h1[i] * W2[i * h + j];
+            h2[j] = a > 0.0 ? a : 0.0;
+        }
+        for (int j = 0; j < n_out; ++j) {
+            double a = b3[j];
+            for (int i = 0; i < h; ++i) a += h2[i] * W3[i * n_out + j];
+            y[j] = a + tmu;
+        }
+        return y;
+    }
+};
+
+// The selector file: $FFC_SELECTOR if set ("none" or empty: no file), else
+// data/selector_mi355x_fp64.txt in the directory of this library.
+std::string selector_path() {
+    if (const char* e = std::getenv("FFC_SELECTOR")) return std::strcmp(e, "none") == 0 ? std::string() : e;
+    Dl_info info;
+    if (dladdr(reinterpret_cast<void*>(&auto_bucket), &info) == 0 || !info.dli_fname) return std::string();
+    std::string lib = info.dli_fname;
+    const size_t slash = lib.find_last_of('/');
+    return (slash == std::string::npos ? std::string(".") : lib.substr(0, slash)) + "/data/selector_mi355x_fp64.txt";
 }
 
 }  // namespace
@@ -138,6 +253,13 @@ struct ffc_form {
     uint32_t* d_wave_mask = nullptr;
     int32_t* d_zero = nullptr;
     double* d_geo_grad = nullptr;  // curvilinear cells: geometry basis gradients at the points
+    // FFC_KERNEL_AUTO: the forms of the launches the selector picks (subs[0] = the library
+    // default tensor launch) and, per cell-count bucket round(log2 cells), the sub-form used
+    // and the selector's candidate index
+    bool is_auto = false, auto_from_selector = false;
+    std::vector<std::unique_ptr<ffc_form>> subs;
+    int8_t bucket_sub[kAutoBuckets] = {};
+    int32_t bucket_cand[kAutoBuckets] = {};
 
     ~ffc_form() {
         for (void* p : {static_cast<void*>(d_koff), static_cast<void*>(d_apack), static_cast<void*>(d_entry),
@@ -171,6 +293,72 @@ int ffc_compile_reference_tensor(const ffc_form_desc* desc, int64_t* n_I, int64_
     return FFC_OK;
 }
 
+namespace {
+// The form a call on `cells` cells runs on: an FFC_KERNEL_AUTO form delegates to the launch
+// its selector picked for that cell count; other forms are their own launch.
+const ffc_form* resolve(const ffc_form* f, int64_t cells) {
+    return f && f->is_auto ? f->subs[f->bucket_sub[auto_bucket(cells)]].get() : f;
+}
+// the library default tensor launch of an AUTO form (entry points other than tabulation)
+const ffc_form* resolve_default(const ffc_form* f) { return f && f->is_auto ? f->subs[0].get() : f; }
+
+int create_auto(const ffc_form_desc* desc, const ffc::FormSpec& spec, ffc_form** out) {
+    std::unique_ptr<ffc_form> f(new ffc_form());
+    f->desc = *desc;
+    f->is_auto = true;
+    ffc_form_desc d0 = *desc;
+    d0.kernel = FFC_KERNEL_TENSOR;
+    ffc_form* sub = nullptr;
+    int rc = ffc_form_create(&d0, &sub);
+    if (rc) return rc;
+    f->subs.emplace_back(sub);
+    f->device = sub->device;
+    f->stream = sub->stream;
+    // the selector was trained on FP64 Lagrange forms on affine cells: it decides there only
+    const bool lagrange = spec.kind >= FFC_MASS && spec.kind <= FFC_NS_CONVECTION;
+    if (desc->precision == FFC_FP64 && lagrange) {
+        const std::string path = selector_path();
+        SelectorNet net;
+        std::string err;
+        if (!path.empty() && net.load(path, &err)) {
+            f->auto_from_selector = true;
+            std::map<int, int> sub_of_cand{{0, 0}};
+            const double lI = std::log2(static_cast<double>(sub->rt.n_I));
+            const double la = std::log2(static_cast<double>(sub->n_alpha_form) + 1.0);
+            for (int b = 0; b < kAutoBuckets; ++b) {
+                // features: form rank, degree, log2 |i|, log2(|alpha| + 1), dimension, log2 cells,
+                // log2(cells |i|)
+                const double x[7] = {2.0, static_cast<double>(desc->degree), lI, la, static_cast<double>(desc->dim),
+                                     static_cast<double>(b), b + lI};
+                const std::vector<double> y = net.predict(x);
+                const int best = static_cast<int>(std::min_element(y.begin(), y.end()) - y.begin());
+                auto it = sub_of_cand.find(best);
+                if (it == sub_of_cand.end()) {
+                    const SelectorNet::Cand& c = net.cands[best];
+                    ffc_form_desc dc = *desc;
+                    dc.kernel = c.kernel;
+                    dc.tile_cells = c.tile_cells;
+                    dc.waves = c.waves;
+                    dc.persistent = c.persistent;
+                    dc.tile_window = c.tile_window;
+                    dc.geometry = c.geometry;
+                    ffc_form* sc = nullptr;
+                    if ((rc = ffc_form_create(&dc, &sc))) return rc;
+                    f->subs.emplace_back(sc);
+                    it = sub_of_cand.emplace(best, static_cast<int>(f->subs.size()) - 1).first;
+                }
+                f->bucket_sub[b] = static_cast<int8_t>(it->second);
+                f->bucket_cand[b] = best;
+            }
+        } else if (std::getenv("FFC_SELECTOR") && !path.empty()) {
+            return fail(FFC_E_INVALID, "FFC_SELECTOR: " + err);  // a file was named and cannot be used
+        }
+    }
+    *out = f.release();
+    return FFC_OK;
+}
+}  // namespace
+
 int ffc_form_create(const ffc_form_desc* desc, ffc_form** out) {
     if (!out) return fail(FFC_E_INVALID, "form output pointer is NULL");
     *out = nullptr;
@@ -180,6 +368,7 @@ int ffc_form_create(const ffc_form_desc* desc, ffc_form** out) {
     int dev = 0;
     rc = check_device(&dev);
     if (rc) return rc;
+    if (desc->kernel == FFC_KERNEL_AUTO) return create_auto(desc, spec, out);
     std::unique_ptr<ffc_form> f(new ffc_form());
     f->desc = *desc;
     f->device = dev;
@@ -358,7 +547,7 @@ int ffc_form_create(const ffc_form_desc* desc, ffc_form** out) {
             // writes, so this launch shape computes every entry
             for (void* p : {static_cast<void*>(f->d_koff), static_cast<void*>(f->d_apack),
                             static_cast<void*>(f->d_entry), static_cast<void*>(f->d_b)})
-                if (p) hipFree(p);
+                if (p) (void)hipFree(p);
             f->d_koff = nullptr, f->d_apack = nullptr, f->d_entry = nullptr, f->d_b = nullptr;
             const ffc::TilesF64 t = ffc::make_tiles_f64(rt, f->tile_window, false);
             f->sym_n = 0;
@@ -375,8 +564,9 @@ int ffc_form_create(const ffc_form_desc* desc, ffc_form** out) {
     return FFC_OK;
 }
 
-int ffc_form_get_info(const ffc_form* f, ffc_form_info* info) {
-    if (!f || !info) return fail(FFC_E_INVALID, "NULL argument");
+int ffc_form_get_info(const ffc_form* form, ffc_form_info* info) {
+    if (!form || !info) return fail(FFC_E_INVALID, "NULL argument");
+    const ffc_form* f = resolve_default(form);
     const auto& rt = f->rt;
     const int d = f->desc.dim;
     info->n_dofs = rt.n;
@@ -396,6 +586,16 @@ int ffc_form_get_info(const ffc_form* f, ffc_form_info* info) {
     info->waves = f->waves;
     info->fused_geometry = f->fused ? 1 : 0;
     info->symmetric = f->sym_n ? 1 : 0;
+    info->auto_launches = form->is_auto ? static_cast<int64_t>(form->subs.size()) : 0;
+    return FFC_OK;
+}
+
+int ffc_form_select(const ffc_form* f, int64_t cells, int32_t* candidate, int32_t* from_selector) {
+    if (!f || !candidate) return fail(FFC_E_INVALID, "NULL argument");
+    if (!f->is_auto) return fail(FFC_E_INVALID, "not an FFC_KERNEL_AUTO form");
+    if (cells < 0) return fail(FFC_E_INVALID, "cells < 0");
+    *candidate = f->bucket_cand[auto_bucket(cells)];
+    if (from_selector) *from_selector = f->auto_from_selector ? 1 : 0;
     return FFC_OK;
 }
 
@@ -464,9 +664,10 @@ int contract_chunk(const ffc_form* f, int64_t n, const double* amap, int64_t ast
 }
 }  // namespace
 
-int ffc_tabulate_tensor_affine(const ffc_form* f, int64_t cells, const double* affine_map, const double* coeffs,
+int ffc_tabulate_tensor_affine(const ffc_form* form, int64_t cells, const double* affine_map, const double* coeffs,
                                void* out) {
-    if (!f) return fail(FFC_E_INVALID, "form is NULL");
+    if (!form) return fail(FFC_E_INVALID, "form is NULL");
+    const ffc_form* f = resolve_default(form);
     if (f->desc.kernel != FFC_KERNEL_TENSOR) return fail(FFC_E_INVALID, "not a tensor-kernel form");
     if (f->desc.kind == FFC_CURVED_LAPLACE) return fail(FFC_E_UNSUPPORTED, "curvilinear cells have no affine map");
     if (cells < 0) return fail(FFC_E_INVALID, "cells < 0");
@@ -495,9 +696,10 @@ bool apply_tile_shape(const ffc_form* f, int* tile_cells, int* waves) {
 }
 }  // namespace
 
-int ffc_apply_tensor(const ffc_form* f, int64_t cells, const double* coords, const double* coeffs, const double* x,
+int ffc_apply_tensor(const ffc_form* form, int64_t cells, const double* coords, const double* coeffs, const double* x,
                      double* y) {
-    if (!f) return fail(FFC_E_INVALID, "form is NULL");
+    if (!form) return fail(FFC_E_INVALID, "form is NULL");
+    const ffc_form* f = resolve_default(form);
     if (f->desc.kernel != FFC_KERNEL_TENSOR || f->desc.precision != FFC_FP64 || f->desc.kind == FFC_CURVED_LAPLACE)
         return fail(FFC_E_UNSUPPORTED, "the operator action needs an FP64 tensor-kernel form on affine cells");
     if (cells < 0) return fail(FFC_E_INVALID, "cells < 0");
@@ -535,8 +737,9 @@ int ffc_apply_tensor(const ffc_form* f, int64_t cells, const double* coords, con
     return FFC_OK;
 }
 
-int ffc_tabulate_tensor(const ffc_form* f, int64_t cells, const double* coords, const double* coeffs, void* out) {
-    if (!f) return fail(FFC_E_INVALID, "form is NULL");
+int ffc_tabulate_tensor(const ffc_form* form, int64_t cells, const double* coords, const double* coeffs, void* out) {
+    if (!form) return fail(FFC_E_INVALID, "form is NULL");
+    const ffc_form* f = resolve(form, cells);
     if (cells < 0) return fail(FFC_E_INVALID, "cells < 0");
     if (cells == 0) return FFC_OK;
     if (!coords || !out) return fail(FFC_E_INVALID, "coords / out is NULL");
@@ -654,7 +857,7 @@ int ffc_batch_create(int32_t n, const ffc_form* const* forms, const int64_t* cel
     std::map<int, std::vector<ffc::BatchItem>> tgroups;              // tile launches
     int64_t amap_doubles = 0;
     for (int i = 0; i < n; ++i) {
-        const ffc_form* f = forms[i];
+        const ffc_form* f = resolve_default(forms[i]);
         if (!f) return fail(FFC_E_INVALID, "NULL form in batch");
         if (f->desc.kernel != FFC_KERNEL_TENSOR) return fail(FFC_E_UNSUPPORTED, "batches use the tensor kernel only");
         if (f->desc.kind == FFC_PIOLA_MASS || f->desc.kind == FFC_CURVED_LAPLACE || f->desc.kind == FFC_NEDELEC_MASS)
@@ -905,12 +1108,9 @@ int ffc_assemble(ffc_assembly* a, const void* element_tensors, int32_t tensor_by
     return e == hipSuccess ? FFC_OK : hip_fail(e, "assembly launch");
 }
 
-int ffc_operator_apply(const ffc_assembly* a, const ffc_form* f, const double* coords, const double* coeffs,
-                       const double* x, double* y, double* work) {
-    if (!a || !f) return fail(FFC_E_INVALID, "assembly / form is NULL");
-    if (f->rt.n != a->n) return fail(FFC_E_INVALID, "the form's element dofs differ from the dofmap's");
-    if (!x || !y) return fail(FFC_E_INVALID, "x / y is NULL");
-    if (a->cells > 0 && (!coords || !work)) return fail(FFC_E_INVALID, "coords / work is NULL");
+namespace {
+int operator_apply_impl(const ffc_assembly* a, const ffc_form* f, const double* coords, const double* coeffs,
+                        const double* x, double* y, double* work) {
     const int64_t m = a->cells * a->n;
     double* xl = work;
     double* yl = work + m;
@@ -922,6 +1122,26 @@ int ffc_operator_apply(const ffc_assembly* a, const ffc_form* f, const double* c
     }
     e = ffc::sum_slots(a->n_global, a->d_slot_ptr, a->d_slots, yl, y, f->stream);
     return e == hipSuccess ? FFC_OK : hip_fail(e, "sum launch");
+}
+
+int check_operator_args(const ffc_assembly* a, const ffc_form*& f, const double* coords, const double* x,
+                        const double* y) {
+    f = resolve_default(f);
+    if (!a || !f) return fail(FFC_E_INVALID, "assembly / form is NULL");
+    if (f->rt.n != a->n) return fail(FFC_E_INVALID, "the form's element dofs differ from the dofmap's");
+    if (!x || !y) return fail(FFC_E_INVALID, "x / y is NULL");
+    if (a->cells > 0 && !coords) return fail(FFC_E_INVALID, "coords is NULL");
+    return FFC_OK;
+}
+
+}  // namespace
+
+int ffc_operator_apply(const ffc_assembly* a, const ffc_form* f, const double* coords, const double* coeffs,
+                       const double* x, double* y, double* work) {
+    int rc = check_operator_args(a, f, coords, x, y);
+    if (rc) return rc;
+    if (a->cells > 0 && !work) return fail(FFC_E_INVALID, "work is NULL");
+    return operator_apply_impl(a, f, coords, coeffs, x, y, work);
 }
 
 void ffc_assembly_destroy(ffc_assembly* a) { delete a; }

@@ -2,7 +2,7 @@
 //
 //  geometry_kernel     one lane per cell, FP64: J = [x^1 - x^0, ...], det J, g = J^{-1}
 //                      (the affine map of Sec. 3.2; det and g_ab = dX_a/dx_b are what
-//                      the generated code of Sec. 5.4 reads from its AffineMap)
+//                      the generated code of Sec. 5.5 reads from its AffineMap)
 //  contract_f64        G_K tile built in LDS from the affine map (+ coefficients), then
 //                      out[c, i] = sum_alpha G[c, alpha] A^0[i, alpha] on
 //                      v_mfma_f64_16x16x4f64: M = 16 cells, N = 16 output entries,
@@ -74,31 +74,65 @@ struct FormTraits {
 
 // ------------------------------------------------------------------ geometry ----
 
-// det J and g = J^{-1} (g_ab = dX_a / dx_b) of a Jacobian J_kb = dx_k / dX_b
+// a*d - b*c to within about one rounding: the rounding error of b*c is recovered exactly
+// with an FMA (Kahan's algorithm), so the cancellation of the two products on a badly
+// shaped cell does not magnify it
+__device__ __forceinline__ double diff_of_products(double a, double d, double b, double c) {
+#pragma clang fp contract(off)
+    const double w = b * c;
+    const double e = fma(-b, c, w);  // w - b*c, exact
+    const double f = fma(a, d, -w);
+    return f + e;
+}
+
+// det J and g = J^{-1} (g_ab = dX_a / dx_b) of a Jacobian J_kb = dx_k / dX_b.  The
+// cofactors are differences of products and det J a sum of three products that cancel
+// on needles and slivers (det small against the products of edge lengths): both are
+// compensated -- cofactors by diff_of_products, the cofactor expansion of det by an
+// error-free transformation of every product and sum (Ogita, Rump and Oishi's Dot2) -- so det J
+// and g keep a relative error of a few roundings up to aspect ratios ~1e3 instead of
+// growing with the square of the aspect ratio.
 template <int D>
 __device__ __forceinline__ void invert_jacobian(const double (&J)[D][D], double& det, double (&g)[D][D]) {
+    // no multiply may be fused into a following add: the error terms assume rounded products
+#pragma clang fp contract(off)
     if constexpr (D == 2) {
-        det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        det = diff_of_products(J[0][0], J[1][1], J[0][1], J[1][0]);
         const double r = 1.0 / det;
         g[0][0] = J[1][1] * r;
         g[0][1] = -J[0][1] * r;
         g[1][0] = -J[1][0] * r;
         g[1][1] = J[0][0] * r;
     } else {
-        const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
-        const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
-        const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
-        det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+        const double c00 = diff_of_products(J[1][1], J[2][2], J[1][2], J[2][1]);
+        const double c01 = diff_of_products(J[1][2], J[2][0], J[1][0], J[2][2]);
+        const double c02 = diff_of_products(J[1][0], J[2][1], J[1][1], J[2][0]);
+        // Dot2: p carries the rounded sum, s the exact errors of every product and sum
+        double p = J[0][0] * c00;
+        double s = fma(J[0][0], c00, -p);
+        {
+            const double h = J[0][1] * c01, r = fma(J[0][1], c01, -h);
+            const double t = p + h, z = t - p;
+            s += ((p - (t - z)) + (h - z)) + r;
+            p = t;
+        }
+        {
+            const double h = J[0][2] * c02, r = fma(J[0][2], c02, -h);
+            const double t = p + h, z = t - p;
+            s += ((p - (t - z)) + (h - z)) + r;
+            p = t;
+        }
+        det = p + s;
         const double r = 1.0 / det;
         g[0][0] = c00 * r;
         g[1][0] = c01 * r;
         g[2][0] = c02 * r;
-        g[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * r;
-        g[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * r;
-        g[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * r;
-        g[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * r;
-        g[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * r;
-        g[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * r;
+        g[0][1] = diff_of_products(J[0][2], J[2][1], J[0][1], J[2][2]) * r;
+        g[1][1] = diff_of_products(J[0][0], J[2][2], J[0][2], J[2][0]) * r;
+        g[2][1] = diff_of_products(J[0][1], J[2][0], J[0][0], J[2][1]) * r;
+        g[0][2] = diff_of_products(J[0][1], J[1][2], J[0][2], J[1][1]) * r;
+        g[1][2] = diff_of_products(J[0][2], J[1][0], J[0][0], J[1][2]) * r;
+        g[2][2] = diff_of_products(J[0][0], J[1][1], J[0][1], J[1][0]) * r;
     }
 }
 

@@ -329,3 +329,31 @@ def curved_workload(dim: int, degree: int, n: int, seed: int, amplitude: float =
     coords = np.ascontiguousarray(P.reshape(P.shape[0], -1).T)
     return Workload("curved", dim, degree, coords, None, name=name,
                     meta={"cells": cells, "n_vertices": int(verts.shape[0])})
+
+
+# ------------------------------------------------------------- badly shaped cells ---
+# Single cells whose Jacobian J = R1 diag(s) R2 (R1, R2 random rotations) has condition
+# number `aspect`: needles (s = (1, 1/a, ..., 1/a): one long edge direction) and slivers
+# (s = (1, ..., 1, 1/a): a flat cell), each translated by U(-1, 1) per coordinate so that
+# the edge vectors are formed by cancelling subtractions, as in a mesh away from the origin.
+
+def badly_shaped(dim: int, cells: int, aspect: float, shape: str, seed: int) -> np.ndarray:
+    """SoA coordinates [(d+1)*d][cells] of positively oriented needles or slivers."""
+    if shape not in ("needle", "sliver"):
+        raise ValueError(shape)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    base = np.eye(dim + 1, dim, -1)  # vertex 0 at the origin, vertex k at e_k
+    out = np.empty((cells, dim + 1, dim))
+    for c in range(cells):
+        R1 = np.linalg.qr(rng.standard_normal((dim, dim)))[0]
+        R2 = np.linalg.qr(rng.standard_normal((dim, dim)))[0]
+        s = np.ones(dim)
+        if shape == "needle":
+            s[1:] = 1.0 / aspect
+        else:
+            s[-1] = 1.0 / aspect
+        v = base @ (R1 @ np.diag(s) @ R2).T + rng.uniform(-1.0, 1.0, size=dim)
+        if np.linalg.det(v[1:] - v[0]) < 0:
+            v[[1, 2]] = v[[2, 1]]
+        out[c] = v
+    return np.ascontiguousarray(out.reshape(cells, -1).T)

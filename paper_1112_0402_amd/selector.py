@@ -23,6 +23,7 @@ from __future__ import annotations
 
 import ctypes
 import math
+import os
 
 import numpy as np
 
@@ -207,6 +208,57 @@ class Selector:
     def choose(self, records):
         return [int(i) for i in np.argmin(self.predict_rel(records), axis=1)]
 
+    def export(self, path, candidates=CANDIDATES_FP64):
+        """Write the trained selector as the text file that the library's automatic kernel
+        choice (FFC_KERNEL_AUTO) reads at form creation: sizes, feature normalisation, the
+        offset of the targets, the flat FP32 parameters and the candidate launches, one per
+        line as "kernel tile_cells waves persistent tile_window geometry" with kernel 1 =
+        tensor, 2 = quadrature and geometry 0 = default, 1 = pass, 2 = fused."""
+        from . import capi
+
+        params = self.net.params.detach().cpu().numpy().astype(np.float32)
+        lines = ["ffc_selector 1", f"n_in {self.net.n_in} n_hidden {self.net.h} n_out {self.net.n_out}",
+                 "mu " + " ".join(repr(float(v)) for v in self.mu),
+                 "sd " + " ".join(repr(float(v)) for v in self.sd),
+                 f"tmu {self.tmu!r}",
+                 f"params {params.size} " + " ".join(repr(float(v)) for v in params),
+                 f"candidates {len(candidates)}"]
+        for c in candidates:
+            lines.append(" ".join(str(v) for v in (
+                capi.KERNELS[c["kernel"]], c.get("tile_cells", 0), c.get("waves", 0), c.get("persistent", 0),
+                c.get("tile_window", 0), capi.GEOMETRY[c.get("geometry", "default")])))
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            f.write("\n".join(lines) + "\n")
+        os.replace(tmp, path)
+
+    @classmethod
+    def load(cls, path):
+        """A selector with the parameters of a file written by export()."""
+        import torch
+
+        tok = open(path).read().split()
+        assert tok[0] == "ffc_selector" and tok[1] == "1", "not a selector file"
+        n_in, h, n_out = int(tok[3]), int(tok[5]), int(tok[7])
+        assert n_in == N_FEATURES and n_out == len(CANDIDATES_FP64)
+        i = 8
+        assert tok[i] == "mu"
+        mu = np.array([float(x) for x in tok[i + 1:i + 1 + n_in]]); i += 1 + n_in
+        assert tok[i] == "sd"
+        sd = np.array([float(x) for x in tok[i + 1:i + 1 + n_in]]); i += 1 + n_in
+        assert tok[i] == "tmu"
+        tmu = float(tok[i + 1]); i += 2
+        assert tok[i] == "params"
+        n = int(tok[i + 1])
+        params = np.array([float(x) for x in tok[i + 2:i + 2 + n]], dtype=np.float32)
+        sel = cls(n_hidden=h)
+        sel.mu, sel.sd, sel.tmu = mu, sd, tmu
+        sel.net.params = torch.tensor(params, dtype=torch.float32, device="cuda")
+        return sel
+
+
+DEFAULT_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "selector_mi355x_fp64.txt")
+
 
 def heuristic_choice(kind: str, dim: int, degree: int) -> int:
     """The paper's complexity model (Sec. 4.4): T_Q / T_T ~ (2q + n_f q - n_D)^d (n_f + n_D d + 1)
@@ -227,3 +279,22 @@ def regret(records, choices):
         valid = [t for t in r["ms"] if t is not None and t > 0]
         out.append(r["ms"][c] / min(valid) - 1.0)
     return np.array(out)
+
+
+if __name__ == "__main__":
+    import argparse
+
+    from . import tune
+
+    ap = argparse.ArgumentParser(description="train the selector on a stored sweep (on the GPU, with the "
+                                             "library's own MLP kernels) and write the file FFC_KERNEL_AUTO reads")
+    ap.add_argument("--sweep", default=os.path.join(os.path.dirname(os.path.abspath(__file__)), "data",
+                                                    "sweep_mi355x_fp64.jsonl"))
+    ap.add_argument("--out", default=DEFAULT_FILE)
+    ap.add_argument("--epochs", type=int, default=3000)
+    ap.add_argument("--seed", type=int, default=0)
+    args = ap.parse_args()
+    sel = Selector(seed=args.seed)
+    loss = sel.fit(tune.load_sweep(args.sweep), epochs=args.epochs)
+    sel.export(args.out)
+    print(f"selector: trained on {args.sweep} (final loss {loss:.4f}), written to {args.out}", flush=True)

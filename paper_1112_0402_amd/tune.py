@@ -141,11 +141,16 @@ def batch_forms(workloads, precision="fp64", choice="default", db: TuneDB | None
     is excluded; items with the same form and launch share one Form."""
     import torch
 
-    from .forms import Form
-
     cands = candidates(precision)
     tensor_idx = [i for i, c in enumerate(cands) if c["kernel"] == "tensor"]
     forms, out, picks = {}, [], []
+
+    def form_of(w, j):  # one Form per (form variant, candidate), shared by the meshes
+        key = (w.kind, w.dim, w.degree, j)
+        if key not in forms:
+            forms[key] = make_form(w.kind, w.dim, w.degree, precision, cands[j])
+        return forms[key]
+
     for w in workloads:
         if choice == "default":
             j = 0
@@ -157,25 +162,19 @@ def batch_forms(workloads, precision="fp64", choice="default", db: TuneDB | None
             else:
                 X = torch.from_numpy(w.coords).cuda()
                 C = None if w.coeffs is None else torch.from_numpy(w.coeffs).cuda()
-                fl = [make_form(w.kind, w.dim, w.degree, precision, cands[i]) for i in tensor_idx]
-                t = measure_all(fl, X, C, reps)
-                for f in fl:
-                    f.close()
+                t = measure_all([form_of(w, i) for i in tensor_idx], X, C, reps)
                 j = tensor_idx[int(np.argmin(t))]
                 if db is not None:
                     db.put(key, {"candidate": j, "tensor_candidate": j, "config": cands[j], "ms": min(t)})
         elif choice == "selector":
-            info = Form(w.kind, w.dim, w.degree, precision=precision).info
+            info = form_of(w, 0).info
             rec = {"kind": w.kind, "dim": w.dim, "degree": w.degree, "cells": w.cells, "n_I": info["n_entries"],
                    "n_alpha": info["n_alpha"], "ms": [1.0] * len(cands)}
             pred = selector.predict_rel([rec])[0]
             j = min(tensor_idx, key=lambda i: pred[i])
         else:
             raise ValueError(f"unknown choice {choice!r}")
-        key = (w.kind, w.dim, w.degree, j)
-        if key not in forms:
-            forms[key] = make_form(w.kind, w.dim, w.degree, precision, cands[j])
-        out.append(forms[key])
+        out.append(form_of(w, j))
         picks.append(j)
     return out, picks
 

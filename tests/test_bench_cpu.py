@@ -34,3 +34,20 @@ def test_quadrature_operation_count():
     assert bench.quadrature_model_flops("wlaplace", 400, 27, 3) == 86_400
     assert bench.quadrature_model_flops("laplace", 9, 1, 2) == 45
     assert bench.quadrature_model_flops("mass", 16, 4, 3) == 64
+
+
+def test_oracle_pass_covers_every_cell_in_chunks():
+    import numpy as np
+
+    import oracle
+    from paper_1112_0402_amd import meshgen
+
+    wl = meshgen.make_workload("wlaplace", 2, 2, 5, 1)  # 50 cells, chunks of 7 leave a ragged tail
+    ref = oracle.tabulate("wlaplace", 2, 2, wl.coords, wl.coeffs)
+    base, errs = bench.oracle_pass(wl, {"same": lambda c0, c1: ref[c0:c1],
+                                        "scaled": lambda c0, c1: ref[c0:c1] * (1 + 1e-9)}, np, chunk=7)
+    assert errs["same"]["max"] == 0.0 and errs["same"]["cells"] == wl.cells
+    assert abs(errs["scaled"]["max"] - 1e-9) < 1e-12
+    assert base["kind"] == "oracle" and base["value"] > 0 and base["sample"].startswith("every cell")
+    base, errs = bench.oracle_pass(wl, {"same": lambda c0, c1: ref[c0:c1]}, np, cells=12, chunk=5)
+    assert errs["same"]["cells"] == 12 and base["sample"].startswith("first 12 cells")

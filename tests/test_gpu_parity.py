@@ -1,7 +1,9 @@
 """GPU parity: the HIP path (through the C-ABI) against the FP64 oracle, element by
 element, on seeded meshes.  FP64 tensor and quadrature kernels: per-cell relative
-Frobenius error <= 1e-12.  Split-BF16: the measured error is printed per form; the
-6-product split must reach <= 1e-6."""
+Frobenius error <= 1e-12.  Split BF16: the 6-product split must reach <= 1e-6; the
+3-product split cannot (about 2^-17 per product before cancellation), so it is held to a
+per-form bound of 1.5 times its measured maximum on the same seeded inputs -- a loss of
+accuracy of the x3 path shows as a failure, not only as a printed number."""
 import math
 
 import numpy as np
@@ -11,13 +13,32 @@ import torch
 import oracle
 from paper_1112_0402_amd import capi, meshgen
 from paper_1112_0402_amd.forms import Batch, Form, compute_geometry
-from tests.gpu_util import rel_fro, require_gpu, say, to_dev
+from tests.gpu_util import every_cell_errors, rel_fro, require_gpu, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
 FP64_TOL = 1e-12
 SPLIT6_TOL = 1e-6
-SPLIT3_BOUND = 1e-4  # sanity bound; the measured value is reported
+# measured maximum per-cell error of the 3-product split per (kind, dim, degree) over the
+# seeded small meshes of these tests (the largest over the tests that run the form); the
+# bound is 1.5 times it
+SPLIT3_MEASURED = {
+    ("laplace", 2, 1): 1.42e-5, ("laplace", 2, 2): 2.36e-5, ("laplace", 2, 3): 2.33e-5, ("laplace", 2, 4): 1.37e-5,
+    ("laplace", 3, 1): 2.27e-5, ("laplace", 3, 2): 3.07e-5, ("laplace", 3, 3): 1.62e-5, ("laplace", 3, 4): 1.42e-5,
+    ("mass", 2, 1): 1.71e-5, ("mass", 2, 2): 7.7e-6, ("mass", 2, 3): 1.34e-5, ("mass", 3, 1): 2.02e-5,
+    ("mass", 3, 2): 7.7e-6, ("mass", 3, 3): 2.41e-5, ("wlaplace", 2, 4): 7.6e-6, ("wlaplace", 3, 3): 9.3e-6,
+    ("elasticity", 2, 3): 1.32e-5, ("elasticity", 3, 2): 1.40e-5, ("ns", 2, 2): 3.34e-5, ("ns", 3, 2): 1.47e-5,
+}
+SPLIT3_UNMEASURED = 1e-4  # forms without a recorded maximum (the measured value is printed)
+
+
+def split3_bound(kind, dim, q):
+    m = SPLIT3_MEASURED.get((kind, dim, q))
+    return 1.5 * m if m is not None else SPLIT3_UNMEASURED
+
+
+def split_tol(precision, kind, dim, q):
+    return SPLIT6_TOL if precision == "bf16x6" else split3_bound(kind, dim, q)
 
 
 def _small(kind, dim, q, seed=5):
@@ -88,7 +109,8 @@ def test_persistent_split_bf16_matches_tile_kernel(kind, dim, q, precision, tile
     e = rel_fro(a[idx], ref)[0]
     say(f"[bf16 persistent] {kind} d={dim} q={q} {precision} {tile_cells} cells: steps {pers.info['persistent_kmax']} "
         f"max err {e:.2e}")
-    assert e <= (SPLIT6_TOL if precision == "bf16x6" else SPLIT3_BOUND)
+    say(f"[x3-max] {kind} {dim} {q} {e:.3e}" if precision == "bf16x3" else "")
+    assert e <= split_tol(precision, kind, dim, q)
 
 
 @pytest.mark.parametrize("kind,dim,q", [("laplace", 2, 1), ("mass", 3, 3), ("laplace", 3, 4), ("wlaplace", 3, 3),
@@ -177,7 +199,9 @@ def test_split_bf16_parity_small(kind, dim, q, precision):
     assert got.dtype == np.float32
     emax, emed = rel_fro(got, ref)
     say(f"[split] {precision} {kind} d={dim} q={q}: max {emax:.2e} median {emed:.2e}")
-    assert emax <= (SPLIT6_TOL if precision == "bf16x6" else SPLIT3_BOUND)
+    if precision == "bf16x3":
+        say(f"[x3-max] {kind} {dim} {q} {emax:.3e}")
+    assert emax <= split_tol(precision, kind, dim, q)
 
 
 # ---------------------------------------------------------------- full sizes ---
@@ -201,9 +225,11 @@ def test_config1_full_mesh():
         assert emax <= FP64_TOL
 
 
-def test_config2_full_size_sampled():
+def test_config2_every_cell():
     """3D elasticity vector P2, 750,000 cells, default launch shape (the benchmarked one):
-    3000 sampled cells against the oracle, and two runs bitwise identical."""
+    every cell of the tensor and the quadrature kernels against the oracle; two tensor runs
+    bitwise identical; tensor and quadrature kernels (independent arithmetic) within 1e-12
+    of each other on every cell."""
     require_gpu()
     wl = meshgen.config2()
     assert wl.cells == 750_000
@@ -213,76 +239,162 @@ def test_config2_full_size_sampled():
     out2 = f.tabulate(X)
     torch.cuda.synchronize()
     assert torch.equal(out1, out2)
-    idx = _sample(wl.cells, 3000, 2)
-    ref = oracle.tabulate("elasticity", 3, 2, wl.coords[:, idx])
-    emax, emed = rel_fro(out1[torch.from_numpy(idx).cuda()].cpu().numpy(), ref)
-    say(f"[cfg2] tensor fp64 sampled: max {emax:.2e} median {emed:.2e}")
-    assert emax <= FP64_TOL
+    del out2
     q = Form("elasticity", 3, 2, kernel="quadrature").tabulate(X)
     torch.cuda.synchronize()
-    emax, emed = rel_fro(q[torch.from_numpy(idx).cuda()].cpu().numpy(), ref)
-    say(f"[cfg2] quadrature fp64 sampled: max {emax:.2e} median {emed:.2e}")
-    assert emax <= FP64_TOL
+    worst = 0.0
+    for c0 in range(0, wl.cells, 65536):  # tensor vs quadrature, on the GPU
+        a, b = out1[c0:c0 + 65536].reshape(-1, 900), q[c0:c0 + 65536].reshape(-1, 900)
+        worst = max(worst, float(((a - b).norm(dim=1) / b.norm(dim=1)).max()))
+    say(f"[cfg2] tensor vs quadrature, every cell: max {worst:.2e}")
+    assert worst <= FP64_TOL
+    errs = every_cell_errors("elasticity", 3, 2, wl.coords, None, {"tensor": out1, "quadrature": q})
+    for name, (emax, emed, n) in errs.items():
+        say(f"[cfg2] {name} fp64 vs oracle, every cell ({n}): max {emax:.2e} median {emed:.2e}")
+        assert n == 750_000 and emax <= FP64_TOL
 
 
-@pytest.mark.parametrize("precision", ["bf16x3", "bf16x6"])
-def test_config3_full_size_sampled(precision):
-    """3D weighted Laplacian P3, w in P1 ~ U(0.5, 2), 1,500,282 cells, split BF16 with
-    FP32 accumulation: 2000 sampled cells against the oracle."""
+def test_config3_every_cell():
+    """3D weighted Laplacian P3, w in P1 ~ U(0.5, 2), 1,500,282 cells: split BF16 x3 and x6
+    (FP32 accumulation) and the FP64 tensor kernel, every cell against the oracle."""
     require_gpu()
     wl = meshgen.config3()
     assert wl.cells == 1_500_282
     X, C = to_dev(wl.coords), to_dev(wl.coeffs)
-    out = Form("wlaplace", 3, 3, precision=precision).tabulate(X, C)
+    outs = {p: Form("wlaplace", 3, 3, precision=p).tabulate(X, C) for p in ("bf16x3", "bf16x6", "fp64")}
     torch.cuda.synchronize()
-    idx = _sample(wl.cells, 2000, 3)
-    ref = oracle.tabulate("wlaplace", 3, 3, wl.coords[:, idx], wl.coeffs[:, idx])
-    emax, emed = rel_fro(out[torch.from_numpy(idx).cuda()].cpu().numpy(), ref)
-    say(f"[cfg3] {precision}: max {emax:.2e} median {emed:.2e}")
-    assert emax <= (SPLIT6_TOL if precision == "bf16x6" else SPLIT3_BOUND)
+    errs = every_cell_errors("wlaplace", 3, 3, wl.coords, wl.coeffs, outs)
+    for p, (emax, emed, n) in errs.items():
+        say(f"[cfg3] {p} vs oracle, every cell ({n}): max {emax:.2e} median {emed:.2e}")
+        if p == "bf16x3":
+            say(f"[x3-max] cfg3 wlaplace 3 3 {emax:.3e}")
+        assert n == 1_500_282
+        assert emax <= (FP64_TOL if p == "fp64" else SPLIT6_TOL if p == "bf16x6" else CFG3_SPLIT3_BOUND)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "bf16x3"])
-def test_config4_full_size_batch_sampled(precision):
+CFG3_SPLIT3_BOUND = 1.5 * 1.31e-5  # 1.5 times the measured maximum of x3 over every cell of this workload
+
+
+# measured maximum x3 error per form variant over every cell of the mixed batch's meshes
+# (the tails of 10^5-cell meshes reach further than the small meshes above); bound 1.5x
+CFG4_SPLIT3_MEASURED = {
+    ("laplace", 2, 1): 1.72e-5, ("laplace", 2, 2): 2.86e-5, ("laplace", 2, 3): 2.92e-5, ("laplace", 2, 4): 1.88e-5,
+    ("laplace", 3, 1): 3.30e-5, ("laplace", 3, 2): 4.52e-5, ("laplace", 3, 3): 2.48e-5, ("laplace", 3, 4): 2.02e-5,
+    ("mass", 2, 1): 1.88e-5, ("mass", 2, 2): 8.5e-6, ("mass", 2, 3): 1.40e-5, ("mass", 3, 1): 2.14e-5,
+    ("mass", 3, 2): 8.4e-6, ("mass", 3, 3): 2.43e-5, ("ns", 2, 2): 5.97e-5, ("ns", 3, 2): 2.59e-5,
+}
+
+
+def test_config4_every_mesh_every_cell():
     """The mixed batch at full size (64 meshes, 7,426,598 cells) in the launch sequence the
-    bench times, captured in a graph and replayed: 24 sampled cells of every mesh against
-    the oracle (FP64 to 1e-12; split to its bound)."""
+    bench times, FP64 captured in a graph and replayed, and the split modes x6 and x3 run
+    eagerly: every cell of every mesh against the oracle (run once per mesh and shared),
+    every output value finite (outputs start as NaN)."""
     require_gpu()
-    wls, forms = _batch_inputs(precision, scale=1.0)
+    wls = meshgen.config4()
     assert sum(w.cells for w in wls) == 7_426_598
-    fl = [forms[(w.kind, w.dim, w.degree)] for w in wls]
     X = [to_dev(w.coords) for w in wls]
     C = [to_dev(w.coeffs) for w in wls]
-    outs = [f.empty_out(w.cells).fill_(float("nan")) for f, w in zip(fl, wls)]
-    s = torch.cuda.Stream()
-    b = Batch(fl, X, C, outs, stream=s)
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g, stream=s):
-        b.run()
-    with torch.cuda.stream(s):
-        g.replay()
-    torch.cuda.synchronize()
-    worst = 0.0
-    for k, (w, o) in enumerate(zip(wls, outs)):
-        idx = np.arange(w.cells) if w.cells <= 24 else _sample(w.cells, 20, 100 + k)
-        ref = oracle.tabulate(w.kind, w.dim, w.degree, np.ascontiguousarray(w.coords[:, idx]),
-                              None if w.coeffs is None else np.ascontiguousarray(w.coeffs[:, idx]))
-        got = o[torch.from_numpy(idx).cuda()].cpu().numpy()
-        worst = max(worst, rel_fro(got, ref)[0])
-    say(f"[cfg4] {precision}: {b.total_cells} cells, {b.launches} launches, max sampled error {worst:.2e}")
-    assert worst <= (FP64_TOL if precision == "fp64" else SPLIT3_BOUND)
+    outs = {}
+    for precision in ("fp64", "bf16x6", "bf16x3"):
+        forms = {}
+        for w in wls:
+            key = (w.kind, w.dim, w.degree)
+            if key not in forms:
+                forms[key] = Form(w.kind, w.dim, w.degree, precision=precision)
+        fl = [forms[(w.kind, w.dim, w.degree)] for w in wls]
+        o = [f.empty_out(w.cells).fill_(float("nan")) for f, w in zip(fl, wls)]
+        s = torch.cuda.Stream()
+        b = Batch(fl, X, C, o, stream=s)
+        if precision == "fp64":
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=s):
+                b.run()
+            with torch.cuda.stream(s):
+                g.replay()
+        else:
+            b.run()
+        torch.cuda.synchronize()
+        say(f"[cfg4] {precision}: {b.total_cells} cells, {b.launches} launches")
+        outs[precision] = o
+    worst = {p: 0.0 for p in outs}
+    x3 = {}
+    failures = []
+    total = 0
+    for k, w in enumerate(wls):
+        errs = every_cell_errors(w.kind, w.dim, w.degree, w.coords, w.coeffs, {p: outs[p][k] for p in outs})
+        total += w.cells
+        for p, (emax, _, _) in errs.items():
+            worst[p] = max(worst[p], emax)
+            if p == "bf16x3":
+                key = (w.kind, w.dim, w.degree)
+                x3[key] = max(x3.get(key, 0.0), emax)
+                tol = 1.5 * CFG4_SPLIT3_MEASURED.get(key, SPLIT3_UNMEASURED / 1.5)
+            else:
+                tol = FP64_TOL if p == "fp64" else SPLIT6_TOL
+            if not emax <= tol:
+                failures.append((w.name, p, emax, tol))
+    for key, e in sorted(x3.items()):
+        say(f"[x3-max] cfg4 {key[0]} {key[1]} {key[2]} {e:.3e}")
+    say(f"[cfg4] every cell of every mesh ({total}): max error fp64 {worst['fp64']:.2e}, "
+        f"bf16x6 {worst['bf16x6']:.2e}, bf16x3 {worst['bf16x3']:.2e}")
+    assert total == 7_426_598
+    assert not failures, failures
 
 
-def test_chunked_tabulation_beyond_workspace():
-    """More cells than the geometry workspace holds (2^21): processed in chunks."""
+def test_chunked_geometry_pass_with_coefficients():
+    """More cells than the geometry workspace holds (2^21), through the geometry-pass path of a
+    form with coefficients, so the chunk loop runs with c0 > 0 and offsets coordinates,
+    coefficients and outputs: every cell against the oracle, and bitwise equal to the
+    one-launch fused path (which has no chunks)."""
     require_gpu()
-    wl = meshgen.make_workload("mass", 2, 1, 1030, 8)  # 2,121,800 cells
+    wl = meshgen.make_workload("wlaplace", 3, 1, 71, 8)  # 2,147,286 cells
     assert wl.cells > (1 << 21)
-    out = Form("mass", 2, 1).tabulate(to_dev(wl.coords))
+    X, C = to_dev(wl.coords), to_dev(wl.coeffs)
+    fp = Form("wlaplace", 3, 1, geometry="pass")
+    ff = Form("wlaplace", 3, 1, geometry="fused")
+    assert fp.info["fused_geometry"] == 0 and fp.info["persistent_waves"] == 0 and ff.info["fused_geometry"] == 1
+    a = fp.tabulate(X, C)
+    b = ff.tabulate(X, C)
     torch.cuda.synchronize()
-    idx = np.unique(np.concatenate([_sample(wl.cells, 1000, 4), np.arange((1 << 21) - 3, (1 << 21) + 3)]))
-    ref = oracle.tabulate("mass", 2, 1, wl.coords[:, idx])
-    assert rel_fro(out[torch.from_numpy(idx).cuda()].cpu().numpy(), ref)[0] <= FP64_TOL
+    assert torch.equal(a, b)
+    errs = every_cell_errors("wlaplace", 3, 1, wl.coords, wl.coeffs, {"pass": a}, chunk=262144)
+    emax, emed, n = errs["pass"]
+    say(f"[chunks] wlaplace P1 3D geometry pass, {n} cells in 2 chunks: max {emax:.2e}")
+    assert emax <= FP64_TOL
+
+
+@pytest.mark.parametrize("kind,q", [("elasticity", 2), ("wlaplace", 3)])
+def test_chunked_operator_action(kind, q):
+    """ffc_apply_tensor on more cells than the geometry workspace holds, on the persistent
+    action path (chunks of 2^21 cells, the coefficients offset per chunk): equal to A^K x_K
+    from the oracle's element tensors on the cells around the chunk boundary and a sample,
+    and to the per-tile action kernel (no chunks) on every cell."""
+    require_gpu()
+    wl = meshgen.make_workload(kind, 3, q, 71, 9)
+    cells = wl.cells
+    assert cells > (1 << 21)
+    fp = Form(kind, 3, q, persistent=1)
+    assert fp.info["persistent_waves"] > 0 and fp.info["persistent_kmax"] <= 16, fp.info
+    ft = Form(kind, 3, q, persistent=-1)
+    n = fp.n
+    X, C = to_dev(wl.coords), to_dev(wl.coeffs)
+    x = torch.from_numpy(np.random.default_rng(2).standard_normal((cells, n))).cuda()
+    yp = fp.apply(X, x, C)
+    yt = ft.apply(X, x, C)
+    torch.cuda.synchronize()
+    rel = ((yp - yt).norm(dim=1) / yt.norm(dim=1)).max().item()
+    say(f"[chunks] {kind} P{q} action, persistent (chunked) vs per-tile on {cells} cells: max {rel:.2e}")
+    assert rel <= 1e-12
+    idx = np.unique(np.concatenate([_sample(cells, 400, 6), np.arange((1 << 21) - 40, (1 << 21) + 40)]))
+    ref = oracle.tabulate(kind, 3, q, np.ascontiguousarray(wl.coords[:, idx]),
+                          None if wl.coeffs is None else np.ascontiguousarray(wl.coeffs[:, idx]))
+    xs = x[torch.from_numpy(idx).cuda()].cpu().numpy()
+    want = np.einsum("cij,cj->ci", ref, xs)
+    got = yp[torch.from_numpy(idx).cuda()].cpu().numpy()
+    e = (np.linalg.norm(got - want, axis=1) / np.linalg.norm(want, axis=1)).max()
+    say(f"[chunks] {kind} P{q} action vs oracle A^K x on {len(idx)} cells around 2^21: max {e:.2e}")
+    assert e <= 1e-12
 
 
 # ---------------------------------------------------------------- edge cases ---
@@ -363,8 +475,9 @@ def test_persistent_batch_matches_oracle_and_single_calls(precision):
         o.zero_()
     b.run()  # counters reset themselves: a second run gives the same result
     torch.cuda.synchronize()
-    tol = FP64_TOL if precision == "fp64" else SPLIT3_BOUND
+    x3, failures = {}, []
     for w, f, x, c, o, o1 in zip(wls, fl, X, C, outs, first):
+        tol = FP64_TOL if precision == "fp64" else split_tol(precision, w.kind, w.dim, w.degree)
         assert torch.equal(o, o1)
         single = f.tabulate(x, c)
         torch.cuda.synchronize()
@@ -372,9 +485,14 @@ def test_persistent_batch_matches_oracle_and_single_calls(precision):
         assert torch.equal(o, single), w.name
         ref = oracle.tabulate(w.kind, w.dim, w.degree, w.coords, w.coeffs)
         e_b = rel_fro(o.cpu().numpy(), ref)[0]
-        e_s = rel_fro(single.cpu().numpy(), ref)[0]
-        assert e_b <= tol, (w.name, e_b)
-        assert e_s <= tol, (w.name, e_s)
+        if precision == "bf16x3":
+            key = (w.kind, w.dim, w.degree)
+            x3[key] = max(x3.get(key, 0.0), e_b)
+        if not e_b <= tol:
+            failures.append((w.name, e_b, tol))
+    for key, e in sorted(x3.items()):
+        say(f"[x3-max] small-batch {key[0]} {key[1]} {key[2]} {e:.3e}")
+    assert not failures, failures
 
 
 @pytest.mark.parametrize("precision", ["fp64", "bf16x6"])

@@ -37,7 +37,9 @@ def test_piola_split_bf16_action_and_orientation(dim):
     e6 = rel_fro(Form("piola", dim, 1, precision="bf16x6").tabulate(to_dev(wl.coords)).cpu().numpy(), ref)[0]
     e3 = rel_fro(Form("piola", dim, 1, precision="bf16x3").tabulate(to_dev(wl.coords)).cpu().numpy(), ref)[0]
     say(f"[piola split] d={dim}: x6 {e6:.2e}, x3 {e3:.2e}")
-    assert e6 <= 1e-6 and e3 <= 1e-4
+    say(f"[x3-max] piola {dim} 1 {e3:.3e}")
+    # x3: 1.5 times its measured maximum on this mesh (1.67e-05 in 2D, 2.19e-05 in 3D)
+    assert e6 <= 1e-6 and e3 <= 1.5 * (1.67e-05 if dim == 2 else 2.19e-05)
     f = Form("piola", dim, 1)
     x = np.random.default_rng(1).normal(size=(wl.cells, dim + 1))
     y = f.apply(to_dev(wl.coords), to_dev(x)).cpu().numpy()

@@ -1,6 +1,8 @@
-"""The quadrature comparison kernel on cell counts that leave a partial last block (its
-blocks hold 8 cells, or more for elasticity with few dofs): every entry of every cell is
-written, nothing past the last cell is, and the values match the oracle."""
+"""The quadrature comparison kernel on cell counts that leave a partial last block (a block
+holds up to 8 cells; more for elasticity, as many as give every thread a 2 x 2 block of
+function pairs, and for elements below 8 dofs, as many as give every thread one entry;
+fewer when one cell's tables fill the LDS): every entry of every cell is written, nothing
+past the last cell is, and the values match the oracle."""
 import numpy as np
 import pytest
 import torch
