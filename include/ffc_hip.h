@@ -318,6 +318,19 @@ int ffc_assemble(ffc_assembly* assembly, const void* element_tensors, int32_t te
  * stream; no allocation. */
 int ffc_operator_apply(const ffc_assembly* assembly, const ffc_form* form, const double* coords, const double* coeffs,
                        const double* x, double* y, double* work);
+/* ffc_operator_apply for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same kernels and the
+ * same result, bit for bit, but the 2 * cells * n_local doubles of scratch (the gathered
+ * local vectors and their products) live in a fixed library-owned device array of 2^24
+ * doubles (128 MiB) instead of a caller's `work` buffer.  Each device the library runs on
+ * holds its own copy of the array until the process ends; its address is looked up on the
+ * first call on a device.  The call allocates and frees nothing.  FFC_E_UNSUPPORTED (before
+ * anything is enqueued) if 2 * cells * n_local exceeds 2^24; FFC_E_INVALID if the form's
+ * device is not the current device.  Every call on one device shares the array and each call
+ * overwrites the part it uses: calls that overlap on one device (other streams, other
+ * threads) race and must be serialised by the caller. */
+int ffc_operator_apply_noalloc(const ffc_assembly* assembly, const ffc_form* form, const double* coords,
+                               const double* coeffs, const double* x, double* y);
 void ffc_assembly_destroy(ffc_assembly* assembly);
 
 /* Kernel selector network.  A multilayer perceptron that predicts the log run time of each

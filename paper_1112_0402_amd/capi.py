@@ -95,10 +95,11 @@ def lib():
     L.ffc_assembly_pattern.argtypes = [vp, vp, vp]
     L.ffc_assemble.argtypes = [vp, vp, i32, vp, i32]
     L.ffc_operator_apply.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.ffc_operator_apply_noalloc.argtypes = [vp, vp, vp, vp, vp, vp]
     L.ffc_assembly_destroy.argtypes = [vp]
     L.ffc_assembly_destroy.restype = None
     for name in ("ffc_assembly_create", "ffc_assembly_info", "ffc_assembly_pattern", "ffc_assemble",
-                 "ffc_operator_apply"):
+                 "ffc_operator_apply", "ffc_operator_apply_noalloc"):
         getattr(L, name).restype = ctypes.c_int
     fp = ctypes.c_float
     L.ffc_mlp_param_count.argtypes = [i32, i32, i32]

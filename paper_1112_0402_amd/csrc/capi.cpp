@@ -11,6 +11,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1134,6 +1135,30 @@ int check_operator_args(const ffc_assembly* a, const ffc_form*& f, const double*
     return FFC_OK;
 }
 
+// Scratch of the allocation-free operator: one array per device, in the library's code
+// object, loaded with it and kept until the process ends.  In host code `scratch` only
+// names the symbol; its device address comes from hipGetSymbolAddress, once per device.
+constexpr int64_t kNoallocScratchDoubles = int64_t(1) << 24;  // 128 MiB
+static __device__ __align__(256) double scratch[kNoallocScratchDoubles];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_on_current_device(int expected_device, double** out) {
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    if (dev != expected_device) return fail(FFC_E_INVALID, "call with the form's device current");
+    if (dev < 0 || dev >= kMaxDevices) return fail(FFC_E_UNSUPPORTED, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(FFC_E_DEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return FFC_OK;
+}
 }  // namespace
 
 int ffc_operator_apply(const ffc_assembly* a, const ffc_form* f, const double* coords, const double* coeffs,
@@ -1141,6 +1166,17 @@ int ffc_operator_apply(const ffc_assembly* a, const ffc_form* f, const double* c
     int rc = check_operator_args(a, f, coords, x, y);
     if (rc) return rc;
     if (a->cells > 0 && !work) return fail(FFC_E_INVALID, "work is NULL");
+    return operator_apply_impl(a, f, coords, coeffs, x, y, work);
+}
+
+int ffc_operator_apply_noalloc(const ffc_assembly* a, const ffc_form* f, const double* coords, const double* coeffs,
+                               const double* x, double* y) {
+    int rc = check_operator_args(a, f, coords, x, y);
+    if (rc) return rc;
+    if (2 * a->cells * a->n > kNoallocScratchDoubles)
+        return fail(FFC_E_UNSUPPORTED, "2 * cells * n_local exceeds the 2^24 doubles of the allocation-free scratch");
+    double* work = nullptr;
+    if ((rc = scratch_on_current_device(f->device, &work))) return rc;
     return operator_apply_impl(a, f, coords, coeffs, x, y, work);
 }
 
