@@ -47,9 +47,12 @@ PROFILES = os.path.join(ROOT, "profiles")
 
 
 def kernel_source_hash() -> str:
+    """sha256 (first 16 hex) of the kernel sources: kernels.h, kernels_device.h and every
+    kernels_*.hip, in name order."""
+    csrc = os.path.join(ROOT, "paper_1112_0402_amd", "csrc")
     h = hashlib.sha256()
-    for f in ("kernels.hip", "kernels.h"):
-        with open(os.path.join(ROOT, "paper_1112_0402_amd", "csrc", f), "rb") as fh:
+    for f in sorted(f for f in os.listdir(csrc) if f.startswith("kernels")):
+        with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 

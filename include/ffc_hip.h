@@ -135,7 +135,10 @@ typedef struct {
     int32_t precision;   /* ffc_precision */
     int32_t kernel;      /* ffc_kernel */
     int32_t tile_cells;  /* cells per workgroup tile of the contraction: 0 = default, else 16, 32 or 64 */
-    int32_t waves;       /* waves per workgroup of the contraction: 0 = default, else 1, 2, 4 or 8 */
+    int32_t waves;       /* waves per workgroup of the contraction: 0 = default, else 1, 2, 4, 8,
+                            12 or 16 (the persistent FP64 kernel: 12 = 6 compute + 6 I/O
+                            waves, which also computes the affine maps; 16 = 10 + 6 with a
+                            geometry pass) */
     int32_t tile_window; /* FP64 tensor kernel: grouping of the n_I output entries into the
                             16-entry MFMA tiles.  0 = default; 16 = consecutive entries; a
                             multiple of 16 = rows clustered greedily (smallest union of nonzero
@@ -148,11 +151,11 @@ typedef struct {
     int32_t geometry;    /* tensor kernel, ffc_tabulate_tensor: where the affine map is
                             computed.  FFC_GEOMETRY_PASS = a geometry kernel writes it to a
                             form-owned workspace that the contraction reads;
-                            FFC_GEOMETRY_FUSED = each cell tile computes it in LDS from the
-                            coordinates (one launch, no workspace).  The persistent kernel
-                            always uses the pass.  0 = default: fused for the per-tile
-                            kernels (measured faster on MI355X at every swept shape), the
-                            pass for the persistent kernel. */
+                            FFC_GEOMETRY_FUSED = the contraction computes it from the
+                            coordinates (one launch, no workspace round trip): the per-tile
+                            kernels per cell tile in LDS, the persistent FP64 kernel one tile
+                            ahead of the contraction.  The persistent split-BF16 kernel always
+                            uses the pass.  0 = default = fused where available. */
     int32_t symmetry;    /* FP64 tensor kernel: 0 = auto (for the symmetric forms -- all but
                             FFC_NS_CONVECTION -- compute only the entries i1 <= i2 on the
                             matrix cores and write each also at (i2, i1): half the MFMA

@@ -38,7 +38,8 @@ def build(verbose: bool = True) -> str:
     o = os.path.join(objdir, "reference_tensor.o")
     jobs.append((["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-c", os.path.join(CSRC, "reference_tensor.cpp"),
                   "-o", o], o))
-    for src in ("kernels.hip", "mlp.hip", "assembly.hip", "capi.cpp"):
+    kernel_units = sorted(f for f in os.listdir(CSRC) if f.startswith("kernels_") and f.endswith(".hip"))
+    for src in (*kernel_units, "mlp.hip", "assembly.hip", "capi.cpp"):
         o = os.path.join(objdir, src.split(".")[0] + ".o")
         extra = ["-x", "hip"] if src.endswith(".cpp") else []
         jobs.append(([HIPCC, *HIP_FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", o], o))

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <initializer_list>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -74,7 +75,7 @@ constexpr int kPersistentMinEntries = 576;
 // The same threshold for the persistent split-BF16 kernel (FP32 output: half the bytes
 // per entry).
 constexpr int kBf16PersistentMinEntries = 256;
-bool valid_waves(int w) { return w == 1 || w == 2 || w == 4 || w == 8 || w == 16; }
+bool valid_waves(int w) { return w == 1 || w == 2 || w == 4 || w == 8 || w == 12 || w == 16; }
 
 int check_desc(const ffc_form_desc* d, ffc::FormSpec* spec) {
     if (!d) return fail(FFC_E_INVALID, "desc is NULL");
@@ -97,7 +98,7 @@ int check_desc(const ffc_form_desc* d, ffc::FormSpec* spec) {
     if (d->kind == FFC_CURVED_LAPLACE && d->precision != FFC_FP64)
         return fail(FFC_E_UNSUPPORTED, "the curvilinear Laplacian is FP64 only");
     if (d->tile_cells != 0 && !valid_tile(d->tile_cells)) return fail(FFC_E_INVALID, "tile_cells must be 0, 16, 32 or 64");
-    if (d->waves != 0 && !valid_waves(d->waves)) return fail(FFC_E_INVALID, "waves must be 0, 1, 2, 4, 8 or 16");
+    if (d->waves != 0 && !valid_waves(d->waves)) return fail(FFC_E_INVALID, "waves must be 0, 1, 2, 4, 8, 12 or 16");
     if (d->geometry < 0 || d->geometry > FFC_GEOMETRY_FUSED) return fail(FFC_E_INVALID, "geometry must be 0, 1 or 2");
     if (d->symmetry < -1 || d->symmetry > 0) return fail(FFC_E_INVALID, "symmetry must be 0 or -1");
     if (d->persistent < -1 || d->persistent > 1) return fail(FFC_E_INVALID, "persistent must be -1, 0 or 1");
@@ -414,14 +415,19 @@ int ffc_form_create(const ffc_form_desc* desc, ffc_form** out) {
         if ((rc = upload(t.koff, &f->d_koff)) || (rc = upload(t.apack, &f->d_apack)) ||
             (rc = upload(t.entry, &f->d_entry)) || (rc = upload(t.b, &f->d_b)))
             return rc;
-        // persistent workgroups: 16 waves with up to 16 register-resident k steps each, or
-        // 8 waves with up to 32; the 16-cell output rows must be stageable in LDS
+        // persistent workgroups of 12 waves (6 compute, ~168 registers per lane: the kernel then
+        // also computes the affine maps) or 16 waves (10 compute, 128 registers, affine maps from
+        // a geometry pass), with up to 24 register-resident k steps per compute wave; the
+        // 16-cell output rows must be stageable in LDS
         const ffc::LdsPlan pl = ffc::plan_lds(spec.dim, spec.kind, 16, rt.n_I, rt.n_alpha, 0, false, ffc::kLdsBudget);
         const bool want_persistent = spec.kind != FFC_CURVED_LAPLACE &&
             (desc->persistent == 1 || (desc->persistent == 0 && rt.n_I >= kPersistentMinEntries));
+        // default 16 waves: measured faster than 12 on MI355X (equal for elasticity P2 once the
+        // 12-wave kernel's own geometry is counted, slower for the convection form's longer
+        // per-wave MFMA chains); 12 on request
         if (want_persistent && pl.staged && (desc->tile_cells == 0 || desc->tile_cells == 16)) {
             ffc::WaveSchedule ws;
-            for (int w : {16}) {
+            for (int w : {16, 12}) {
                 if (desc->waves != 0 && desc->waves != w) continue;
                 ffc::WaveSchedule cand = ffc::make_wave_schedule(t, w - ffc::kIoWaves);
                 if (cand.max_steps <= 24 && 16 * static_cast<int64_t>(rt.n_I) / 2 <=
@@ -506,8 +512,13 @@ int ffc_form_create(const ffc_form_desc* desc, ffc_form** out) {
         f->amap_cap = spec.kind == FFC_CURVED_LAPLACE ? ((int64_t(1) << 21) * (1 + spec.dim * spec.dim) / rows + 63) / 64 * 64
                                                      : int64_t(1) << 21;
         const size_t bytes = static_cast<size_t>(f->amap_cap) * rows * sizeof(double);
-        f->fused = desc->geometry != FFC_GEOMETRY_PASS && f->pwaves == 0;
-        if (!f->fused && hipMalloc(reinterpret_cast<void**>(&f->d_amap), bytes) != hipSuccess)
+        // fused: the contraction computes the affine map itself -- the per-tile kernels in LDS
+        // per tile, the persistent FP64 kernel one tile ahead (the split-BF16 persistent kernel
+        // keeps the pass)
+        f->fused = desc->geometry != FFC_GEOMETRY_PASS && !f->bpersistent && (f->pwaves == 0 || f->pwaves == 12);
+        // the workspace serves the geometry pass, and the persistent operator action
+        const bool need_workspace = !f->fused || f->pwaves > 0;
+        if (need_workspace && hipMalloc(reinterpret_cast<void**>(&f->d_amap), bytes) != hipSuccess)
             return fail(FFC_E_NOMEM, "hipMalloc failed for the geometry workspace");
         // default launch shape when the persistent kernel does not apply
         const bool bf = desc->precision != FFC_FP64;
@@ -774,10 +785,15 @@ int ffc_tabulate_tensor(const ffc_form* form, int64_t cells, const double* coord
     const bool bf16 = f->desc.precision != FFC_FP64;
     const size_t obytes = bf16 ? 4 : 8;
     if (f->fused) {
-        // one launch: every cell tile computes its affine map from the coordinates
+        // one launch: the contraction computes the affine maps from the coordinates
         ffc::ContractArgs a = contract_args(f, cells, nullptr, 0, coeffs, cells, out);
         a.coords = coords;
-        hipError_t e = ffc::launch_contract(d, kind, bf16, f->tile_cells, f->waves, a, f->stream);
+        hipError_t e = hipErrorInvalidValue;
+        if (f->pwaves > 0 && !bf16) {
+            ffc::PersistArgs p{f->d_woff, f->d_wave_b, f->d_wave_word, f->d_wave_mask, f->d_zero, f->n_zero};
+            e = ffc::launch_contract_persistent(d, kind, f->pkmax, f->pwaves, f->pgrid, a, p, f->stream);
+        }
+        if (e == hipErrorInvalidValue) e = ffc::launch_contract(d, kind, bf16, f->tile_cells, f->waves, a, f->stream);
         if (e != hipSuccess) return hip_fail(e, "contraction kernel launch");
         return FFC_OK;
     }
@@ -806,7 +822,7 @@ struct BatchLaunch {
     ffc::BatchItem* d_items = nullptr;
     int32_t* d_unit_item = nullptr;  // tile launches: [units] item of each tile
     int64_t units = 0;               // tiles
-    int waves = 16, mt = 1, grid = 0;  // tile launches: workgroup size and tile size 16*mt
+    int waves = 16, mt = 1, grid = 0;  // waves per workgroup; tile launches: tile size 16*mt
     size_t lds = 0;
 };
 
@@ -909,13 +925,18 @@ int ffc_batch_create(int32_t n, const ffc_form* const* forms, const int64_t* cel
             it.head_bytes = pb.head_bytes;
             amap_doubles += cells[i] * (1 + d * d);
             pgroups[f].push_back(it);
-        } else if (!bf && f->pwaves == 16 && aligned && p16.staged &&
-            (1 + d * d + f->rt.n_coeff) * 16 <= 64 * (16 - ffc::kIoWaves)) {
+        } else if (!bf && (f->pwaves == 12 || f->pwaves == 16) && aligned && p16.staged &&
+                   ffc::persistent_fetch_rows(d, f->desc.kind, f->pwaves == 12) * 16 <= 64 * (f->pwaves - ffc::kIoWaves) &&
+                   p16.stage_bytes + ffc::persistent_head_bytes(d, f->desc.kind, f->pwaves == 12) + p16.g_bytes <=
+                       ffc::kLdsBudget) {
+            // 12-wave schedules: the persistent launch computes each tile's affine map from the
+            // coordinates; 16-wave schedules read the maps of a geometry pass
             it.kmax = f->pkmax;
             it.p = ffc::PersistArgs{f->d_woff, f->d_wave_b, f->d_wave_word, f->d_wave_mask, f->d_zero, f->n_zero};
             it.stage_bytes = p16.stage_bytes;
-            it.head_bytes = p16.head_bytes;
-            amap_doubles += cells[i] * (1 + d * d);
+            it.head_bytes = ffc::persistent_head_bytes(d, f->desc.kind, f->pwaves == 12);
+            it.waves = f->pwaves;
+            if (f->pwaves == 16) amap_doubles += cells[i] * (1 + d * d);
             pgroups[f].push_back(it);
         } else {
             const int ct = f->tile_cells;
@@ -943,16 +964,23 @@ int ffc_batch_create(int32_t n, const ffc_form* const* forms, const int64_t* cel
         L.kmax = L.items[0].kmax;
         L.mt = bf16 ? L.items[0].mt : 1;
         const int ct = 16 * L.mt;
-        L.lds = bf16 ? ffc::plan_bf16_persistent(L.dim, L.kind, ct, L.items[0].n_I, L.items[0].n_tiles,
-                                                 L.items[0].kpad, L.items[0].n_seg).total
-                     : ffc::plan_lds(L.dim, L.kind, 16, L.items[0].n_I, L.items[0].n_alpha, 0, false,
-                                     ffc::kLdsBudget).total;
+        if (bf16) {
+            L.lds = ffc::plan_bf16_persistent(L.dim, L.kind, ct, L.items[0].n_I, L.items[0].n_tiles, L.items[0].kpad,
+                                              L.items[0].n_seg).total;
+        } else {
+            const ffc::LdsPlan pl =
+                ffc::plan_lds(L.dim, L.kind, 16, L.items[0].n_I, L.items[0].n_alpha, 0, false, ffc::kLdsBudget);
+            L.lds = pl.stage_bytes + L.items[0].head_bytes + pl.g_bytes;
+        }
+        L.waves = bf16 ? 16 : L.items[0].waves;
         for (auto& it : L.items) {
             it.unit_begin = L.units;
             L.units += (it.cells + ct - 1) / ct;
-            it.amap = b->d_amap + amap_off;
-            b->geometry.push_back({it.dim, it.cells, it.coords, b->d_amap + amap_off});
-            amap_off += it.cells * (1 + it.dim * it.dim);
+            if (bf16 || L.waves == 16) {  // affine maps from a geometry pass
+                it.amap = b->d_amap + amap_off;
+                b->geometry.push_back({it.dim, it.cells, it.coords, b->d_amap + amap_off});
+                amap_off += it.cells * (1 + it.dim * it.dim);
+            }
         }
         // one 1024-thread workgroup per CU (the register file holds one)
         L.grid = static_cast<int>(std::min<int64_t>(prop.multiProcessorCount, L.units));
@@ -995,7 +1023,7 @@ int ffc_batch_run(ffc_batch* b) {
     }
     for (const auto& L : b->launches) {
         hipError_t e = L.persistent
-                           ? ffc::launch_batch_persistent(L.dim, L.kind, L.kmax, b->nseg, L.mt, L.d_items,
+                           ? ffc::launch_batch_persistent(L.dim, L.kind, L.kmax, b->nseg, L.mt, L.waves, L.d_items,
                                                           static_cast<int>(L.items.size()), L.units, L.grid, L.lds,
                                                           b->stream)
                            : ffc::launch_batch_tiles(L.d_items, L.d_unit_item, L.units, L.waves, L.mt, b->nseg,

@@ -94,6 +94,8 @@ struct PersistArgs {
 constexpr int kIoWaves = 6;
 // 16-byte register slots per I/O lane holding a staged tile (16 rows of up to 912 doubles)
 constexpr int kIoSlots = 20;
+// With a.coords set the kernel computes each tile's affine map from the coordinates
+// (a.amap unused); else it reads the affine map from a.amap.
 // Returns hipErrorInvalidValue when the form does not fit this kernel (caller falls back).
 hipError_t launch_contract_persistent(int dim, int kind, int kmax, int waves, int grid, ContractArgs a,
                                       const PersistArgs& p, hipStream_t stream);
@@ -114,6 +116,10 @@ hipError_t launch_contract_bf16_persistent(int dim, int kind, int tile_cells, in
 // contraction, plus at most 16 register steps per wave and 16 * n_dof <= 2 * 64 * kIoWaves.
 size_t apply_lds_bytes(int dim, int kind, int tile_cells, int n_I, int n_alpha, int n_dof);
 hipError_t launch_apply(int dim, int kind, int tile_cells, int waves, ContractArgs a, hipStream_t stream);
+// LDS of the persistent FP64 kernel's map / coefficient / coordinate rows (geo: the kernel
+// computes the affine map), and the rows its compute waves fetch per tile
+size_t persistent_head_bytes(int dim, int kind, bool geo);
+int persistent_fetch_rows(int dim, int kind, bool geo);
 hipError_t launch_apply_persistent(int dim, int kind, int kmax, int waves, int grid, ContractArgs a,
                                    const PersistArgs& p, hipStream_t stream);
 hipError_t launch_quadrature(int dim, int kind, const QuadArgs& a, hipStream_t stream);
@@ -134,7 +140,8 @@ struct BatchItem {
     int32_t dim, kind, n_I, n_alpha, n_tiles, kpad, n_seg, n_coeff;
     int32_t mt, staged;     // tile items: cell tile 16*mt, output rows staged in LDS
     int32_t sym_n, reserved2;  // FP64 symmetric forms: element dofs, else 0
-    int32_t kmax, reserved; // persistent items: register steps per wave
+    int32_t kmax, waves;    // persistent items: register steps per wave; FP64: waves per workgroup
+                            // (12: the launch computes the affine maps, 16: read from amap)
     size_t stage_bytes, head_bytes;  // LDS plan: staged rows (0 = direct stores), map + coefficients
     const int32_t* koff;
     const uint32_t* apack;
@@ -152,10 +159,11 @@ struct BatchItem {
 hipError_t launch_batch_tiles(const BatchItem* items, const int32_t* unit_item, int64_t units, int waves, int mt,
                               int nseg, size_t lds, hipStream_t stream);
 // Persistent launch over the items of one form (items in unit_begin order, `tiles` cell
-// tiles in all): `grid` workgroups of 16 waves, workgroup w runs tiles w, w + grid, ...
-// nseg 0: FP64 kernel (16-cell tiles, kmax register steps); nseg 3 / 6: split-BF16 kernel
-// (16*mt-cell tiles, kmax = its register steps).
-hipError_t launch_batch_persistent(int dim, int kind, int kmax, int nseg, int mt, const BatchItem* items, int n_items,
-                                   int64_t tiles, int grid, size_t lds, hipStream_t stream);
+// tiles in all): `grid` workgroups, workgroup w runs tiles w, w + grid, ...
+// nseg 0: FP64 kernel (16-cell tiles, kmax register steps; 12 waves computing the affine
+// maps from the coordinates, or 16 waves reading them from the items' amap); nseg 3 / 6:
+// split-BF16 kernel (16 waves, 16*mt-cell tiles, kmax = its register steps, amap read).
+hipError_t launch_batch_persistent(int dim, int kind, int kmax, int nseg, int mt, int waves, const BatchItem* items,
+                                   int n_items, int64_t tiles, int grid, size_t lds, hipStream_t stream);
 
 }  // namespace ffc

@@ -1,0 +1,94 @@
+// Geometry kernels: the affine map (one lane per cell) and, for curvilinear cells, G at the points.
+#include "kernels_device.h"
+
+namespace ffc {
+
+template <int D>
+__global__ __launch_bounds__(256) void geometry_kernel(int64_t cells, const double* __restrict__ coords,
+                                                       int64_t cstride, double* __restrict__ amap, int64_t astride) {
+    const int64_t c = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (c >= cells) return;
+    double x[D + 1][D];
+#pragma unroll
+    for (int v = 0; v <= D; ++v)
+#pragma unroll
+        for (int k = 0; k < D; ++k) x[v][k] = __builtin_nontemporal_load(&coords[(v * D + k) * cstride + c]);
+    double det, g[D][D];
+    affine_map<D>(x, det, g);
+    amap[c] = det;
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = 0; b < D; ++b) amap[(1 + a * D + b) * astride + c] = g[a][b];
+}
+
+// Cells with P2 geometry (NG nodes): one lane per cell; at every quadrature point p,
+// J(X_p) = sum_k x_k (grad Psi_k(X_p))^T, then G[(p, a <= b)] = |det J| (g g^T)_ab, SoA
+// [n_pts * D(D+1)/2][gstride].  grad: [n_pts][NG][D] reference gradients of the geometry basis.
+template <int D>
+__global__ __launch_bounds__(256) void curved_geometry_kernel(int64_t cells, const double* __restrict__ coords,
+                                                              int64_t cstride, int n_pts,
+                                                              const double* __restrict__ grad, double* __restrict__ G,
+                                                              int64_t gstride) {
+    constexpr int NG = D == 2 ? 6 : 10;
+    constexpr int NP = D * (D + 1) / 2;
+    const int64_t c = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (c >= cells) return;
+    double x[NG][D];
+#pragma unroll
+    for (int k = 0; k < NG; ++k)
+#pragma unroll
+        for (int j = 0; j < D; ++j) x[k][j] = __builtin_nontemporal_load(&coords[(k * D + j) * cstride + c]);
+    for (int p = 0; p < n_pts; ++p) {
+        double J[D][D];
+#pragma unroll
+        for (int j = 0; j < D; ++j)
+#pragma unroll
+            for (int b = 0; b < D; ++b) J[j][b] = 0.0;
+#pragma unroll
+        for (int k = 0; k < NG; ++k)
+#pragma unroll
+            for (int b = 0; b < D; ++b) {
+                const double gk = grad[(p * NG + k) * D + b];
+#pragma unroll
+                for (int j = 0; j < D; ++j) J[j][b] = fma(x[k][j], gk, J[j][b]);
+            }
+        double det, g[D][D];
+        invert_jacobian<D>(J, det, g);
+        const double adet = fabs(det);
+        int pr = 0;
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int b = a; b < D; ++b, ++pr) {
+                double s = 0.0;
+#pragma unroll
+                for (int k = 0; k < D; ++k) s += g[a][k] * g[b][k];
+                G[(p * NP + pr) * gstride + c] = adet * s;
+            }
+    }
+}
+
+hipError_t launch_curved_geometry(int dim, int64_t cells, const double* coords, int64_t cstride, int n_pts,
+                                  const double* grad, double* G, int64_t gstride, hipStream_t stream) {
+    if (cells <= 0) return hipSuccess;
+    const unsigned grid = static_cast<unsigned>((cells + 255) / 256);
+    if (dim == 2)
+        curved_geometry_kernel<2><<<grid, 256, 0, stream>>>(cells, coords, cstride, n_pts, grad, G, gstride);
+    else
+        curved_geometry_kernel<3><<<grid, 256, 0, stream>>>(cells, coords, cstride, n_pts, grad, G, gstride);
+    return hipGetLastError();
+}
+
+hipError_t launch_geometry(int dim, int64_t cells, const double* coords, int64_t cstride, double* amap,
+                           int64_t astride, hipStream_t stream) {
+    if (cells <= 0) return hipSuccess;
+    const unsigned grid = static_cast<unsigned>((cells + 255) / 256);
+    if (dim == 2)
+        geometry_kernel<2><<<grid, 256, 0, stream>>>(cells, coords, cstride, amap, astride);
+    else
+        geometry_kernel<3><<<grid, 256, 0, stream>>>(cells, coords, cstride, amap, astride);
+    return hipGetLastError();
+}
+
+}  // namespace ffc

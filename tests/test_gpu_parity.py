@@ -114,17 +114,22 @@ def test_persistent_split_bf16_matches_tile_kernel(kind, dim, q, precision, tile
 
 
 @pytest.mark.parametrize("kind,dim,q", [("laplace", 2, 1), ("mass", 3, 3), ("laplace", 3, 4), ("wlaplace", 3, 3),
-                                        ("elasticity", 3, 1), ("ns", 2, 2), ("wlaplace", 2, 4), ("elasticity", 2, 3)])
+                                        ("elasticity", 3, 1), ("ns", 2, 2), ("wlaplace", 2, 4), ("elasticity", 2, 3),
+                                        ("elasticity", 3, 2), ("ns", 3, 2)])
 @pytest.mark.parametrize("precision", ["fp64", "bf16x6"])
 @pytest.mark.parametrize("tile_cells", [0, 16, 64])
 def test_fused_geometry_matches_geometry_pass(kind, dim, q, precision, tile_cells):
-    """The one-launch path (affine map computed per tile in LDS) equals the geometry pass
-    plus contraction bit for bit, and the oracle to the precision's bound."""
+    """The one-launch path (affine map computed in the contraction: per tile in LDS, or one
+    tile ahead in the persistent kernel) equals the geometry pass plus contraction bit for
+    bit, and the oracle to the precision's bound."""
     require_gpu()
     wl = _small(kind, dim, q)
     fused = Form(kind, dim, q, precision=precision, geometry="fused", tile_cells=tile_cells)
     passed = Form(kind, dim, q, precision=precision, geometry="pass", tile_cells=tile_cells)
     a, b = _run(fused, wl), _run(passed, wl)
+    if fused.info["persistent_waves"]:
+        say(f"[fused] {kind} d={dim} q={q} {precision}: persistent {fused.info['persistent_waves']} waves, "
+            f"fused {fused.info['fused_geometry']}; pass form: {passed.info['persistent_waves']} waves")
     assert np.array_equal(a, b)
     ref = oracle.tabulate(kind, dim, q, wl.coords, wl.coeffs)
     assert rel_fro(a, ref)[0] <= (FP64_TOL if precision == "fp64" else SPLIT6_TOL)
@@ -584,3 +589,31 @@ def test_contraction_from_shared_geometry():
     qf = Form("laplace", 3, 2, kernel="quadrature")
     assert capi.lib().ffc_tabulate_tensor_affine(qf.handle, wl.cells, am.data_ptr(), None,
                                                  qf.empty_out(wl.cells).data_ptr()) == capi.FFC_E_INVALID
+
+
+@pytest.mark.parametrize("kind,dim,q", [("elasticity", 3, 2), ("ns", 3, 2), ("elasticity", 2, 3), ("wlaplace", 3, 3)])
+def test_persistent_kernel_computing_its_affine_maps(kind, dim, q):
+    """The 12-wave persistent FP64 kernel that computes each tile's affine map from the
+    coordinates (one tile ahead, no geometry pass) equals the 16-wave kernel reading the
+    geometry pass's maps bit for bit -- single mesh, and as the persistent launch of a batch
+    whose items are cut at ragged sizes -- and the oracle to 1e-12."""
+    require_gpu()
+    n = 40 if dim == 2 else 9
+    wl = meshgen.make_workload(kind, dim, q, n, 61, max_cells=4999)
+    f12 = Form(kind, dim, q, waves=12, persistent=1)
+    f16 = Form(kind, dim, q, waves=16, persistent=1, geometry="pass")
+    assert f12.info["persistent_waves"] == 12 and f12.info["fused_geometry"] == 1
+    assert f16.info["persistent_waves"] == 16 and f16.info["fused_geometry"] == 0
+    a, b = _run(f12, wl), _run(f16, wl)
+    assert np.array_equal(a, b)
+    ref = oracle.tabulate(kind, dim, q, wl.coords, wl.coeffs)
+    assert rel_fro(a, ref)[0] <= FP64_TOL
+    X, C = to_dev(wl.coords), to_dev(wl.coeffs)
+    cuts = [0, 17, 1300, wl.cells]  # items of 17, 1283 and the rest of the cells
+    Xs = [X[:, c0:c1].contiguous() for c0, c1 in zip(cuts, cuts[1:])]
+    Cs = [None if C is None else C[:, c0:c1].contiguous() for c0, c1 in zip(cuts, cuts[1:])]
+    outs = [f12.empty_out(x.shape[1]).fill_(float("nan")) for x in Xs]
+    bt = Batch([f12] * len(Xs), Xs, Cs, outs)
+    bt.run()
+    torch.cuda.synchronize()
+    assert np.array_equal(np.concatenate([o.cpu().numpy() for o in outs]), a)
