@@ -68,10 +68,12 @@ int upload(const std::vector<T>& host, T** dev) {
 
 bool valid_tile(int t) { return t == 16 || t == 32 || t == 64; }
 
-// Element tensors with at least this many entries use the persistent FP64 kernel by
-// default; below it a 16-cell tile carries too little output to pay for the per-tile
-// pipeline (measured: persistent wins at 900 entries, loses at 400 and below).
+// Element tensors with at least this many entries use the persistent FP64 kernel on 16-cell
+// tiles by default; from kPersistentMidEntries on, the 12-wave persistent kernel on tiles of
+// 16, 32 or 64 cells (below it, even a 64-cell tile carries too little output to pay for the
+// per-tile pipeline; measured on MI355X: the tile kernels win at 36 entries and below).
 constexpr int kPersistentMinEntries = 576;
+constexpr int kPersistentMidEntries = 100;
 // The same threshold for the persistent split-BF16 kernel (FP32 output: half the bytes
 // per entry).
 constexpr int kBf16PersistentMinEntries = 256;
@@ -243,6 +245,7 @@ struct ffc_form {
     int64_t amap_cap = 0;
     // persistent FP64 contraction
     int pwaves = 0, pkmax = 0, pgrid = 0, n_zero = 0;
+    int pmt = 1;  // persistent FP64 kernel: cell tiles of 16 * pmt cells
     bool bpersistent = false;  // split modes: persistent BF16 contraction (pwaves, pkmax, pgrid set)
     int ptile = 16;            // its cell tile
     bool fused = false;  // ffc_tabulate_tensor computes the affine map inside the tile kernel
@@ -417,23 +420,62 @@ int ffc_form_create(const ffc_form_desc* desc, ffc_form** out) {
             return rc;
         // persistent workgroups of 12 waves (6 compute, ~168 registers per lane: the kernel then
         // also computes the affine maps) or 16 waves (10 compute, 128 registers, affine maps from
-        // a geometry pass), with up to 24 register-resident k steps per compute wave; the
-        // 16-cell output rows must be stageable in LDS
-        const ffc::LdsPlan pl = ffc::plan_lds(spec.dim, spec.kind, 16, rt.n_I, rt.n_alpha, 0, false, ffc::kLdsBudget);
+        // a geometry pass), with up to 24 register-resident k steps per compute wave; cell tiles
+        // of 16 cells, or (12 waves, tile_cells = 32 or 64) 32 or 64 cells with up to 16 steps;
+        // the output rows of a tile must be stageable in LDS and in the I/O registers
         const bool want_persistent = spec.kind != FFC_CURVED_LAPLACE &&
-            (desc->persistent == 1 || (desc->persistent == 0 && rt.n_I >= kPersistentMinEntries));
-        // default 16 waves: measured faster than 12 on MI355X (equal for elasticity P2 once the
-        // 12-wave kernel's own geometry is counted, slower for the convection form's longer
-        // per-wave MFMA chains); 12 on request
-        if (want_persistent && pl.staged && (desc->tile_cells == 0 || desc->tile_cells == 16)) {
+            (desc->persistent == 1 || (desc->persistent == 0 && rt.n_I >= kPersistentMidEntries));
+        // launch shapes to try, in order: (waves per workgroup, 16-cell blocks per cell tile)
+        std::vector<std::pair<int, int>> shapes;
+        auto waves_ok = [&](int w) { return desc->waves == 0 || desc->waves == w; };
+        const int req_mt = desc->tile_cells == 16 ? 1 : desc->tile_cells == 32 ? 2 : desc->tile_cells == 64 ? 4 : 0;
+        ffc::WaveSchedule ws12;  // the 12-wave schedule (6 compute waves), if have12
+        bool have12 = false;
+        if (want_persistent && desc->persistent == 1 && req_mt > 0) {
+            // as requested; 32- and 64-cell tiles take 12-wave workgroups
+            for (int w : {16, 12})
+                if (waves_ok(w) && (req_mt == 1 || w == 12)) shapes.push_back({w, req_mt});
+        } else if (want_persistent && (desc->persistent == 1 || rt.n_I >= kPersistentMinEntries)) {
+            // large tensors: 16-cell tiles.  16 waves first (the affine maps from a geometry
+            // pass), but 12 (the kernel computes them) for forms with coefficients -- measured
+            // on MI355X: the convection form 10% faster on 12 waves, elasticity 1.5% slower
+            if (desc->tile_cells == 0 || req_mt == 1) {
+                const bool twelve_first = desc->persistent == 0 && rt.n_coeff > 0;
+                for (int w : twelve_first ? std::initializer_list<int>{12, 16} : std::initializer_list<int>{16, 12})
+                    if (waves_ok(w)) shapes.push_back({w, 1});
+            }
+        } else if (want_persistent && desc->tile_cells == 0 && waves_ok(12)) {
+            // mid-size tensors: 12 waves, on the largest cell tile whose staged rows and
+            // schedule fit -- except 16-cell tiles once those carry 48 KiB of output and a
+            // wave takes at most 8 steps (measured on MI355X, 100 to 400 entries: 64-cell
+            // tiles 20-35% faster than the tile kernels at 100 and 144 entries, 32-cell tiles
+            // at 225; at 400 entries 16-cell tiles with 8 steps, 32-cell tiles with 16)
+            ws12 = ffc::make_wave_schedule(t, 12 - ffc::kIoWaves);
+            have12 = true;
+            std::vector<int> fit;
+            for (int m : {4, 2, 1})
+                if (ws12.max_steps <= (m == 1 ? 24 : 16) &&
+                    ffc::persistent_fits(spec.dim, spec.kind, rt.n_I, rt.n_alpha, m, true, nullptr, nullptr, nullptr))
+                    fit.push_back(m);
+            if (!fit.empty()) {
+                int m = fit.front();
+                if (fit.back() == 1 && 16 * 8 * static_cast<int64_t>(rt.n_I) >= 48 * 1024 && ws12.max_steps <= 8)
+                    m = 1;
+                shapes.push_back({12, m});
+            }
+        }
+        if (!shapes.empty()) {
             ffc::WaveSchedule ws;
-            for (int w : {16, 12}) {
-                if (desc->waves != 0 && desc->waves != w) continue;
-                ffc::WaveSchedule cand = ffc::make_wave_schedule(t, w - ffc::kIoWaves);
-                if (cand.max_steps <= 24 && 16 * static_cast<int64_t>(rt.n_I) / 2 <=
-                                                static_cast<int64_t>(ffc::kIoSlots - 1) * 64 * ffc::kIoWaves) {
-                    ws = cand;
+            for (const auto& [w, mt] : shapes) {
+                if (!ffc::persistent_fits(spec.dim, spec.kind, rt.n_I, rt.n_alpha, mt, w == 12, nullptr, nullptr,
+                                          nullptr))
+                    continue;
+                ffc::WaveSchedule cand =
+                    w == 12 && have12 ? ws12 : ffc::make_wave_schedule(t, w - ffc::kIoWaves);
+                if (cand.max_steps <= (mt == 1 ? 24 : 16)) {
+                    ws = std::move(cand);
                     ws.waves = w;
+                    f->pmt = mt;
                     break;
                 }
             }
@@ -594,7 +636,7 @@ int ffc_form_get_info(const ffc_form* form, ffc_form_info* info) {
     info->quad_points = f->quad_npts;
     info->persistent_waves = f->pwaves;
     info->persistent_kmax = f->pkmax;
-    info->tile_cells = f->bpersistent ? f->ptile : f->pwaves ? 16 : f->tile_cells;
+    info->tile_cells = f->bpersistent ? f->ptile : f->pwaves ? 16 * f->pmt : f->tile_cells;
     info->waves = f->waves;
     info->fused_geometry = f->fused ? 1 : 0;
     info->symmetric = f->sym_n ? 1 : 0;
@@ -667,7 +709,8 @@ int contract_chunk(const ffc_form* f, int64_t n, const double* amap, int64_t ast
         e = ffc::launch_contract_bf16_persistent(f->desc.dim, f->desc.kind, f->ptile, f->pgrid, a, f->stream);
     } else if (f->pwaves > 0) {
         ffc::PersistArgs p{f->d_woff, f->d_wave_b, f->d_wave_word, f->d_wave_mask, f->d_zero, f->n_zero};
-        e = ffc::launch_contract_persistent(f->desc.dim, f->desc.kind, f->pkmax, f->pwaves, f->pgrid, a, p, f->stream);
+        e = ffc::launch_contract_persistent(f->desc.dim, f->desc.kind, f->pkmax, f->pwaves, f->pmt, f->pgrid, a, p,
+                                            f->stream);
     }
     if (e == hipErrorInvalidValue)
         e = ffc::launch_contract(f->desc.dim, f->desc.kind, bf16, f->tile_cells, f->waves, a, f->stream);
@@ -720,7 +763,7 @@ int ffc_apply_tensor(const ffc_form* form, int64_t cells, const double* coords, 
     const auto& rt = f->rt;
     if (rt.n_coeff > 0 && !coeffs) return fail(FFC_E_INVALID, "this form needs coefficients (coeffs is NULL)");
     const int d = f->desc.dim, kind = f->desc.kind, n = rt.n;
-    if (f->pwaves > 0) {
+    if (f->pwaves > 0 && f->pmt == 1) {
         hipError_t e = hipSuccess;
         for (int64_t c0 = 0; c0 < cells; c0 += f->amap_cap) {
             const int64_t m = std::min(f->amap_cap, cells - c0);
@@ -791,7 +834,7 @@ int ffc_tabulate_tensor(const ffc_form* form, int64_t cells, const double* coord
         hipError_t e = hipErrorInvalidValue;
         if (f->pwaves > 0 && !bf16) {
             ffc::PersistArgs p{f->d_woff, f->d_wave_b, f->d_wave_word, f->d_wave_mask, f->d_zero, f->n_zero};
-            e = ffc::launch_contract_persistent(d, kind, f->pkmax, f->pwaves, f->pgrid, a, p, f->stream);
+            e = ffc::launch_contract_persistent(d, kind, f->pkmax, f->pwaves, f->pmt, f->pgrid, a, p, f->stream);
         }
         if (e == hipErrorInvalidValue) e = ffc::launch_contract(d, kind, bf16, f->tile_cells, f->waves, a, f->stream);
         if (e != hipSuccess) return hip_fail(e, "contraction kernel launch");
@@ -915,7 +958,6 @@ int ffc_batch_create(int32_t n, const ffc_form* const* forms, const int64_t* cel
         it.nonzero = f->d_nz;
         std::copy(f->gpiece, f->gpiece + 6, it.gpiece);
         const bool aligned = (reinterpret_cast<uintptr_t>(outs[i]) & 15u) == 0;
-        const ffc::LdsPlan p16 = ffc::plan_lds(d, f->desc.kind, 16, f->rt.n_I, f->rt.n_alpha, 0, false, ffc::kLdsBudget);
         if (bf && f->bpersistent && aligned) {
             const ffc::LdsPlan pb =
                 ffc::plan_bf16_persistent(d, f->desc.kind, f->ptile, f->rt.n_I, f->n_tiles, f->kpad, f->n_seg);
@@ -925,17 +967,18 @@ int ffc_batch_create(int32_t n, const ffc_form* const* forms, const int64_t* cel
             it.head_bytes = pb.head_bytes;
             amap_doubles += cells[i] * (1 + d * d);
             pgroups[f].push_back(it);
-        } else if (!bf && (f->pwaves == 12 || f->pwaves == 16) && aligned && p16.staged &&
-                   ffc::persistent_fetch_rows(d, f->desc.kind, f->pwaves == 12) * 16 <= 64 * (f->pwaves - ffc::kIoWaves) &&
-                   p16.stage_bytes + ffc::persistent_head_bytes(d, f->desc.kind, f->pwaves == 12) + p16.g_bytes <=
-                       ffc::kLdsBudget) {
+        } else if (size_t pst = 0, phd = 0;
+                   !bf && (f->pwaves == 12 || f->pwaves == 16) && aligned &&
+                   ffc::persistent_fits(d, f->desc.kind, f->rt.n_I, f->rt.n_alpha, f->pmt, f->pwaves == 12, &pst, &phd,
+                                        nullptr)) {
             // 12-wave schedules: the persistent launch computes each tile's affine map from the
             // coordinates; 16-wave schedules read the maps of a geometry pass
             it.kmax = f->pkmax;
             it.p = ffc::PersistArgs{f->d_woff, f->d_wave_b, f->d_wave_word, f->d_wave_mask, f->d_zero, f->n_zero};
-            it.stage_bytes = p16.stage_bytes;
-            it.head_bytes = ffc::persistent_head_bytes(d, f->desc.kind, f->pwaves == 12);
+            it.stage_bytes = pst;
+            it.head_bytes = phd;
             it.waves = f->pwaves;
+            it.mt = f->pmt;
             if (f->pwaves == 16) amap_doubles += cells[i] * (1 + d * d);
             pgroups[f].push_back(it);
         } else {
@@ -962,15 +1005,16 @@ int ffc_batch_create(int32_t n, const ffc_form* const* forms, const int64_t* cel
         L.dim = L.items[0].dim;
         L.kind = L.items[0].kind;
         L.kmax = L.items[0].kmax;
-        L.mt = bf16 ? L.items[0].mt : 1;
+        L.mt = L.items[0].mt;
         const int ct = 16 * L.mt;
         if (bf16) {
             L.lds = ffc::plan_bf16_persistent(L.dim, L.kind, ct, L.items[0].n_I, L.items[0].n_tiles, L.items[0].kpad,
                                               L.items[0].n_seg).total;
         } else {
-            const ffc::LdsPlan pl =
-                ffc::plan_lds(L.dim, L.kind, 16, L.items[0].n_I, L.items[0].n_alpha, 0, false, ffc::kLdsBudget);
-            L.lds = pl.stage_bytes + L.items[0].head_bytes + pl.g_bytes;
+            size_t total = 0;
+            ffc::persistent_fits(L.dim, L.kind, L.items[0].n_I, L.items[0].n_alpha, L.mt, L.items[0].waves == 12,
+                                 nullptr, nullptr, &total);
+            L.lds = total;
         }
         L.waves = bf16 ? 16 : L.items[0].waves;
         for (auto& it : L.items) {

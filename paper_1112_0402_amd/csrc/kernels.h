@@ -94,11 +94,19 @@ struct PersistArgs {
 constexpr int kIoWaves = 6;
 // 16-byte register slots per I/O lane holding a staged tile (16 rows of up to 912 doubles)
 constexpr int kIoSlots = 20;
+// the same for tiles of 16 * mt cells: 32-cell tiles of up to 408 entries per cell, 64-cell
+// tiles of up to 144 (fewer slots leave the registers that the extra MFMA row blocks need)
+constexpr int persistent_io_slots(int mt) { return mt == 1 ? kIoSlots : mt == 2 ? 18 : 13; }
+// Cell tiles of 16 * mt cells (mt = 1, 2 or 4; 2 and 4 with 16 waves and at most 16 steps).
 // With a.coords set the kernel computes each tile's affine map from the coordinates
-// (a.amap unused); else it reads the affine map from a.amap.
+// (a.amap unused; 12 waves, mt = 1); else it reads the affine map from a.amap.
 // Returns hipErrorInvalidValue when the form does not fit this kernel (caller falls back).
-hipError_t launch_contract_persistent(int dim, int kind, int kmax, int waves, int grid, ContractArgs a,
+hipError_t launch_contract_persistent(int dim, int kind, int kmax, int waves, int mt, int grid, ContractArgs a,
                                       const PersistArgs& p, hipStream_t stream);
+// Whether a form's tiles of 16 * mt cells fit the persistent FP64 kernel (output rows staged in
+// LDS and in the I/O waves' registers), and its LDS plan.
+bool persistent_fits(int dim, int kind, int n_I, int n_alpha, int mt, bool geo, size_t* stage_bytes,
+                     size_t* head_bytes, size_t* total_bytes);
 // Persistent split-BF16 contraction (same pipeline) on cell tiles of 16 or 32 cells:
 // wave w of the 16 - kIoWaves compute waves owns A^0 tiles w, w + 10, ...; their B
 // fragments (kpad / 32 chunks each) stay in registers.
@@ -118,7 +126,7 @@ size_t apply_lds_bytes(int dim, int kind, int tile_cells, int n_I, int n_alpha, 
 hipError_t launch_apply(int dim, int kind, int tile_cells, int waves, ContractArgs a, hipStream_t stream);
 // LDS of the persistent FP64 kernel's map / coefficient / coordinate rows (geo: the kernel
 // computes the affine map), and the rows its compute waves fetch per tile
-size_t persistent_head_bytes(int dim, int kind, bool geo);
+size_t persistent_head_bytes(int dim, int kind, bool geo, int tile_cells);
 int persistent_fetch_rows(int dim, int kind, bool geo);
 hipError_t launch_apply_persistent(int dim, int kind, int kmax, int waves, int grid, ContractArgs a,
                                    const PersistArgs& p, hipStream_t stream);

@@ -49,7 +49,7 @@ hipError_t launch_batch_tiles(const BatchItem* items, const int32_t* unit_item, 
 // above (A^0 fragments loaded once, the pipeline never drained between items; every tile
 // costs the same, so the static split is balanced to one tile).
 
-template <int D, int KIND, int KMAX, int MAXT, bool GEO>
+template <int D, int KIND, int KMAX, int MAXT, bool GEO, int MT>
 __global__ __launch_bounds__(MAXT) void batch_persistent_kernel(const BatchItem* __restrict__ items, int n_items,
                                                                 int64_t total_tiles) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
@@ -64,9 +64,10 @@ __global__ __launch_bounds__(MAXT) void batch_persistent_kernel(const BatchItem*
     A.head_bytes = f.head_bytes;
     const PersistArgs P{as_global(f.p.woff), as_global(f.p.wave_b), as_global(f.p.wave_word),
                         as_global(f.p.wave_mask), as_global(f.p.zero_entries), f.p.n_zero};
-    ItemCursor<16> src{items, n_items, -1, 0, 0, MeshTile{}};
+    ItemCursor<16 * MT> src{items, n_items, -1, 0, 0, MeshTile{}};
     // GEO: the affine map of each tile is computed in the kernel from the items' coordinates
-    persistent_tiles<D, KIND, KMAX, kIoSlots, false, GEO>(A, P, src, blockIdx.x, total_tiles, gridDim.x, smem_raw);
+    persistent_tiles<D, KIND, KMAX, persistent_io_slots(MT), false, GEO, MT>(A, P, src, blockIdx.x, total_tiles,
+                                                                            gridDim.x, smem_raw);
 }
 
 template <int D, int KIND, int NSEG, int KS, int MT>
@@ -114,35 +115,58 @@ static hipError_t launch_batch_bf16_d(int kind, int mt, int ks, const BatchItem*
 }
 
 template <int D, int KIND, int MAXT, bool GEO>
-static hipError_t launch_batch_persistent_kt(int kmax, const BatchItem* items, int n_items, int64_t tiles, int grid,
-                                             size_t lds, hipStream_t s) {
+static hipError_t launch_batch_persistent_kt(int kmax, int mt, const BatchItem* items, int n_items, int64_t tiles,
+                                             int grid, size_t lds, hipStream_t s) {
+    if (mt == 2 || mt == 4) {  // 12 waves, 32- or 64-cell tiles
+        if constexpr (MAXT != 768) {
+            return hipErrorInvalidValue;
+        } else if (mt == 2) {
+            if (kmax <= 8)
+                return launch_lds(batch_persistent_kernel<D, KIND, 8, MAXT, GEO, 2>, grid, MAXT, lds, s, items, n_items,
+                                  tiles);
+            if (kmax <= 16)
+                return launch_lds(batch_persistent_kernel<D, KIND, 16, MAXT, GEO, 2>, grid, MAXT, lds, s, items, n_items,
+                                  tiles);
+            return hipErrorInvalidValue;
+        } else {
+            if (kmax <= 8)
+                return launch_lds(batch_persistent_kernel<D, KIND, 8, MAXT, GEO, 4>, grid, MAXT, lds, s, items, n_items,
+                                  tiles);
+            if (kmax <= 16)
+                return launch_lds(batch_persistent_kernel<D, KIND, 16, MAXT, GEO, 4>, grid, MAXT, lds, s, items, n_items,
+                                  tiles);
+            return hipErrorInvalidValue;
+        }
+    }
     if (kmax <= 8)
-        return launch_lds(batch_persistent_kernel<D, KIND, 8, MAXT, GEO>, grid, MAXT, lds, s, items, n_items, tiles);
+        return launch_lds(batch_persistent_kernel<D, KIND, 8, MAXT, GEO, 1>, grid, MAXT, lds, s, items, n_items, tiles);
     if (kmax <= 16)
-        return launch_lds(batch_persistent_kernel<D, KIND, 16, MAXT, GEO>, grid, MAXT, lds, s, items, n_items, tiles);
-    return launch_lds(batch_persistent_kernel<D, KIND, 24, MAXT, GEO>, grid, MAXT, lds, s, items, n_items, tiles);
+        return launch_lds(batch_persistent_kernel<D, KIND, 16, MAXT, GEO, 1>, grid, MAXT, lds, s, items, n_items, tiles);
+    return launch_lds(batch_persistent_kernel<D, KIND, 24, MAXT, GEO, 1>, grid, MAXT, lds, s, items, n_items, tiles);
 }
 
 template <int D, int KIND>
-static hipError_t launch_batch_persistent_k(int kmax, int waves, const BatchItem* items, int n_items, int64_t tiles,
-                                            int grid, size_t lds, hipStream_t s) {
+static hipError_t launch_batch_persistent_k(int kmax, int waves, int mt, const BatchItem* items, int n_items,
+                                            int64_t tiles, int grid, size_t lds, hipStream_t s) {
     // 12 waves: the launch computes its affine maps (the register budget of the geometry);
     // 16 waves: it reads the maps of the batch's geometry passes
-    return waves == 12 ? launch_batch_persistent_kt<D, KIND, 768, true>(kmax, items, n_items, tiles, grid, lds, s)
-                       : launch_batch_persistent_kt<D, KIND, 1024, false>(kmax, items, n_items, tiles, grid, lds, s);
+    return waves == 12
+               ? launch_batch_persistent_kt<D, KIND, 768, true>(kmax, mt, items, n_items, tiles, grid, lds, s)
+               : launch_batch_persistent_kt<D, KIND, 1024, false>(kmax, mt, items, n_items, tiles, grid, lds, s);
 }
 
 template <int D>
-static hipError_t launch_batch_persistent_d(int kind, int kmax, int waves, const BatchItem* items, int n_items,
+static hipError_t launch_batch_persistent_d(int kind, int kmax, int waves, int mt, const BatchItem* items, int n_items,
                                             int64_t tiles, int grid, size_t lds, hipStream_t s) {
+#define FFC_BATCH_P(K) return launch_batch_persistent_k<D, K>(kmax, waves, mt, items, n_items, tiles, grid, lds, s)
     switch (kind) {
-    case K_MASS: return launch_batch_persistent_k<D, K_MASS>(kmax, waves, items, n_items, tiles, grid, lds, s);
-    case K_LAPLACE: return launch_batch_persistent_k<D, K_LAPLACE>(kmax, waves, items, n_items, tiles, grid, lds, s);
-    case K_WLAPLACE: return launch_batch_persistent_k<D, K_WLAPLACE>(kmax, waves, items, n_items, tiles, grid, lds, s);
-    case K_ELASTICITY:
-        return launch_batch_persistent_k<D, K_ELASTICITY>(kmax, waves, items, n_items, tiles, grid, lds, s);
-    default: return launch_batch_persistent_k<D, K_NS>(kmax, waves, items, n_items, tiles, grid, lds, s);
+    case K_MASS: FFC_BATCH_P(K_MASS);
+    case K_LAPLACE: FFC_BATCH_P(K_LAPLACE);
+    case K_WLAPLACE: FFC_BATCH_P(K_WLAPLACE);
+    case K_ELASTICITY: FFC_BATCH_P(K_ELASTICITY);
+    default: FFC_BATCH_P(K_NS);
     }
+#undef FFC_BATCH_P
 }
 
 hipError_t launch_batch_persistent(int dim, int kind, int kmax, int nseg, int mt, int waves, const BatchItem* items,
@@ -156,8 +180,8 @@ hipError_t launch_batch_persistent(int dim, int kind, int kmax, int nseg, int mt
         return dim == 2 ? launch_batch_bf16_d<2, 6>(kind, mt, kmax, items, n_items, tiles, grid, lds, stream)
                         : launch_batch_bf16_d<3, 6>(kind, mt, kmax, items, n_items, tiles, grid, lds, stream);
     if (waves != 12 && waves != 16) return hipErrorInvalidValue;
-    return dim == 2 ? launch_batch_persistent_d<2>(kind, kmax, waves, items, n_items, tiles, grid, lds, stream)
-                    : launch_batch_persistent_d<3>(kind, kmax, waves, items, n_items, tiles, grid, lds, stream);
+    return dim == 2 ? launch_batch_persistent_d<2>(kind, kmax, waves, mt, items, n_items, tiles, grid, lds, stream)
+                    : launch_batch_persistent_d<3>(kind, kmax, waves, mt, items, n_items, tiles, grid, lds, stream);
 }
 
 }  // namespace ffc

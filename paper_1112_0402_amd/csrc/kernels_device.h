@@ -582,17 +582,24 @@ __device__ __forceinline__ double reference_vertex(int v, int k) { return v == k
 // trip through HBM): coordinates are prefetched two tiles ahead, staged in LDS at the top of
 // the next iteration, and turned into the following tile's map by the last compute wave
 // after its MFMA steps -- while the I/O waves store -- into the second of two map blocks.
-template <int D, int KIND, int KMAX, int IOS, bool ACT = false, bool GEO = false, class Src>
+// MT: cell tiles of 16*MT cells (MT row blocks of the MFMA per register-resident B fragment),
+// for element tensors small enough that a 16-cell tile would carry too little output per
+// pass of the pipeline.
+template <int D, int KIND, int KMAX, int IOS, bool ACT = false, bool GEO = false, int MT = 1, class Src>
 __device__ __forceinline__ void persistent_tiles(const ContractArgs& A, const PersistArgs& P, Src& src, int64_t ct,
                                                  const int64_t ct_end, const int64_t step, unsigned char* smem_raw) {
     using FT = FormTraits<KIND, D>;
-    constexpr int CT = 16;
+    constexpr int CT = 16 * MT;
+    static_assert(!(ACT && MT > 1), "the operator action runs 16-cell tiles");
     constexpr int NA = FT::n_alpha;
     constexpr int NC = FT::n_coeff;
     constexpr int GS = NA | 1;
     constexpr int ROWS = 1 + D * D + NC;
     constexpr int XR = (D + 1) * D;  // coordinate rows (GEO)
     static_assert(!(ACT && GEO), "the operator action reads a precomputed affine map");
+    // values each fetching thread prefetches per tile (at least 6 compute waves fetch)
+    constexpr int FROWS = GEO ? NC + XR : ROWS;
+    constexpr int FR = (FROWS * CT + 383) / 384;
     // One register file, two uses (the compiler cannot see that a wave only ever takes one
     // role, so separate arrays would both count): a compute lane keeps the B fragment of
     // step s in R[2s], R[2s+1] and its packed word in R[2*KMAX + s]; an I/O lane keeps
@@ -652,11 +659,13 @@ __device__ __forceinline__ void persistent_tiles(const ContractArgs& A, const Pe
     // MFMA and each store
     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
 
-    // thread r*CT + c (r < ROWS) fetches row r of cell c: affine map, then coefficients.
-    // GEO: threads [0, NC*CT) fetch coefficient row r = tid / CT, threads [NC*CT, (NC+XR)*CT)
-    // coordinate row r = tid / CT - NC (all in compute waves, which never store)
-    auto fetch = [&](const MeshTile& t) -> double {
-        const int r = tid / CT, c = tid - (tid / CT) * CT;
+    // value i = r*CT + c (r < ROWS) of a tile is row r of cell c: affine map, then
+    // coefficients; GEO: values [0, NC*CT) are coefficient rows, [NC*CT, (NC+XR)*CT) coordinate
+    // rows.  Thread tid fetches values tid + f * (64 * compute waves), f < FR (compute waves
+    // only: they never store)
+    const int nft = 64 * n_compute;
+    auto fetch_i = [&](const MeshTile& t, int i) -> double {
+        const int r = i / CT, c = i - (i / CT) * CT;
         const int64_t cell = t.ct * CT + c;
         if constexpr (GEO) {
             if (r < NC) return cell < t.cells ? t.coeffs[r * t.cstride + cell] : 0.0;
@@ -666,8 +675,10 @@ __device__ __forceinline__ void persistent_tiles(const ContractArgs& A, const Pe
         if (cell >= t.cells) return r == 0 ? 1.0 : 0.0;
         return r < 1 + D * D ? t.amap[r * t.astride + cell] : t.coeffs[(r - 1 - D * D) * t.cstride + cell];
     };
-    const bool coef_thread = tid < NC * CT;
-    const bool coord_thread = GEO && !coef_thread && tid < (NC + XR) * CT;
+    auto fidx = [&](int f) { return tid + f * nft; };
+    auto is_coef = [&](int i) { return tid < io_begin && i < NC * CT; };
+    auto is_coord = [&](int i) { return GEO && tid < io_begin && i >= NC * CT && i < (NC + XR) * CT; };
+    auto is_row = [&](int i) { return tid < io_begin && i < ROWS * CT; };
     Src srcx = src;  // GEO: a cursor for the coordinates, which run one tile ahead
     // output run of a tile: start and length in doubles (element tensors, or y)
     const int nd = A.n_dof;
@@ -686,7 +697,9 @@ __device__ __forceinline__ void persistent_tiles(const ContractArgs& A, const Pe
     };
     double px0 = 0.0, px1 = 0.0;
     int xbuf = 0;
-    double pre = 0.0;
+    double pre[FR];
+#pragma unroll
+    for (int f = 0; f < FR; ++f) pre[f] = 0.0;
     double* cur_out = nullptr;
     int64_t cur_n = 0;
     if (ct < ct_end) {
@@ -695,20 +708,28 @@ __device__ __forceinline__ void persistent_tiles(const ContractArgs& A, const Pe
         if constexpr (GEO) {
             // the first tile's map, built before the loop; the second tile's coordinates in flight
             const MeshTile tx = srcx.at(ct);
-            if (coef_thread) pre = fetch(t);
-            if (coord_thread) {
-                const int i = tid - NC * CT;
-                xc[(i / CT) * AS + i % CT] = fetch(tx);
+#pragma unroll
+            for (int f = 0; f < FR; ++f) {
+                const int i = fidx(f);
+                if (is_coef(i)) pre[f] = fetch_i(t, i);
+                if (is_coord(i)) {
+                    const int k = i - NC * CT;
+                    xc[(k / CT) * AS + k % CT] = fetch_i(tx, i);
+                }
             }
             __syncthreads();
             if (tid < CT) tile_affine_map<D>(xc, AS, tid, am);
             if (ct + step < ct_end) {
                 const MeshTile tx1 = srcx.at(ct + step);
-                if (coord_thread) pre = fetch(tx1);
+#pragma unroll
+                for (int f = 0; f < FR; ++f)
+                    if (is_coord(fidx(f))) pre[f] = fetch_i(tx1, fidx(f));
             }
             __syncthreads();
         } else {
-            if (tid < ROWS * CT) pre = fetch(t);
+#pragma unroll
+            for (int f = 0; f < FR; ++f)
+                if (is_row(fidx(f))) pre[f] = fetch_i(t, fidx(f));
         }
         if (ACT && tid >= io_begin) {
             px0 = fetchx(t, io_lane);
@@ -733,54 +754,72 @@ __device__ __forceinline__ void persistent_tiles(const ContractArgs& A, const Pe
         if ((io_n & 1) && io_lane == 0)
             o[io_n - 1] = __builtin_bit_cast(double, u32x2{R[4 * (IOS - 1)], R[4 * (IOS - 1) + 1]});
     };
+    // the staged entries no step writes (zero A^0 rows) stay zero from tile to tile: nothing
+    // else is ever written there
+    for (int i = tid; i < CT * P.n_zero && tid < io_begin; i += io_begin) {
+        const int c = i / P.n_zero;
+        st[c * nI + P.zero_entries[i - c * P.n_zero]] = 0.0;
+    }
+    // The fetching below sits in a branch on the wave (uniform): a wait for the previous
+    // prefetch that the compiler places in code every wave runs would make the I/O waves wait
+    // for their stores, i.e. for the write-out of the previous tile to reach memory, once per
+    // tile.
+    const bool fetcher = wave < n_compute;
     for (; ct < ct_end; ct += step) {
         const bool more = ct + step < ct_end;
         double* nxt_out = nullptr;
         int64_t nxt_n = 0;
-        if constexpr (GEO) {
-            // this tile's coefficients, the next tile's coordinates
-            if (coef_thread) cf[(tid / CT) * AS + tid % CT] = pre;
-            if (coord_thread) {
-                const int i = tid - NC * CT;
-                xc[(i / CT) * AS + i % CT] = pre;
+        MeshTile tn{};
+        if (more) {
+            tn = src.at(ct + step);
+            out_run(tn, nxt_out, nxt_n);
+        }
+        if (fetcher) {
+#pragma unroll
+            for (int f = 0; f < FR; ++f) {
+                const int i = fidx(f);
+                if constexpr (GEO) {
+                    // this tile's coefficients, the next tile's coordinates
+                    if (is_coef(i)) cf[(i / CT) * AS + i % CT] = pre[f];
+                    if (is_coord(i)) {
+                        const int k = i - NC * CT;
+                        xc[(k / CT) * AS + k % CT] = pre[f];
+                    }
+                } else {
+                    if (is_row(i)) am[(i / CT) * AS + i % CT] = pre[f];
+                }
             }
-        } else {
-            if (tid < ROWS * CT) am[(tid / CT) * AS + tid % CT] = pre;
+            if (more) {
+#pragma unroll
+                for (int f = 0; f < FR; ++f) {
+                    const int i = fidx(f);
+                    if (GEO ? is_coef(i) : is_row(i)) pre[f] = fetch_i(tn, i);
+                }
+            }
+            if constexpr (GEO) {
+                if (ct + 2 * step < ct_end) {
+                    const MeshTile tx = srcx.at(ct + 2 * step);
+#pragma unroll
+                    for (int f = 0; f < FR; ++f)
+                        if (is_coord(fidx(f))) pre[f] = fetch_i(tx, fidx(f));
+                }
+            }
         }
         if constexpr (ACT) {
             if (tid >= io_begin) {
                 double* xb = xs + xbuf * CT * nd;
                 if (io_lane < CT * nd) xb[io_lane] = px0;
                 if (io_lane + 64 * kIoWaves < CT * nd) xb[io_lane + 64 * kIoWaves] = px1;
-            }
-        }
-        if (more) {
-            const MeshTile t = src.at(ct + step);
-            out_run(t, nxt_out, nxt_n);
-            if constexpr (GEO) {
-                if (coef_thread) pre = fetch(t);
-            } else {
-                if (tid < ROWS * CT) pre = fetch(t);
-            }
-            if (ACT && tid >= io_begin) {
-                px0 = fetchx(t, io_lane);
-                px1 = fetchx(t, io_lane + 64 * kIoWaves);
-            }
-        }
-        if constexpr (GEO) {
-            if (ct + 2 * step < ct_end) {
-                const MeshTile tx = srcx.at(ct + 2 * step);
-                if (coord_thread) pre = fetch(tx);
+                if (more) {
+                    px0 = fetchx(tn, io_lane);
+                    px1 = fetchx(tn, io_lane + 64 * kIoWaves);
+                }
             }
         }
         lds_barrier();
         for (int i = tid; i < CT * NA; i += blockDim.x) {
             const int c = i / NA, al = i - c * NA;
             Gs[c * GS + al] = g_entry<KIND, D>(am, cf, AS, c, al);
-        }
-        for (int i = tid; i < CT * P.n_zero && tid < io_begin; i += io_begin) {
-            const int c = i / P.n_zero;
-            st[c * nI + P.zero_entries[i - c * P.n_zero]] = 0.0;
         }
         lds_barrier();
         if (tid >= io_begin) {
@@ -791,29 +830,43 @@ __device__ __forceinline__ void persistent_tiles(const ContractArgs& A, const Pe
             // loop, which would cost 4 registers a step
             int nIs = nI;
             asm volatile("" : "+s"(nIs));
-            d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+            d4 acc[MT];
+#pragma unroll
+            for (int m = 0; m < MT; ++m) acc[m] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int s = 0; s < KMAX; ++s) {
                 if (s < ns) {
                     const uint32_t word = R[2 * KMAX + s];
                     const double bv = __builtin_bit_cast(double, u32x2{R[2 * s], R[2 * s + 1]});
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(grow[word & 0xffu], bv, acc, 0, 0, 0);
+                    double av[MT];
+#pragma unroll
+                    for (int m = 0; m < MT; ++m) av[m] = grow[m * 16 * GS + (word & 0xffu)];
+#pragma unroll
+                    for (int m = 0; m < MT; ++m)
+                        acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[m], bv, acc[m], 0, 0, 0);
                     if ((endmask >> s) & 1u) {
                         const int e = static_cast<int>((word >> 8) & 0xfffu) - 1;
                         if (e >= 0) {
 #pragma unroll
-                            for (int i = 0; i < 4; ++i) st[(i * 4 + lk) * nIs + e] = acc[i];
+                            for (int m = 0; m < MT; ++m)
+#pragma unroll
+                                for (int i = 0; i < 4; ++i) st[(m * 16 + i * 4 + lk) * nIs + e] = acc[m][i];
                         }
                         // symmetric forms: the transposed entry (none on the diagonal)
                         const int e2 = static_cast<int>(word >> 20) - 1;
                         if (e2 >= 0) {
 #pragma unroll
-                            for (int i = 0; i < 4; ++i) st[(i * 4 + lk) * nIs + e2] = acc[i];
+                            for (int m = 0; m < MT; ++m)
+#pragma unroll
+                                for (int i = 0; i < 4; ++i) st[(m * 16 + i * 4 + lk) * nIs + e2] = acc[m][i];
                         }
-                        acc = d4{0.0, 0.0, 0.0, 0.0};
-                        // keeps the reset inside this branch (no select on every step that
-                        // would wait for each MFMA's result)
-                        asm volatile("" : "+v"(acc));
+#pragma unroll
+                        for (int m = 0; m < MT; ++m) {
+                            acc[m] = d4{0.0, 0.0, 0.0, 0.0};
+                            // keeps the reset inside this branch (no select on every step that
+                            // would wait for each MFMA's result)
+                            asm volatile("" : "+v"(acc[m]));
+                        }
                     }
                 }
             }

@@ -617,3 +617,50 @@ def test_persistent_kernel_computing_its_affine_maps(kind, dim, q):
     bt.run()
     torch.cuda.synchronize()
     assert np.array_equal(np.concatenate([o.cpu().numpy() for o in outs]), a)
+
+
+# mid-size forms (100 to 400 entries) whose 12-wave schedules fit tiles of 32 cells and, up to
+# 144 entries, 64 cells (the staged rows of a tile must fit the I/O registers)
+MT_FORMS = [("laplace", 3, 2), ("mass", 3, 3), ("laplace", 3, 3), ("laplace", 2, 4), ("elasticity", 2, 2),
+            ("wlaplace", 3, 2), ("ns", 2, 2), ("mass", 2, 4)]
+MT_EXPECTED = {("laplace", 3, 2): (32, 64), ("mass", 3, 3): (32,), ("laplace", 3, 3): (32,),
+               ("laplace", 2, 4): (32,), ("elasticity", 2, 2): (32, 64), ("wlaplace", 3, 2): (32, 64),
+               ("ns", 2, 2): (32, 64), ("mass", 2, 4): (32,)}
+
+
+@pytest.mark.parametrize("kind,dim,q", MT_FORMS)
+def test_persistent_kernel_with_32_and_64_cell_tiles(kind, dim, q):
+    """Persistent FP64 tiles of 32 and 64 cells (two or four 16-cell blocks per MFMA pass over
+    the register-resident operands) run each 16-cell block through the same steps as 16-cell
+    tiles: bit for bit equal to them, single mesh and as a batch cut at ragged sizes, and to
+    the oracle to 1e-12.  A form whose schedule or staged rows do not fit takes another
+    launch, which the form info reports."""
+    require_gpu()
+    n = 40 if dim == 2 else 9
+    wl = meshgen.make_workload(kind, dim, q, n, 71, max_cells=4999)
+    base = Form(kind, dim, q, waves=12, persistent=1)
+    assert base.info["persistent_waves"] == 12 and base.info["tile_cells"] == 16
+    a = _run(base, wl)
+    ref = oracle.tabulate(kind, dim, q, wl.coords, wl.coeffs)
+    assert rel_fro(a, ref)[0] <= FP64_TOL
+    X, C = to_dev(wl.coords), to_dev(wl.coeffs)
+    taken = []
+    for tc in (32, 64):
+        f = Form(kind, dim, q, waves=12, persistent=1, tile_cells=tc)
+        say(f"[mt] {kind} d={dim} q={q} tile_cells={tc}: n_I {f.info['n_entries']} -> persistent "
+            f"{f.info['persistent_waves']} waves, {f.info['tile_cells']}-cell tiles, kmax {f.info['persistent_kmax']}")
+        b = _run(f, wl)
+        assert rel_fro(b, ref)[0] <= FP64_TOL
+        if f.info["persistent_waves"] != 12 or f.info["tile_cells"] != tc:
+            continue
+        taken.append(tc)
+        assert f.info["fused_geometry"] == 1
+        assert np.array_equal(a, b)
+        cuts = [0, 33, 1000, 1001, wl.cells]  # items of 33, 967, 1 and the rest of the cells
+        Xs = [X[:, c0:c1].contiguous() for c0, c1 in zip(cuts, cuts[1:])]
+        Cs = [None if C is None else C[:, c0:c1].contiguous() for c0, c1 in zip(cuts, cuts[1:])]
+        outs = [f.empty_out(x.shape[1]).fill_(float("nan")) for x in Xs]
+        Batch([f] * len(Xs), Xs, Cs, outs).run()
+        torch.cuda.synchronize()
+        assert np.array_equal(np.concatenate([o.cpu().numpy() for o in outs]), a)
+    assert tuple(taken) == MT_EXPECTED.get((kind, dim, q), ()), taken
