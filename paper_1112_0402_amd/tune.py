@@ -27,6 +27,11 @@ CANDIDATES_FP64 = (
     # one launch: affine map computed per cell tile
     {"kernel": "tensor", "tile_cells": 64, "waves": 4, "persistent": -1, "tile_window": 16, "geometry": "fused"},
     {"kernel": "tensor", "tile_cells": 32, "waves": 8, "persistent": -1, "tile_window": 16, "geometry": "fused"},
+    # persistent, 12 waves (A^0 fragments in registers, affine map computed one tile ahead),
+    # cell tiles of 16, 32 and 64 cells (where they fit; else the library's fallback launch)
+    {"kernel": "tensor", "tile_cells": 16, "waves": 12, "persistent": 1, "tile_window": 0},
+    {"kernel": "tensor", "tile_cells": 32, "waves": 12, "persistent": 1, "tile_window": 0},
+    {"kernel": "tensor", "tile_cells": 64, "waves": 12, "persistent": 1, "tile_window": 0},
     {"kernel": "quadrature"},  # last: the analytic rule's alternative
 )
 CANDIDATES_SPLIT = (
