@@ -528,12 +528,14 @@ int ffc_form_create(const ffc_form_desc* desc, ffc_form** out) {
         if ((rc = upload(t.b, &f->d_bb)) || (rc = upload(t.nonzero, &f->d_nz))) return rc;
         // persistent split-BF16 kernel when the form fits it (B fragments of at most 16
         // steps per wave in registers, a staged tile in the I/O lanes' registers)
-        // (cell tiles of 32, else 16 cells: the largest that fits)
+        // (cell tiles: the largest that fits among 64, 32, 16 cells for 6 products, 32 and 16
+        // for 3 -- measured on MI355X: 64-cell tiles 4% faster than 32 for x6 on the weighted
+        // Laplacian P3, 7% slower for x3; 64 for x3 on request)
         if (desc->kernel == FFC_KERNEL_TENSOR &&
             (desc->persistent == 1 || (desc->persistent == 0 && rt.n_I >= kBf16PersistentMinEntries)) &&
             (desc->waves == 0 || desc->waves == 16)) {
-            for (int ct : {32, 16}) {
-                if (desc->tile_cells != 0 && desc->tile_cells != ct) continue;
+            for (int ct : {64, 32, 16}) {
+                if (desc->tile_cells != ct && (desc->tile_cells != 0 || (ct == 64 && t.n_seg != 6))) continue;
                 if (!ffc::plan_bf16_persistent(spec.dim, spec.kind, ct, rt.n_I, t.n_tiles, t.kpad, t.n_seg).staged)
                     continue;
                 hipDeviceProp_t prop;
@@ -554,14 +556,6 @@ int ffc_form_create(const ffc_form_desc* desc, ffc_form** out) {
         f->amap_cap = spec.kind == FFC_CURVED_LAPLACE ? ((int64_t(1) << 21) * (1 + spec.dim * spec.dim) / rows + 63) / 64 * 64
                                                      : int64_t(1) << 21;
         const size_t bytes = static_cast<size_t>(f->amap_cap) * rows * sizeof(double);
-        // fused: the contraction computes the affine map itself -- the per-tile kernels in LDS
-        // per tile, the persistent FP64 kernel one tile ahead (the split-BF16 persistent kernel
-        // keeps the pass)
-        f->fused = desc->geometry != FFC_GEOMETRY_PASS && !f->bpersistent && (f->pwaves == 0 || f->pwaves == 12);
-        // the workspace serves the geometry pass, and the persistent operator action
-        const bool need_workspace = !f->fused || f->pwaves > 0;
-        if (need_workspace && hipMalloc(reinterpret_cast<void**>(&f->d_amap), bytes) != hipSuccess)
-            return fail(FFC_E_NOMEM, "hipMalloc failed for the geometry workspace");
         // default launch shape when the persistent kernel does not apply
         const bool bf = desc->precision != FFC_FP64;
         auto plan = [&](int ct) {
@@ -613,6 +607,19 @@ int ffc_form_create(const ffc_form_desc* desc, ffc_form** out) {
         }
         const size_t lds = ffc::contract_lds_bytes(spec.dim, spec.kind, f->tile_cells, rt.n_I, rt.n_alpha, f->kpad, bf);
         if (lds > ffc::kLdsBudget) return fail(FFC_E_UNSUPPORTED, "tile does not fit the 160 KiB LDS of a CU");
+        // fused: the contraction computes the affine map itself -- the per-tile kernels in LDS
+        // per tile, the persistent FP64 kernel one tile ahead (the split-BF16 persistent kernel
+        // keeps the pass).  By default not for FP64 tile launches of 16-cell tiles (large
+        // tensors the persistent kernel does not take): measured on MI355X, the pass is 17-20%
+        // faster there (Laplacian P4 on tetrahedra, 2^18 and 2^19 cells)
+        const bool pass_default = !bf && f->pwaves == 0 && f->tile_cells == 16 && rt.n_I >= kPersistentMinEntries;
+        f->fused = desc->geometry == FFC_GEOMETRY_FUSED ||
+                   (desc->geometry == 0 && !pass_default && !f->bpersistent && (f->pwaves == 0 || f->pwaves == 12));
+        if (f->bpersistent || f->pwaves == 16) f->fused = false;
+        // the workspace serves the geometry pass, and the persistent operator action
+        const bool need_workspace = !f->fused || f->pwaves > 0;
+        if (need_workspace && hipMalloc(reinterpret_cast<void**>(&f->d_amap), bytes) != hipSuccess)
+            return fail(FFC_E_NOMEM, "hipMalloc failed for the geometry workspace");
     }
     *out = f.release();
     return FFC_OK;

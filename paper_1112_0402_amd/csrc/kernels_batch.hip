@@ -102,8 +102,9 @@ template <int D, int NSEG>
 static hipError_t launch_batch_bf16_d(int kind, int mt, int ks, const BatchItem* items, int n_items, int64_t tiles,
                                       int grid, size_t lds, hipStream_t s) {
 #define FFC_BATCH_BF16_KIND(K)                                                                \
-    return mt == 1 ? launch_batch_bf16_m<D, K, NSEG, 1>(ks, items, n_items, tiles, grid, lds, s) \
-                   : launch_batch_bf16_m<D, K, NSEG, 2>(ks, items, n_items, tiles, grid, lds, s)
+    return mt == 1   ? launch_batch_bf16_m<D, K, NSEG, 1>(ks, items, n_items, tiles, grid, lds, s) \
+           : mt == 2 ? launch_batch_bf16_m<D, K, NSEG, 2>(ks, items, n_items, tiles, grid, lds, s) \
+                     : launch_batch_bf16_m<D, K, NSEG, 4>(ks, items, n_items, tiles, grid, lds, s)
     switch (kind) {
     case K_MASS: FFC_BATCH_BF16_KIND(K_MASS);
     case K_LAPLACE: FFC_BATCH_BF16_KIND(K_LAPLACE);

@@ -942,7 +942,7 @@ __device__ __forceinline__ void persistent_tiles(const ContractArgs& A, const Pe
 template <int MT>
 struct Bf16PersistTraits {
     // 16-byte register slots per I/O lane holding one staged tile (CT rows of FP32)
-    static constexpr int ios = MT == 1 ? 10 : 12;
+    static constexpr int ios = MT == 1 ? 10 : MT == 2 ? 12 : 17;
 };
 
 template <int D, int KIND, int NSEG, int KS, int MT, class Src>

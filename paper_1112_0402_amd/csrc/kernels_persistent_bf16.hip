@@ -27,8 +27,9 @@ static hipError_t launch_bf16_persistent_m(int ks, int grid, size_t lds, const C
 template <int D, int KIND, int NSEG>
 static hipError_t launch_bf16_persistent_k(int mt, int ks, int grid, size_t lds, const ContractArgs& a,
                                            hipStream_t s) {
-    return mt == 1 ? launch_bf16_persistent_m<D, KIND, NSEG, 1>(ks, grid, lds, a, s)
-                   : launch_bf16_persistent_m<D, KIND, NSEG, 2>(ks, grid, lds, a, s);
+    return mt == 1   ? launch_bf16_persistent_m<D, KIND, NSEG, 1>(ks, grid, lds, a, s)
+           : mt == 2 ? launch_bf16_persistent_m<D, KIND, NSEG, 2>(ks, grid, lds, a, s)
+                     : launch_bf16_persistent_m<D, KIND, NSEG, 4>(ks, grid, lds, a, s);
 }
 
 template <int D, int NSEG>
@@ -53,9 +54,11 @@ int bf16_persistent_steps(int n_tiles, int kpad) {
 
 LdsPlan plan_bf16_persistent(int dim, int kind, int tile_cells, int n_I, int n_tiles, int kpad, int n_seg) {
     LdsPlan p = plan_lds(dim, kind, tile_cells, n_I, 0, kpad, true, kLdsBudget);
-    const int ios = tile_cells == 16 ? Bf16PersistTraits<1>::ios : Bf16PersistTraits<2>::ios;
+    const int ios = tile_cells == 16   ? Bf16PersistTraits<1>::ios
+                    : tile_cells == 32 ? Bf16PersistTraits<2>::ios
+                                       : Bf16PersistTraits<4>::ios;
     const int64_t units = (tile_cells * static_cast<int64_t>(n_I) + 3) / 4;
-    const bool fits = (tile_cells == 16 || tile_cells == 32) && p.staged &&
+    const bool fits = (tile_cells == 16 || tile_cells == 32 || tile_cells == 64) && p.staged &&
                       bf16_persistent_steps(n_tiles, kpad) <= bf16_persistent_max_steps(tile_cells, n_seg) &&
                       units <= static_cast<int64_t>(ios) * 64 * kIoWaves &&
                       (1 + dim * dim + n_coeff_of(dim, kind)) * tile_cells <= 1024;

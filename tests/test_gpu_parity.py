@@ -88,11 +88,12 @@ def test_fp64_launch_shapes(tile_cells, waves):
 @pytest.mark.parametrize("kind,dim,q", [("wlaplace", 3, 3), ("mass", 3, 3), ("laplace", 3, 3), ("laplace", 2, 4),
                                         ("wlaplace", 2, 4), ("ns", 2, 2), ("elasticity", 2, 3), ("mass", 2, 1)])
 @pytest.mark.parametrize("precision", ["bf16x3", "bf16x6"])
-@pytest.mark.parametrize("tile_cells", [16, 32])
+@pytest.mark.parametrize("tile_cells", [16, 32, 64])
 def test_persistent_split_bf16_matches_tile_kernel(kind, dim, q, precision, tile_cells):
     """The persistent split-BF16 kernel (B fragments in registers, I/O waves) against the
     per-tile kernel: same pieces and the same K order, so equal bit for bit, over a mesh of
-    several tiles per workgroup with a ragged tail; and the oracle on sampled cells."""
+    several tiles per workgroup with a ragged tail, single mesh and as a batch cut at ragged
+    sizes; and the oracle on sampled cells."""
     require_gpu()
     n = 70 if dim == 2 else 12
     wl = meshgen.make_workload(kind, dim, q, n, 77, max_cells=9999)
@@ -103,6 +104,14 @@ def test_persistent_split_bf16_matches_tile_kernel(kind, dim, q, precision, tile
     assert not tile.info["persistent_waves"]
     a, b = _run(pers, wl), _run(tile, wl)
     assert np.array_equal(a, b)
+    X, C = to_dev(wl.coords), to_dev(wl.coeffs)
+    cuts = [0, 65, 3000, wl.cells]
+    Xs = [X[:, c0:c1].contiguous() for c0, c1 in zip(cuts, cuts[1:])]
+    Cs = [None if C is None else C[:, c0:c1].contiguous() for c0, c1 in zip(cuts, cuts[1:])]
+    outs = [pers.empty_out(x.shape[1]).fill_(float("nan")) for x in Xs]
+    Batch([pers] * len(Xs), Xs, Cs, outs).run()
+    torch.cuda.synchronize()
+    assert np.array_equal(np.concatenate([o.cpu().numpy() for o in outs]), a)
     idx = _sample(wl.cells, 64, 5)
     ref = oracle.tabulate(kind, dim, q, np.ascontiguousarray(wl.coords[:, idx]),
                           None if wl.coeffs is None else np.ascontiguousarray(wl.coeffs[:, idx]))
