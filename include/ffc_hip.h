@@ -134,7 +134,9 @@ typedef struct {
     int32_t degree;      /* Lagrange degree q of u and v: 1..4 (vector forms: 1..3) */
     int32_t precision;   /* ffc_precision */
     int32_t kernel;      /* ffc_kernel */
-    int32_t tile_cells;  /* cells per workgroup tile of the contraction: 0 = default, else 16, 32 or 64 */
+    int32_t tile_cells;  /* cells per workgroup tile of the contraction: 0 = default, else 16, 32 or 64
+                            (with persistent = 1: the persistent kernel's cell tile; 32 and 64
+                            in FP64 take 12 waves) */
     int32_t waves;       /* waves per workgroup of the contraction: 0 = default, else 1, 2, 4, 8,
                             12 or 16 (the persistent FP64 kernel: 12 = 6 compute + 6 I/O
                             waves, which also computes the affine maps; 16 = 10 + 6 with a
@@ -145,9 +147,10 @@ typedef struct {
                             A^0 columns) inside windows of that many consecutive entries;
                             -1 = clustered over all entries.  Ignored by the other kernels. */
     int32_t persistent;  /* tensor kernel: 0 = auto (persistent workgroups with the A^0 tiles
-                            in registers for element tensors of at least 576 entries in FP64,
-                            256 in the split modes, when they fit), 1 = persistent whenever
-                            it fits, -1 = one workgroup per cell tile */
+                            in registers for element tensors of at least 100 entries in FP64
+                            -- 12 waves on 16-, 32- or 64-cell tiles below 576 entries, 16-cell
+                            tiles from 576 -- and 256 in the split modes, when they fit),
+                            1 = persistent whenever it fits, -1 = one workgroup per cell tile */
     int32_t geometry;    /* tensor kernel, ffc_tabulate_tensor: where the affine map is
                             computed.  FFC_GEOMETRY_PASS = a geometry kernel writes it to a
                             form-owned workspace that the contraction reads;
@@ -155,7 +158,9 @@ typedef struct {
                             coordinates (one launch, no workspace round trip): the per-tile
                             kernels per cell tile in LDS, the persistent FP64 kernel one tile
                             ahead of the contraction.  The persistent split-BF16 kernel always
-                            uses the pass.  0 = default = fused where available. */
+                            uses the pass, and so does the 16-wave persistent FP64 kernel.
+                            0 = default = fused where available, except FP64 tile launches of
+                            16-cell tiles (large tensors), which take the pass. */
     int32_t symmetry;    /* FP64 tensor kernel: 0 = auto (for the symmetric forms -- all but
                             FFC_NS_CONVECTION -- compute only the entries i1 <= i2 on the
                             matrix cores and write each also at (i2, i1): half the MFMA
