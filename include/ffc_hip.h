@@ -63,7 +63,9 @@ typedef enum {
     FFC_E_INVALID = -1,     /* bad argument (NULL pointer, negative size, wrong mode) */
     FFC_E_UNSUPPORTED = -2, /* form / dimension / degree / precision not supported   */
     FFC_E_DEVICE = -3,      /* HIP runtime error, or no usable gfx950 device        */
-    FFC_E_NOMEM = -5        /* host or device allocation failed (create calls only) */
+    FFC_E_DEGENERATE = -4,  /* ffc_check_cells found degenerate cells                */
+    FFC_E_NOMEM = -5        /* host or device allocation failed (create calls, and
+                               the validation call's counters)                       */
 } ffc_status;
 
 /* Forms (v = test, u = trial):
@@ -264,6 +266,20 @@ int ffc_apply_tensor(const ffc_form* form, int64_t cells, const double* coords, 
  * 1 + a*d + b = g_ab = (J^{-1})_ab.  Asynchronous on `stream` (hipStream_t, NULL =
  * default). */
 int ffc_compute_geometry(int32_t dim, int64_t cells, const double* coords, double* affine_map, void* stream);
+
+/* Validation mode, off the hot path (which never checks the cells): the affine map of a
+ * cell (Sec. 3.2, the map from the reference cell) must be invertible for its element
+ * tensor to exist.  Counts the cells whose map is degenerate, |det J| <= tol * h^d with h
+ * the cell's longest edge (the ratio of its volume to that of the cube on that edge, so
+ * tol is scale-free; tol = 0 flags det J == 0 exactly), or whose det J is not finite.
+ * coords: device SoA [(d+1)*d][cells] as for ffc_tabulate_tensor.  count, first (host, each
+ * may be NULL): the number of degenerate cells and the smallest such index (-1 if none).
+ * Returns FFC_E_DEGENERATE when any cell is degenerate, FFC_OK otherwise; FFC_E_INVALID
+ * for cells < 0, tol < 0 or not finite, coords NULL with cells > 0; FFC_E_UNSUPPORTED for
+ * dim not 2 or 3.  Allocates two device words per call and waits for `stream` (hipStream_t,
+ * NULL = default) before returning. */
+int ffc_check_cells(int32_t dim, int64_t cells, const double* coords, double tol, int64_t* count, int64_t* first,
+                    void* stream);
 
 /* Mixed batches (many meshes of uneven size, mixed forms and degrees; the level-3 BLAS
  * batching of Sec. 3.5 taken across meshes).  A batch is built from `n` (form, cells,

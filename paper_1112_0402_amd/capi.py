@@ -23,6 +23,7 @@ FFC_OK = 0
 FFC_E_INVALID = -1
 FFC_E_UNSUPPORTED = -2
 FFC_E_DEVICE = -3
+FFC_E_DEGENERATE = -4
 FFC_E_NOMEM = -5
 
 
@@ -84,6 +85,7 @@ def lib():
     L.ffc_tabulate_tensor_affine.argtypes = [vp, i64, vp, vp, vp]
     L.ffc_apply_tensor.argtypes = [vp, i64, vp, vp, vp, vp]
     L.ffc_compute_geometry.argtypes = [i32, i64, vp, vp, vp]
+    L.ffc_check_cells.argtypes = [i32, i64, vp, ctypes.c_double, ctypes.POINTER(i64), ctypes.POINTER(i64), vp]
     L.ffc_batch_create.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(i64), ctypes.POINTER(vp),
                                    ctypes.POINTER(vp), ctypes.POINTER(vp), vp, ctypes.POINTER(vp)]
     L.ffc_batch_run.argtypes = [vp]
@@ -113,7 +115,7 @@ def lib():
     for name in ("ffc_compile_reference_tensor", "ffc_form_create", "ffc_form_get_info", "ffc_form_select",
                  "ffc_tabulate_tensor",
                  "ffc_tabulate_tensor_affine", "ffc_apply_tensor",
-                 "ffc_compute_geometry", "ffc_batch_create", "ffc_batch_run", "ffc_batch_info"):
+                 "ffc_compute_geometry", "ffc_check_cells", "ffc_batch_create", "ffc_batch_run", "ffc_batch_info"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L

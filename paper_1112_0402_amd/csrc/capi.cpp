@@ -675,6 +675,39 @@ int ffc_compute_geometry(int32_t dim, int64_t cells, const double* coords, doubl
     return FFC_OK;
 }
 
+int ffc_check_cells(int32_t dim, int64_t cells, const double* coords, double tol, int64_t* count, int64_t* first,
+                    void* stream) {
+    if (count) *count = 0;
+    if (first) *first = -1;
+    if (dim != 2 && dim != 3) return fail(FFC_E_UNSUPPORTED, "dim must be 2 or 3");
+    if (cells < 0) return fail(FFC_E_INVALID, "cells < 0");
+    if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(FFC_E_INVALID, "tol must be finite and >= 0");
+    if (cells == 0) return FFC_OK;
+    if (!coords) return fail(FFC_E_INVALID, "coords is NULL");
+    int dev;
+    int rc = check_device(&dev);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    unsigned long long* d_out = nullptr;
+    if (hipMalloc(reinterpret_cast<void**>(&d_out), 2 * sizeof(unsigned long long)) != hipSuccess)
+        return fail(FFC_E_NOMEM, "hipMalloc failed for the validation counters");
+    unsigned long long h_out[2] = {0ull, ~0ull};
+    hipError_t e = ffc::launch_degenerate_cells(dim, cells, coords, tol, d_out, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(h_out, d_out, sizeof(h_out), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(d_out);
+    if (e != hipSuccess) return hip_fail(e, "degenerate-cell check");
+    if (count) *count = static_cast<int64_t>(h_out[0]);
+    if (first) *first = h_out[0] ? static_cast<int64_t>(h_out[1]) : -1;
+    if (h_out[0]) {
+        char msg[160];
+        std::snprintf(msg, sizeof(msg), "%llu degenerate cell(s) (|det J| <= tol * h^d), the first at index %llu",
+                      h_out[0], h_out[1]);
+        return fail(FFC_E_DEGENERATE, msg);
+    }
+    return FFC_OK;
+}
+
 namespace {
 // contraction of cells [0, n) whose affine map sits at amap with row stride astride
 ffc::ContractArgs contract_args(const ffc_form* f, int64_t n, const double* amap, int64_t astride,

@@ -67,6 +67,10 @@ struct QuadArgs {
     int cells_per_block;
 };
 
+// out[0] = number of cells with |det J| <= tol * h^D (h = longest edge) or det J not finite,
+// out[1] = the smallest such index (~0 if none); out: 2 device words
+hipError_t launch_degenerate_cells(int dim, int64_t cells, const double* coords, double tol, unsigned long long* out,
+                                   hipStream_t stream);
 hipError_t launch_geometry(int dim, int64_t cells, const double* coords, int64_t cstride, double* amap,
                            int64_t astride, hipStream_t stream);
 // Cells with P2 geometry: coords SoA [n_geo * dim][cstride] (P2 nodes in the dof order), grad

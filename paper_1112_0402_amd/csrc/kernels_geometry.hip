@@ -80,6 +80,65 @@ hipError_t launch_curved_geometry(int dim, int64_t cells, const double* coords, 
     return hipGetLastError();
 }
 
+// Validation of the affine maps, off the hot path: cell c is degenerate when |det J| <=
+// tol * h^D, h its longest edge (scale-free: the ratio is the cell's volume against that of a
+// cube on its longest edge), or when det J is not finite.  out[0] counts degenerate cells,
+// out[1] holds the smallest degenerate index: per wave a ballot, then one lane (the first
+// degenerate one) updates both with global atomics.
+template <int D>
+__global__ __launch_bounds__(256) void degenerate_cells_kernel(int64_t cells, const double* __restrict__ coords,
+                                                              double tol, unsigned long long* __restrict__ out) {
+    const int64_t c = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    bool bad = false;
+    if (c < cells) {
+        double x[D + 1][D];
+#pragma unroll
+        for (int v = 0; v <= D; ++v)
+#pragma unroll
+            for (int k = 0; k < D; ++k) x[v][k] = coords[(v * D + k) * cells + c];
+        double det, g[D][D];
+        affine_map<D>(x, det, g);
+        double h2 = 0.0;
+#pragma unroll
+        for (int v = 0; v <= D; ++v)
+#pragma unroll
+            for (int w = v + 1; w <= D; ++w) {
+                double e2 = 0.0;
+#pragma unroll
+                for (int k = 0; k < D; ++k) e2 = fma(x[w][k] - x[v][k], x[w][k] - x[v][k], e2);
+                h2 = fmax(h2, e2);
+            }
+        const double h = sqrt(h2);
+        double bound = tol;
+#pragma unroll
+        for (int k = 0; k < D; ++k) bound *= h;
+        bad = !(fabs(det) > bound);  // also true for a NaN det
+    }
+    const unsigned long long m = __ballot(bad);
+    if (m != 0ull && static_cast<int>(threadIdx.x & 63u) == __builtin_ctzll(m)) {
+        atomicAdd(&out[0], static_cast<unsigned long long>(__popcll(m)));
+        atomicMin(&out[1], static_cast<unsigned long long>(c));
+    }
+}
+
+__global__ void degenerate_init_kernel(unsigned long long* out) {
+    out[0] = 0ull;
+    out[1] = ~0ull;
+}
+
+hipError_t launch_degenerate_cells(int dim, int64_t cells, const double* coords, double tol, unsigned long long* out,
+                                   hipStream_t stream) {
+    degenerate_init_kernel<<<1, 1, 0, stream>>>(out);
+    if (cells > 0) {
+        const unsigned grid = static_cast<unsigned>((cells + 255) / 256);
+        if (dim == 2)
+            degenerate_cells_kernel<2><<<grid, 256, 0, stream>>>(cells, coords, tol, out);
+        else
+            degenerate_cells_kernel<3><<<grid, 256, 0, stream>>>(cells, coords, tol, out);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_geometry(int dim, int64_t cells, const double* coords, int64_t cstride, double* amap,
                            int64_t astride, hipStream_t stream) {
     if (cells <= 0) return hipSuccess;

@@ -137,6 +137,19 @@ class Form:
             pass
 
 
+def check_cells(coords: torch.Tensor, dim: int, tol: float = 0.0, stream=None):
+    """Validation mode: (number of degenerate cells, smallest such index or -1); a cell is
+    degenerate when |det J| <= tol * h^d (h its longest edge) or det J is not finite.  Does
+    not raise for degenerate cells (the C call returns FFC_E_DEGENERATE for them)."""
+    _check_tensor("coords", coords, torch.float64)
+    count, first = ctypes.c_int64(), ctypes.c_int64()
+    rc = capi.lib().ffc_check_cells(dim, coords.shape[1], _ptr(coords), float(tol), ctypes.byref(count),
+                                    ctypes.byref(first), _stream_handle(stream))
+    if rc not in (capi.FFC_OK, capi.FFC_E_DEGENERATE):
+        capi.check(rc)
+    return count.value, first.value
+
+
 def compute_geometry(coords: torch.Tensor, dim: int, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     """Affine map per cell: [1 + d*d, cells] (det J, then g_ab = (J^{-1})_ab)."""
     _check_tensor("coords", coords, torch.float64)

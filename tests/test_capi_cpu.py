@@ -133,6 +133,17 @@ def test_argument_validation_without_device():
     assert L.ffc_compute_geometry(5, 10, None, None, None) == capi.FFC_E_UNSUPPORTED
     assert L.ffc_compute_geometry(2, -1, None, None, None) == capi.FFC_E_INVALID
     assert L.ffc_compute_geometry(2, 0, None, None, None) == capi.FFC_OK
+    # the validation call: argument errors before any device work; nothing to check -> OK
+    cnt, first = ctypes.c_int64(7), ctypes.c_int64(7)
+    assert L.ffc_check_cells(4, 10, None, 0.0, ctypes.byref(cnt), ctypes.byref(first), None) == capi.FFC_E_UNSUPPORTED
+    assert (cnt.value, first.value) == (0, -1)
+    assert L.ffc_check_cells(3, -1, None, 0.0, None, None, None) == capi.FFC_E_INVALID
+    assert L.ffc_check_cells(3, 10, None, -1e-9, None, None, None) == capi.FFC_E_INVALID
+    assert L.ffc_check_cells(3, 10, None, float("nan"), None, None, None) == capi.FFC_E_INVALID
+    assert L.ffc_check_cells(3, 10, None, 0.0, None, None, None) == capi.FFC_E_INVALID
+    assert b"coords" in L.ffc_last_error()
+    assert L.ffc_check_cells(2, 0, None, 0.0, ctypes.byref(cnt), ctypes.byref(first), None) == capi.FFC_OK
+    assert (cnt.value, first.value) == (0, -1)
 
 
 def test_form_create_without_gpu_fails_loudly():
