@@ -511,8 +511,8 @@ int ffc_form_create(const ffc_form_desc* desc, ffc_form** out) {
                     (rc = upload(wword, &f->d_wave_word)) || (rc = upload(wmask, &f->d_wave_mask)) ||
                     (rc = upload(ws.zero_entries, &f->d_zero)))
                     return rc;
-                // one 1024-thread workgroup per CU: at ~128 registers per lane two would
-                // not be resident together
+                // one workgroup per CU: 1024 threads at ~128 registers per lane, or 768 at
+                // ~168, fill the register file
                 hipDeviceProp_t prop;
                 HIP_TRY(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
                 f->pgrid = prop.multiProcessorCount;
@@ -567,9 +567,19 @@ int ffc_form_create(const ffc_form_desc* desc, ffc_form** out) {
                 // small FP64 tensors (measured on MI355X): 64-cell tiles staged in at most
                 // 40 KiB of LDS (several workgroups per CU); else 32-cell tiles staged in at
                 // most 80 KiB (two per CU); else 64-cell tiles written directly (consecutive
-                // output rows per MFMA tile keep those writes in whole 128-byte runs)
+                // output rows per MFMA tile keep those writes in whole 128-byte runs).  Tiny
+                // tensors take one- or two-wave workgroups: a tile's latency chain (coordinate
+                // load, geometry, MFMA, staged write) is then overlapped by more resident
+                // workgroups -- 32-cell tiles of one wave up to 16 entries (P1 forms 1.3-1.9x
+                // faster than 64-cell tiles of 4 waves), 64-cell tiles of two waves up to 36
+                // (1.2x)
                 const ffc::LdsPlan p64 = plan(64), p32 = plan(32);
-                if (p64.staged && p64.total <= 40 * 1024) {
+                const bool tiny = spec.kind != FFC_CURVED_LAPLACE;
+                if (tiny && rt.n_I <= 16 && p32.staged) {
+                    f->tile_cells = 32, dw = 1;
+                } else if (tiny && rt.n_I <= 36 && p64.staged && p64.total <= 40 * 1024) {
+                    f->tile_cells = 64, dw = 2;
+                } else if (p64.staged && p64.total <= 40 * 1024) {
                     f->tile_cells = 64, dw = 4;
                 } else if (p32.staged && p32.total <= 80 * 1024) {
                     f->tile_cells = 32, dw = 8;
@@ -1066,7 +1076,7 @@ int ffc_batch_create(int32_t n, const ffc_form* const* forms, const int64_t* cel
                 amap_off += it.cells * (1 + it.dim * it.dim);
             }
         }
-        // one 1024-thread workgroup per CU (the register file holds one)
+        // one workgroup per CU (768 or 1024 threads: the register file holds one)
         L.grid = static_cast<int>(std::min<int64_t>(prop.multiProcessorCount, L.units));
         b->launches.push_back(std::move(L));
     }

@@ -14,7 +14,7 @@
 //                      per-cell matrix-vector product into a matrix-matrix product, Sec. 3.5)
 //  contract_bf16       the same with G and A^0 split into BF16 pieces, concatenated along
 //                      K, on v_mfma_f32_16x16x32_bf16 with FP32 accumulation
-//  contract_*_persistent  one 1024-thread workgroup per CU walking cell tiles: each compute
+//  contract_*_persistent  one workgroup per CU (12 or 16 waves) walking cell tiles: each compute
 //                      wave keeps its share of the A^0 tiles in registers, dedicated I/O
 //                      waves write the staged rows of one tile during the next tile's MFMA
 //                      steps (also the operator action y_K = A^K x_K, and mixed batches)
@@ -534,14 +534,28 @@ struct ItemCursor {
     int n, idx;
     int64_t begin, end;
     MeshTile base;
+    // the item's fields go to scalar registers: kept in vector registers, the compiler
+    // reloaded them from the item array at every tile, and the wait for that load made the
+    // I/O waves wait for their own stores once per tile
+    static __device__ __forceinline__ int64_t uniform(int64_t v) {
+        const uint64_t u = static_cast<uint64_t>(v);
+        const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(u));
+        const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(u >> 32));
+        return static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo);
+    }
+    template <class T>
+    static __device__ __forceinline__ T* uniform_ptr(T* p) {
+        return as_global(reinterpret_cast<T*>(uniform(static_cast<int64_t>(reinterpret_cast<uintptr_t>(p)))));
+    }
     __device__ __forceinline__ MeshTile at(int64_t g) {
         while (g >= end && idx + 1 < n) {
             ++idx;
             const BatchItem& it = items[idx];
-            begin = it.unit_begin;
-            end = begin + (it.cells + CT - 1) / CT;
-            base = MeshTile{as_global(it.amap), it.cells, as_global(it.coeffs), it.cells,
-                            as_global(static_cast<double*>(it.out)), it.cells, 0, as_global(it.coords)};
+            begin = uniform(it.unit_begin);
+            const int64_t cells = uniform(it.cells);
+            end = begin + (cells + CT - 1) / CT;
+            base = MeshTile{uniform_ptr(it.amap), cells, uniform_ptr(it.coeffs), cells,
+                            uniform_ptr(static_cast<double*>(it.out)), cells, 0, uniform_ptr(it.coords)};
         }
         MeshTile t = base;
         t.ct = g - begin;

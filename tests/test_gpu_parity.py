@@ -76,6 +76,35 @@ def test_fp64_parity_small(kind, dim, q, kernel):
     assert emax <= FP64_TOL
 
 
+@pytest.mark.parametrize("kind,dim,q", [("laplace", 2, 1), ("mass", 3, 1), ("laplace", 3, 1), ("laplace", 2, 2),
+                                        ("elasticity", 2, 1), ("ns", 2, 1), ("wlaplace", 3, 1), ("piola", 3, 1),
+                                        ("nedelec", 3, 1)])
+def test_tiny_tensor_tile_shapes(kind, dim, q):
+    """Element tensors of at most 36 entries default to one- or two-wave workgroups (32-cell
+    tiles of one wave up to 16 entries, 64-cell tiles of two up to 36); every such shape
+    runs the same MFMA steps per tile as the 4-wave shape, so all are bitwise equal to it,
+    and match the oracle to 1e-12, on a mesh with a ragged last tile."""
+    require_gpu()
+    wl = meshgen.make_workload(kind, dim, q, 40 if dim == 2 else 9, 83, max_cells=4321)
+    f0 = Form(kind, dim, q)
+    n_I = f0.info["n_entries"]
+    if n_I <= 16:
+        assert (f0.info["tile_cells"], f0.info["waves"]) == (32, 1)
+    elif n_I <= 36:
+        assert (f0.info["tile_cells"], f0.info["waves"]) == (64, 2)
+    if kind == "piola":
+        ref = oracle.piola_mass(dim, wl.coords)
+    elif kind == "nedelec":
+        ref = oracle.nedelec_mass(dim, wl.coords)
+    else:
+        ref = oracle.tabulate(kind, dim, q, wl.coords, wl.coeffs)
+    base = _run(Form(kind, dim, q, tile_cells=64, waves=4), wl)
+    assert rel_fro(base, ref)[0] <= FP64_TOL
+    for tc, w in [(0, 0), (32, 1), (64, 1), (64, 2), (16, 1), (32, 2)]:
+        got = _run(Form(kind, dim, q, tile_cells=tc, waves=w), wl)
+        assert np.array_equal(got, base), (tc, w)
+
+
 @pytest.mark.parametrize("tile_cells,waves", [(16, 1), (32, 2), (64, 8), (16, 4)])
 def test_fp64_launch_shapes(tile_cells, waves):
     require_gpu()
