@@ -151,7 +151,8 @@ typedef struct {
     int32_t persistent;  /* tensor kernel: 0 = auto (persistent workgroups with the A^0 tiles
                             in registers for element tensors of at least 100 entries in FP64
                             -- 12 waves on 16-, 32- or 64-cell tiles below 576 entries, 16-cell
-                            tiles from 576 -- and 256 in the split modes, when they fit),
+                            tiles from 576 -- and 144 in the split modes, 100 for forms with
+                            coefficients, when they fit),
                             1 = persistent whenever it fits, -1 = one workgroup per cell tile */
     int32_t geometry;    /* tensor kernel, ffc_tabulate_tensor: where the affine map is
                             computed.  FFC_GEOMETRY_PASS = a geometry kernel writes it to a

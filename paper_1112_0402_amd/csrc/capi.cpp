@@ -74,9 +74,13 @@ bool valid_tile(int t) { return t == 16 || t == 32 || t == 64; }
 // per-tile pipeline; measured on MI355X: the tile kernels win at 36 entries and below).
 constexpr int kPersistentMinEntries = 576;
 constexpr int kPersistentMidEntries = 100;
-// The same threshold for the persistent split-BF16 kernel (FP32 output: half the bytes
-// per entry).
-constexpr int kBf16PersistentMinEntries = 256;
+// The persistent split-BF16 kernel (FP32 output: half the bytes per entry; it reads the
+// affine maps of a geometry pass) by default from 144 entries, or from 100 for forms with
+// coefficients (measured on MI355X at ~10^6 cells: 64-cell persistent tiles 5-19% faster
+// than the tile kernels there, 3-11% slower for the 100-entry Laplacian and mass matrices
+// on tetrahedra, whose geometry-pass traffic is large against their output).
+constexpr int kBf16PersistentMinEntries = 144;
+constexpr int kBf16PersistentMinEntriesCoeff = 100;
 bool valid_waves(int w) { return w == 1 || w == 2 || w == 4 || w == 8 || w == 12 || w == 16; }
 
 int check_desc(const ffc_form_desc* d, ffc::FormSpec* spec) {
@@ -528,14 +532,17 @@ int ffc_form_create(const ffc_form_desc* desc, ffc_form** out) {
         if ((rc = upload(t.b, &f->d_bb)) || (rc = upload(t.nonzero, &f->d_nz))) return rc;
         // persistent split-BF16 kernel when the form fits it (B fragments of at most 16
         // steps per wave in registers, a staged tile in the I/O lanes' registers)
-        // (cell tiles: the largest that fits among 64, 32, 16 cells for 6 products, 32 and 16
-        // for 3 -- measured on MI355X: 64-cell tiles 4% faster than 32 for x6 on the weighted
-        // Laplacian P3, 7% slower for x3; 64 for x3 on request)
-        if (desc->kernel == FFC_KERNEL_TENSOR &&
-            (desc->persistent == 1 || (desc->persistent == 0 && rt.n_I >= kBf16PersistentMinEntries)) &&
-            (desc->waves == 0 || desc->waves == 16)) {
+        // (cell tiles: the largest that fits among 64, 32, 16 cells -- except 3 products on
+        // tensors of 256 entries and more, which take 32 and 16 (measured on MI355X: 64-cell
+        // tiles 4% faster than 32 for x6 on the weighted Laplacian P3, 7% slower for x3, and
+        // faster for both below 256 entries); 64 there on request)
+        const bool bwant = desc->persistent == 1 ||
+                           (desc->persistent == 0 && (rt.n_I >= kBf16PersistentMinEntries ||
+                                                      (rt.n_I >= kBf16PersistentMinEntriesCoeff && rt.n_coeff > 0)));
+        if (desc->kernel == FFC_KERNEL_TENSOR && bwant && (desc->waves == 0 || desc->waves == 16)) {
             for (int ct : {64, 32, 16}) {
-                if (desc->tile_cells != ct && (desc->tile_cells != 0 || (ct == 64 && t.n_seg != 6))) continue;
+                const bool skip64 = ct == 64 && t.n_seg != 6 && rt.n_I >= 256;
+                if (desc->tile_cells != ct && (desc->tile_cells != 0 || skip64)) continue;
                 if (!ffc::plan_bf16_persistent(spec.dim, spec.kind, ct, rt.n_I, t.n_tiles, t.kpad, t.n_seg).staged)
                     continue;
                 hipDeviceProp_t prop;
