@@ -280,6 +280,10 @@ __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(
 __host__ __device__ inline int n_coeff_of(int dim, int kind) {
     return kind == K_WLAPLACE ? dim + 1 : kind == K_NS ? dim * (dim + 1) : 0;
 }
+// Regions of 32 KB and more are written with non-temporal stores (streamed to HBM without
+// allocating in the caches): measured on MI355X 20% faster for 16-cell tiles of large
+// tensors (Laplacian P4 on tetrahedra, convection P2 in split x6), ~5% slower for the small
+// regions of tiny tensors, which keep ordinary stores.
 template <typename T>
 __device__ __forceinline__ void write_region(const T* __restrict__ st, T* __restrict__ out, int64_t n) {
     constexpr int V = 16 / sizeof(T);
@@ -287,7 +291,11 @@ __device__ __forceinline__ void write_region(const T* __restrict__ st, T* __rest
     const int64_t nv = n / V;
     const vec* s = reinterpret_cast<const vec*>(st);
     vec* o = reinterpret_cast<vec*>(out);
-    for (int64_t i = threadIdx.x; i < nv; i += blockDim.x) o[i] = s[i];
+    if (n * static_cast<int64_t>(sizeof(T)) >= 32768) {
+        for (int64_t i = threadIdx.x; i < nv; i += blockDim.x) __builtin_nontemporal_store(s[i], &o[i]);
+    } else {
+        for (int64_t i = threadIdx.x; i < nv; i += blockDim.x) o[i] = s[i];
+    }
     for (int64_t i = nv * V + threadIdx.x; i < n; i += blockDim.x) out[i] = st[i];
 }
 // ----------------------------------------------------------- FP64 contraction ---
@@ -754,7 +762,9 @@ __device__ __forceinline__ void persistent_tiles(const ContractArgs& A, const Pe
     double* io_out = nullptr;
     int64_t io_n = 0;
     // I/O lanes: store the tile held in R (slot j -> 16-byte pair io_lane + j * 64 * kIoWaves;
-    // an odd last value rides in the last slot of lane 0, which the host keeps unused)
+    // an odd last value rides in the last slot of lane 0, which the host keeps unused), with
+    // non-temporal stores (measured on MI355X: 7-20% faster for the mid-size tensors, neutral
+    // for elasticity P2)
     auto io_store = [&]() {
         double* o = io_out;
         const int64_t nv = io_n / 2;
@@ -762,7 +772,9 @@ __device__ __forceinline__ void persistent_tiles(const ContractArgs& A, const Pe
         d2v* ov = reinterpret_cast<d2v*>(o) + io_lane;
 #pragma unroll
         for (int j = 0; j < IOS; ++j) {
-            if (j < jn) *ov = __builtin_bit_cast(d2v, u32x4{R[4 * j], R[4 * j + 1], R[4 * j + 2], R[4 * j + 3]});
+            if (j < jn)
+                __builtin_nontemporal_store(__builtin_bit_cast(d2v, u32x4{R[4 * j], R[4 * j + 1], R[4 * j + 2], R[4 * j + 3]}),
+                                            ov);
             ov += 64 * kIoWaves;
         }
         if ((io_n & 1) && io_lane == 0)
@@ -1052,7 +1064,7 @@ __device__ __forceinline__ void persistent_tiles_bf16(const ContractArgs& A, Src
         u32x4* ov = reinterpret_cast<u32x4*>(io_out) + io_lane;
 #pragma unroll
         for (int j = 0; j < IOS; ++j) {
-            if (j < jn) *ov = u32x4{R[4 * j], R[4 * j + 1], R[4 * j + 2], R[4 * j + 3]};
+            if (j < jn) __builtin_nontemporal_store(u32x4{R[4 * j], R[4 * j + 1], R[4 * j + 2], R[4 * j + 3]}, ov);
             ov += 64 * kIoWaves;
         }
     };
