@@ -440,11 +440,12 @@ int ffc_form_create(const ffc_form_desc* desc, ffc_form** out) {
             for (int w : {16, 12})
                 if (waves_ok(w) && (req_mt == 1 || w == 12)) shapes.push_back({w, req_mt});
         } else if (want_persistent && (desc->persistent == 1 || rt.n_I >= kPersistentMinEntries)) {
-            // large tensors: 16-cell tiles.  16 waves first (the affine maps from a geometry
-            // pass), but 12 (the kernel computes them) for forms with coefficients -- measured
-            // on MI355X: the convection form 10% faster on 12 waves, elasticity 1.5% slower
+            // large tensors: 16-cell tiles.  12 waves first (the kernel computes the affine
+            // maps: one launch), else 16 (the maps from a geometry pass) -- measured on MI355X
+            // with the non-temporal write-out: elasticity P2 step 1.07 vs 1.09 ms, the
+            // convection form 10% faster on 12 waves; 16 first when persistent = 1 is asked for
             if (desc->tile_cells == 0 || req_mt == 1) {
-                const bool twelve_first = desc->persistent == 0 && rt.n_coeff > 0;
+                const bool twelve_first = desc->persistent == 0;
                 for (int w : twelve_first ? std::initializer_list<int>{12, 16} : std::initializer_list<int>{16, 12})
                     if (waves_ok(w)) shapes.push_back({w, 1});
             }
