@@ -253,6 +253,9 @@ struct ffc_form {
     bool bpersistent = false;  // split modes: persistent BF16 contraction (pwaves, pkmax, pgrid set)
     int ptile = 16;            // its cell tile
     bool fused = false;  // ffc_tabulate_tensor computes the affine map inside the tile kernel
+    // FP64: tabulations take the 16-cell tile kernel although a persistent schedule exists
+    // (which the operator action and batches keep using)
+    bool tab_tile = false;
     int sym_n = 0;       // FP64 symmetric tiles: element dofs
     int n_alpha_form = 0;  // |alpha| and nnz of A^0 as the form defines them (before the fold)
     int64_t nnz_form = 0;
@@ -570,6 +573,15 @@ int ffc_form_create(const ffc_form_desc* desc, ffc_form** out) {
             return ffc::plan_lds(spec.dim, spec.kind, ct, rt.n_I, rt.n_alpha, f->kpad, bf, ffc::kLdsBudget);
         };
         int dw = 0;  // default waves
+        // Large symmetric tensors without coefficients (Laplacian, elasticity; >= 576 entries):
+        // with non-temporal stores for the staged rows, 16-cell tiles of one workgroup each
+        // after a geometry pass measured faster than the persistent kernel on MI355X
+        // (elasticity P2, 750k cells: step 1.031 vs 1.054-1.078 ms; 9% in the sweep at 2^18 and
+        // 2^19 cells), so tabulation takes them; the persistent schedule stays for the action
+        if (!bf && f->pwaves > 0 && desc->persistent == 0 && desc->tile_cells == 0 && desc->waves == 0 &&
+            (spec.kind == FFC_LAPLACE || spec.kind == FFC_ELASTICITY) && rt.n_I >= kPersistentMinEntries &&
+            plan(16).staged)
+            f->tab_tile = true;
         if (f->tile_cells == 0) {
             if (!bf && rt.n_I < kPersistentMinEntries) {
                 // small FP64 tensors (measured on MI355X): 64-cell tiles staged in at most
@@ -630,7 +642,8 @@ int ffc_form_create(const ffc_form_desc* desc, ffc_form** out) {
         // keeps the pass).  By default not for FP64 tile launches of 16-cell tiles (large
         // tensors the persistent kernel does not take): measured on MI355X, the pass is 17-20%
         // faster there (Laplacian P4 on tetrahedra, 2^18 and 2^19 cells)
-        const bool pass_default = !bf && f->pwaves == 0 && f->tile_cells == 16 && rt.n_I >= kPersistentMinEntries;
+        const bool pass_default =
+            !bf && (f->pwaves == 0 || f->tab_tile) && f->tile_cells == 16 && rt.n_I >= kPersistentMinEntries;
         f->fused = desc->geometry == FFC_GEOMETRY_FUSED ||
                    (desc->geometry == 0 && !pass_default && !f->bpersistent && (f->pwaves == 0 || f->pwaves == 12));
         if (f->bpersistent || f->pwaves == 16) f->fused = false;
@@ -659,9 +672,9 @@ int ffc_form_get_info(const ffc_form* form, ffc_form_info* info) {
     info->mfma_k_per_tile = f->mfma_k;
     info->n_tiles = f->n_tiles;
     info->quad_points = f->quad_npts;
-    info->persistent_waves = f->pwaves;
+    info->persistent_waves = f->tab_tile ? 0 : f->pwaves;
     info->persistent_kmax = f->pkmax;
-    info->tile_cells = f->bpersistent ? f->ptile : f->pwaves ? 16 * f->pmt : f->tile_cells;
+    info->tile_cells = f->bpersistent ? f->ptile : (f->pwaves && !f->tab_tile) ? 16 * f->pmt : f->tile_cells;
     info->waves = f->waves;
     info->fused_geometry = f->fused ? 1 : 0;
     info->symmetric = f->sym_n ? 1 : 0;
@@ -765,7 +778,7 @@ int contract_chunk(const ffc_form* f, int64_t n, const double* amap, int64_t ast
     hipError_t e = hipErrorInvalidValue;
     if (f->bpersistent) {
         e = ffc::launch_contract_bf16_persistent(f->desc.dim, f->desc.kind, f->ptile, f->pgrid, a, f->stream);
-    } else if (f->pwaves > 0) {
+    } else if (f->pwaves > 0 && !f->tab_tile) {
         ffc::PersistArgs p{f->d_woff, f->d_wave_b, f->d_wave_word, f->d_wave_mask, f->d_zero, f->n_zero};
         e = ffc::launch_contract_persistent(f->desc.dim, f->desc.kind, f->pkmax, f->pwaves, f->pmt, f->pgrid, a, p,
                                             f->stream);
@@ -890,7 +903,7 @@ int ffc_tabulate_tensor(const ffc_form* form, int64_t cells, const double* coord
         ffc::ContractArgs a = contract_args(f, cells, nullptr, 0, coeffs, cells, out);
         a.coords = coords;
         hipError_t e = hipErrorInvalidValue;
-        if (f->pwaves > 0 && !bf16) {
+        if (f->pwaves > 0 && !bf16 && !f->tab_tile) {
             ffc::PersistArgs p{f->d_woff, f->d_wave_b, f->d_wave_word, f->d_wave_mask, f->d_zero, f->n_zero};
             e = ffc::launch_contract_persistent(d, kind, f->pkmax, f->pwaves, f->pmt, f->pgrid, a, p, f->stream);
         }
