@@ -573,16 +573,19 @@ int ffc_form_create(const ffc_form_desc* desc, ffc_form** out) {
             return ffc::plan_lds(spec.dim, spec.kind, ct, rt.n_I, rt.n_alpha, f->kpad, bf, ffc::kLdsBudget);
         };
         int dw = 0;  // default waves
-        // Large symmetric tensors without coefficients (Laplacian, elasticity; >= 576 entries):
-        // with non-temporal stores for the staged rows, 16-cell tiles of one workgroup each
-        // after a geometry pass measured faster than the persistent kernel on MI355X
-        // (elasticity P2, 750k cells: step 1.031 vs 1.054-1.078 ms; 9% in the sweep at 2^18 and
-        // 2^19 cells), so tabulation takes them; the persistent schedule stays for the action
+        // Tensors of 400 entries and more without coefficients: with non-temporal stores for
+        // the staged rows, 16-cell tiles of one workgroup each after a geometry pass measured
+        // faster than the persistent kernel on MI355X (elasticity P2 on tetrahedra, 750k
+        // cells: step 1.02-1.03 vs 1.06 ms; Laplacian P3 on tetrahedra 0.569 vs 0.667 ms,
+        // elasticity P3 on triangles 0.520 vs 0.578, mass P3 0.610 vs 0.639 at ~10^6 cells;
+        // not at 225 entries, nor for the forms with coefficients), so tabulation takes them;
+        // the persistent schedule stays for the operator action and batches
         if (!bf && f->pwaves > 0 && desc->persistent == 0 && desc->tile_cells == 0 && desc->waves == 0 &&
-            (spec.kind == FFC_LAPLACE || spec.kind == FFC_ELASTICITY) && rt.n_I >= kPersistentMinEntries &&
-            plan(16).staged)
+            rt.n_coeff == 0 && rt.n_I >= 400 && plan(16).staged)
             f->tab_tile = true;
-        if (f->tile_cells == 0) {
+        if (f->tab_tile) {
+            f->tile_cells = 16, dw = 16;
+        } else if (f->tile_cells == 0) {
             if (!bf && rt.n_I < kPersistentMinEntries) {
                 // small FP64 tensors (measured on MI355X): 64-cell tiles staged in at most
                 // 40 KiB of LDS (several workgroups per CU); else 32-cell tiles staged in at
@@ -643,7 +646,7 @@ int ffc_form_create(const ffc_form_desc* desc, ffc_form** out) {
         // tensors the persistent kernel does not take): measured on MI355X, the pass is 17-20%
         // faster there (Laplacian P4 on tetrahedra, 2^18 and 2^19 cells)
         const bool pass_default =
-            !bf && (f->pwaves == 0 || f->tab_tile) && f->tile_cells == 16 && rt.n_I >= kPersistentMinEntries;
+            !bf && f->tile_cells == 16 && (f->tab_tile || (f->pwaves == 0 && rt.n_I >= kPersistentMinEntries));
         f->fused = desc->geometry == FFC_GEOMETRY_FUSED ||
                    (desc->geometry == 0 && !pass_default && !f->bpersistent && (f->pwaves == 0 || f->pwaves == 12));
         if (f->bpersistent || f->pwaves == 16) f->fused = false;
