@@ -66,9 +66,9 @@ def measure(form, X, C, reps: int = 5, warmup: int = 2) -> float:
 def measure_all(forms, X, C, reps: int = 7, warmup: int = 2):
     """Median milliseconds of one tabulation for each form on the same mesh, measured in
     interleaved rounds (every form once per round), so clock and power drift during the
-    measurement falls on all candidates alike; each round starts one form later than the
-    previous one, so no form always follows the same (e.g. a long quadrature) launch.  Forms
-    sharing an output dtype share one output buffer."""
+    measurement falls on all candidates alike; each round takes the forms in a fresh random
+    order (seeded), so no form always follows the same launch (a long quadrature launch slows
+    the launch after it).  Forms sharing an output dtype share one output buffer."""
     import torch
 
     outs = {}
@@ -80,9 +80,9 @@ def measure_all(forms, X, C, reps: int = 7, warmup: int = 2):
             f.tabulate(X, C, out=outs[f.out_dtype])
     torch.cuda.synchronize()
     times = [[] for _ in forms]
-    for r in range(reps):
-        for k in range(len(forms)):
-            j = (k + r) % len(forms)
+    rng = np.random.default_rng(12345)
+    for _ in range(reps):
+        for j in rng.permutation(len(forms)):
             f = forms[j]
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             a.record(f.stream)
