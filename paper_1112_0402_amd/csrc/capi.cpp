@@ -443,12 +443,13 @@ int ffc_form_create(const ffc_form_desc* desc, ffc_form** out) {
             for (int w : {16, 12})
                 if (waves_ok(w) && (req_mt == 1 || w == 12)) shapes.push_back({w, req_mt});
         } else if (want_persistent && (desc->persistent == 1 || rt.n_I >= kPersistentMinEntries)) {
-            // large tensors: 16-cell tiles.  12 waves first (the kernel computes the affine
-            // maps: one launch), else 16 (the maps from a geometry pass) -- measured on MI355X
-            // with the non-temporal write-out: elasticity P2 step 1.07 vs 1.09 ms, the
-            // convection form 10% faster on 12 waves; 16 first when persistent = 1 is asked for
+            // large tensors: 16-cell tiles.  Forms with coefficients: 12 waves first (the
+            // kernel computes the affine maps: one launch; the convection form 10% faster than
+            // on 16 waves).  Without coefficients 16 waves first: those forms tabulate on
+            // per-tile workgroups by default (below), and the schedule serves the operator
+            // action, measured faster on 16 waves (elasticity P2: 0.77 vs 0.88 ms per action)
             if (desc->tile_cells == 0 || req_mt == 1) {
-                const bool twelve_first = desc->persistent == 0;
+                const bool twelve_first = desc->persistent == 0 && rt.n_coeff > 0;
                 for (int w : twelve_first ? std::initializer_list<int>{12, 16} : std::initializer_list<int>{16, 12})
                     if (waves_ok(w)) shapes.push_back({w, 1});
             }
