@@ -702,3 +702,58 @@ def test_persistent_kernel_with_32_and_64_cell_tiles(kind, dim, q):
         torch.cuda.synchronize()
         assert np.array_equal(np.concatenate([o.cpu().numpy() for o in outs]), a)
     assert tuple(taken) == MT_EXPECTED.get((kind, dim, q), ()), taken
+
+
+# the library's default launch per form (ffc_form_create's rules), as the header documents
+DEFAULT_LAUNCHES = [
+    # kind, dim, q: (persistent waves, tile cells, waves of the tile launch or None, fused geometry)
+    ("elasticity", 3, 2, (0, 16, 16, 0)),   # >= 400 entries, no coefficients: 16-cell tiles after a pass
+    ("laplace", 3, 3, (0, 16, 16, 0)),
+    ("mass", 3, 3, (0, 16, 16, 0)),
+    ("ns", 3, 2, (12, 16, None, 1)),        # large, with coefficients: 12-wave persistent, maps in-kernel
+    ("wlaplace", 3, 3, (12, 32, None, 1)),  # 400 entries, 16 steps: 32-cell persistent tiles
+    ("laplace", 3, 2, (12, 64, None, 1)),   # 100 entries: 64-cell persistent tiles
+    ("laplace", 2, 4, (12, 32, None, 1)),   # 225 entries: 32-cell persistent tiles
+    ("laplace", 2, 2, (0, 64, 2, 1)),       # 36 entries: 64-cell tiles of two waves
+    ("laplace", 2, 1, (0, 32, 1, 1)),       # 9 entries: 32-cell tiles of one wave
+]
+
+
+@pytest.mark.parametrize("kind,dim,q,expect", DEFAULT_LAUNCHES)
+def test_default_launches(kind, dim, q, expect):
+    """The default launch of each form class is the documented one, its element tensors
+    equal the same launch requested explicitly bit for bit, and the oracle within 1e-12; for
+    the forms that tabulate on 16-cell tiles the operator action matches the oracle's tensors
+    applied to x, and for large tensors equals bit for bit the action of a form that asks for
+    the 16-wave persistent kernel."""
+    require_gpu()
+    f = Form(kind, dim, q)
+    pw, tc, w, fused = expect
+    got = (f.info["persistent_waves"], f.info["tile_cells"], f.info["fused_geometry"])
+    assert got == (pw, tc, fused), (kind, dim, q, f.info)
+    if w is not None:
+        assert f.info["waves"] == w, f.info
+    wl = meshgen.make_workload(kind, dim, q, 40 if dim == 2 else 8, 97, max_cells=2999)
+    a = _run(f, wl)
+    ref = oracle.tabulate(kind, dim, q, wl.coords, wl.coeffs)
+    assert rel_fro(a, ref)[0] <= FP64_TOL
+    if pw == 0:
+        explicit = Form(kind, dim, q, persistent=-1, tile_cells=tc, waves=w,
+                        geometry="fused" if fused else "pass")
+    else:
+        explicit = Form(kind, dim, q, persistent=1, tile_cells=tc, waves=pw)
+    assert np.array_equal(a, _run(explicit, wl))
+    if pw == 0 and tc == 16:
+        X, C = to_dev(wl.coords), to_dev(wl.coeffs)
+        xh = np.random.default_rng(3).standard_normal((wl.cells, f.n))
+        y = f.apply(X, torch.from_numpy(xh).cuda(), C)
+        torch.cuda.synchronize()
+        yref = np.einsum("cij,cj->ci", ref, xh)
+        assert np.abs(y.cpu().numpy() - yref).max() <= FP64_TOL * np.abs(yref).max()
+        if f.n_I >= 576:
+            # large tensors keep the 16-wave schedule for the action
+            p = Form(kind, dim, q, persistent=1, waves=16)
+            assert p.info["persistent_waves"] == 16
+            y2 = p.apply(X, torch.from_numpy(xh).cuda(), C)
+            torch.cuda.synchronize()
+            assert torch.equal(y, y2)
