@@ -8,7 +8,7 @@ import pytest
 import torch
 
 import oracle
-from paper_1112_0402_amd import meshgen
+from paper_1112_0402_amd import capi, meshgen
 from paper_1112_0402_amd.forms import Form
 from tests.gpu_util import rel_fro, require_gpu, to_dev
 from tests.test_gpu_parity import ALL_FORMS, FP64_TOL, split_tol
@@ -75,3 +75,42 @@ def test_output_placement_split(kind, dim, q, precision):
     require_gpu()
     for cells in (1, 33, 241):
         _check(kind, dim, q, precision, cells)
+
+
+@pytest.mark.parametrize("kind,dim,q", ALL_FORMS)
+def test_action_placement(kind, dim, q):
+    """The operator action y_K = A^K x_K into a view of a NaN buffer with guards, aligned and
+    not: guards untouched, every value written, both placements bitwise equal, and y equal
+    to the oracle's element tensors applied to x."""
+    require_gpu()
+    key = (kind, dim, q, "fp64")
+    if key not in _FORMS:
+        _FORMS[key] = Form(kind, dim, q)
+    f = _FORMS[key]
+    if 16 * f.n_I * 8 > 160 * 1024:
+        # a 16-cell tile of element tensors does not fit the LDS: the action refuses the form
+        wl = meshgen.make_workload(kind, dim, q, 11 if dim == 2 else 5, 78, max_cells=5)
+        with pytest.raises(capi.FFCError) as ei:
+            f.apply(to_dev(wl.coords), torch.zeros((wl.cells, f.n), dtype=torch.float64, device="cuda"),
+                    to_dev(wl.coeffs))
+        assert ei.value.code == capi.FFC_E_UNSUPPORTED
+        return
+    for cells in (1, 17, 241):
+        wl = meshgen.make_workload(kind, dim, q, 11 if dim == 2 else 5, 78, max_cells=cells)
+        X, C = to_dev(wl.coords), to_dev(wl.coeffs)
+        xh = np.random.default_rng(cells).standard_normal((wl.cells, f.n))
+        x = torch.from_numpy(xh).cuda()
+        got = {}
+        for shift in (0, 1):
+            n_el = wl.cells * f.n
+            buf = torch.full((n_el + 2 * GUARD + 1,), float("nan"), dtype=torch.float64, device="cuda")
+            y = buf[GUARD + shift:GUARD + shift + n_el].view(wl.cells, f.n)
+            f.apply(X, x, C, y=y)
+            torch.cuda.synchronize()
+            b = buf.cpu().numpy()
+            assert np.isnan(b[:GUARD + shift]).all() and np.isnan(b[GUARD + shift + n_el:]).all(), (kind, dim, q, cells)
+            got[shift] = y.cpu().numpy()
+            assert not np.isnan(got[shift]).any(), (kind, dim, q, cells)
+        assert np.array_equal(got[0], got[1]), (kind, dim, q, cells)
+        ref = np.einsum("cij,cj->ci", oracle.tabulate(kind, dim, q, wl.coords, wl.coeffs), xh)
+        assert np.abs(got[0] - ref).max() <= FP64_TOL * max(np.abs(ref).max(), 1e-300), (kind, dim, q, cells)
