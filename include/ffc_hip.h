@@ -234,7 +234,10 @@ int ffc_form_select(const ffc_form* form, int64_t cells, int32_t* candidate, int
 
 /* Enqueue the evaluation of `cells` element tensors on the form's stream and return
  * (asynchronous).  coords: device SoA as above; coeffs: device SoA or NULL; out: device
- * buffer of cells * n_I entries, double (FP64 and quadrature) or float (split modes).
+ * buffer of cells * n_I entries, double (FP64 and quadrature) or float (split modes),
+ * aligned to its element size; a 16-byte aligned out takes the staged launches (whole
+ * contiguous regions), any other the tile launch with direct stores (the same values;
+ * FP64 bit for bit).  Nothing outside the cells * n_I entries is written.
  * cells == 0 is a no-op.  Not safe for concurrent calls on one form (shared workspace). */
 int ffc_tabulate_tensor(const ffc_form* form, int64_t cells, const double* coords, const double* coeffs, void* out);
 
