@@ -114,3 +114,29 @@ def test_action_placement(kind, dim, q):
         assert np.array_equal(got[0], got[1]), (kind, dim, q, cells)
         ref = np.einsum("cij,cj->ci", oracle.tabulate(kind, dim, q, wl.coords, wl.coeffs), xh)
         assert np.abs(got[0] - ref).max() <= FP64_TOL * max(np.abs(ref).max(), 1e-300), (kind, dim, q, cells)
+
+
+@pytest.mark.parametrize("kind,dim,q", [("piola", 2, 1), ("piola", 3, 1), ("nedelec", 2, 1), ("nedelec", 3, 1),
+                                        ("curved", 2, 1), ("curved", 2, 2), ("curved", 3, 1), ("curved", 3, 2)])
+def test_output_placement_other_kinds(kind, dim, q):
+    """The same placement checks for the Piola-mapped and curvilinear forms (FP64)."""
+    require_gpu()
+    f = Form(kind, dim, q)
+    for cells in (1, 17, 241):
+        if kind == "curved":
+            wl = meshgen.curved_workload(dim, q, 11 if dim == 2 else 5, 79, max_cells=cells)
+        else:
+            wl = meshgen.make_workload(kind, dim, q, 11 if dim == 2 else 5, 79, max_cells=cells)
+        X = to_dev(wl.coords)
+        got = {}
+        for shift in (0, 1):
+            buf, o = _placed(f, wl.cells, shift)
+            f.tabulate(X, out=o)
+            torch.cuda.synchronize()
+            assert _guards_intact(buf, wl.cells, f, shift), (kind, dim, q, cells, shift)
+            got[shift] = o.cpu().numpy()
+            assert not np.isnan(got[shift]).any(), (kind, dim, q, cells, shift)
+        assert np.array_equal(got[0], got[1]), (kind, dim, q, cells)
+        ref = (oracle.curved_laplace(dim, q, wl.coords) if kind == "curved"
+               else oracle.piola_mass(dim, wl.coords) if kind == "piola" else oracle.nedelec_mass(dim, wl.coords))
+        assert rel_fro(got[0], ref)[0] <= FP64_TOL, (kind, dim, q, cells)
