@@ -757,3 +757,57 @@ def test_default_launches(kind, dim, q, expect):
             y2 = p.apply(X, torch.from_numpy(xh).cuda(), C)
             torch.cuda.synchronize()
             assert torch.equal(y, y2)
+
+
+GRAPH_CASES = [
+    ("elasticity", 3, 2, {}), ("ns", 3, 2, {}), ("laplace", 3, 2, {}), ("laplace", 2, 1, {}), ("laplace", 3, 4, {}),
+    ("elasticity", 3, 2, {"persistent": 1, "waves": 16}), ("wlaplace", 3, 3, {"precision": "bf16x6"}),
+    ("wlaplace", 3, 3, {"precision": "bf16x3"}), ("elasticity", 3, 2, {"kernel": "quadrature"}),
+    ("laplace", 3, 3, {"kernel": "auto"}),
+]
+
+
+@pytest.mark.parametrize("kind,dim,q,opts", GRAPH_CASES)
+def test_tabulation_graph_replay(kind, dim, q, opts):
+    """Each launch class captured in a graph (the geometry pass and the contraction, or one
+    fused launch) and replayed three times, with other eager work and synchronisations
+    between the replays: every replay equals the eager result bit for bit.  FP64 tensor
+    forms also replay their operator action."""
+    require_gpu()
+    s = torch.cuda.Stream()
+    f = Form(kind, dim, q, stream=s, **opts)
+    other = Form("mass", 2, 1)
+    wl = meshgen.make_workload(kind, dim, q, 40 if dim == 2 else 12, 123, max_cells=9001)
+    ow = meshgen.make_workload("mass", 2, 1, 20, 124)
+    X, C, OX = to_dev(wl.coords), to_dev(wl.coeffs), to_dev(ow.coords)
+    out = f.empty_out(wl.cells)
+    act = f.info["out_bytes"] == 8 and opts.get("kernel", "tensor") == "tensor"
+    if act:
+        x = torch.from_numpy(np.random.default_rng(5).standard_normal((wl.cells, f.n))).cuda()
+        y = torch.empty_like(x)
+    with torch.cuda.stream(s):
+        f.tabulate(X, C, out=out)
+        if act:
+            f.apply(X, x, C, y=y)
+    torch.cuda.synchronize()
+    eager = out.clone()
+    eager_y = y.clone() if act else None
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        f.tabulate(X, C, out=out)
+        if act:
+            f.apply(X, x, C, y=y)
+    for rep in range(3):
+        out.fill_(float("nan"))
+        if act:
+            y.fill_(float("nan"))
+        other.tabulate(OX)  # eager work between the replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), (kind, dim, q, opts, rep)
+        if act:
+            assert torch.equal(y, eager_y), (kind, dim, q, opts, rep, "action")
+    ref = oracle.tabulate(kind, dim, q, wl.coords[:, :64].copy(), None if wl.coeffs is None else wl.coeffs[:, :64].copy())
+    tol = FP64_TOL if f.info["out_bytes"] == 8 else split_tol(opts["precision"], kind, dim, q)
+    assert rel_fro(out[:64].cpu().numpy(), ref)[0] <= tol
