@@ -126,3 +126,45 @@ def test_global_operator_matches_assembled_matrix(kind, dim, q, n):
     e = float(np.abs(y.cpu().numpy() - ref).max() / scale)
     say(f"[operator] {kind} d={dim} q={q}: {ng} dofs, max error {e:.2e}")
     assert e <= TOL
+
+
+def test_global_operator_graph_replay():
+    """The matrix-free y = A x (gather, per-cell action, fixed-order sum) and its
+    allocation-free entry point, each captured in a graph and replayed three times with eager
+    work between the replays: every replay equals the eager result bit for bit."""
+    require_gpu()
+    s = torch.cuda.Stream()
+    wl = meshgen.make_workload("elasticity", 3, 2, 5, 12)
+    dm, ng = meshgen.lagrange_dofmap(wl.meta["cells"], 2, 3)
+    form = Form("elasticity", 3, 2, stream=s)
+    asm = Assembly(dm, ng, stream=s)
+    X, xd = to_dev(wl.coords), to_dev(np.random.default_rng(6).uniform(-1.0, 1.0, size=ng))
+    y = torch.empty(ng, dtype=torch.float64, device="cuda")
+    y2 = torch.empty_like(y)
+    work = torch.empty(2 * asm.cells * asm.n_local, dtype=torch.float64, device="cuda")
+
+    def noalloc():
+        capi.check(capi.lib().ffc_operator_apply_noalloc(asm._h, form.handle, X.data_ptr(), None, xd.data_ptr(),
+                                                         y2.data_ptr()))
+
+    with torch.cuda.stream(s):
+        asm.apply(form, X, xd, y=y, work=work)
+        noalloc()
+    torch.cuda.synchronize()
+    eager, eager2 = y.clone(), y2.clone()
+    assert torch.equal(eager, eager2)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        asm.apply(form, X, xd, y=y, work=work)
+        noalloc()
+    other = Form("mass", 2, 1)
+    ow = to_dev(meshgen.make_workload("mass", 2, 1, 20, 13).coords)
+    for rep in range(3):
+        y.fill_(float("nan"))
+        y2.fill_(float("nan"))
+        other.tabulate(ow)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(y, eager), rep
+        assert torch.equal(y2, eager2), rep
