@@ -811,3 +811,41 @@ def test_tabulation_graph_replay(kind, dim, q, opts):
     ref = oracle.tabulate(kind, dim, q, wl.coords[:, :64].copy(), None if wl.coeffs is None else wl.coeffs[:, :64].copy())
     tol = FP64_TOL if f.info["out_bytes"] == 8 else split_tol(opts["precision"], kind, dim, q)
     assert rel_fro(out[:64].cpu().numpy(), ref)[0] <= tol
+
+
+def test_forms_on_concurrent_streams():
+    """Forms share no device state: five forms (geometry pass + tile kernel, 12- and 16-wave
+    persistent, split-BF16 persistent after a pass, quadrature), each on its own stream,
+    tabulate and apply interleaved without synchronisation; every result equals the same
+    call run alone."""
+    require_gpu()
+    specs = [("elasticity", 3, 2, {}), ("ns", 3, 2, {}), ("elasticity", 3, 2, {"persistent": 1, "waves": 16}),
+             ("wlaplace", 3, 3, {"precision": "bf16x6"}), ("laplace", 3, 2, {"kernel": "quadrature"})]
+    streams = [torch.cuda.Stream() for _ in specs]
+    forms = [Form(k, d, q, stream=s, **o) for (k, d, q, o), s in zip(specs, streams)]
+    wls = [meshgen.make_workload(k, d, q, 14, 300 + i, max_cells=12000) for i, (k, d, q, _) in enumerate(specs)]
+    X = [to_dev(w.coords) for w in wls]
+    C = [to_dev(w.coeffs) for w in wls]
+    acts = [f.info["out_bytes"] == 8 and o.get("kernel", "tensor") == "tensor" for f, (_, _, _, o) in zip(forms, specs)]
+    xs = [torch.from_numpy(np.random.default_rng(i).standard_normal((w.cells, f.n))).cuda()
+          for i, (f, w) in enumerate(zip(forms, wls))]
+    alone, alone_y = [], []
+    for f, s, x, c, xv, a in zip(forms, streams, X, C, xs, acts):
+        with torch.cuda.stream(s):
+            alone.append(f.tabulate(x, c))
+            alone_y.append(f.apply(x, xv, c) if a else None)
+        torch.cuda.synchronize()
+    outs = [f.empty_out(w.cells).fill_(float("nan")) for f, w in zip(forms, wls)]
+    ys = [torch.full_like(xv, float("nan")) for xv in xs]
+    torch.cuda.synchronize()
+    for rep in range(2):
+        for f, s, x, c, o, xv, y, a in zip(forms, streams, X, C, outs, xs, ys, acts):
+            with torch.cuda.stream(s):
+                f.tabulate(x, c, out=o)
+                if a:
+                    f.apply(x, xv, c, y=y)
+    torch.cuda.synchronize()
+    for (k, d, q, o_), o, r, y, ry, a in zip(specs, outs, alone, ys, alone_y, acts):
+        assert torch.equal(o, r), (k, d, q, o_)
+        if a:
+            assert torch.equal(y, ry), (k, d, q, o_, "action")
