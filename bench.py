@@ -700,8 +700,9 @@ def other_configs(args, torch, np):
         "value": bt["fp64_selector"]["value"], "unit": "element tensors/s",
         "vs_default": bt["fp64_selector"]["value"] / bt["fp64_default"]["value"],
         "vs_autotune": bt["fp64_selector"]["value"] / bt["fp64_autotune"]["value"],
-        "note": "mixed 64-mesh batch with each mesh's launch picked by the selector network that "
-                "FFC_KERNEL_AUTO forms load; mesh sizes not in the sweep it was trained on"}
+        "note": "mixed 64-mesh batch with each form's launch picked by the selector network that "
+                "FFC_KERNEL_AUTO forms load, for the form's cells summed over the batch (one launch per "
+                "form and shape); sizes not in the sweep it was trained on"}
     out["batch64_mixed"] = bt
     return out
 

@@ -145,13 +145,20 @@ def batch_forms(workloads, precision="fp64", choice="default", db: TuneDB | None
     """One form per batch item (a Batch groups items by launch shape): the library default
     launch (`choice="default"`), the exhaustive autotuner's winner on the item's own mesh,
     cached in `db` per (form, log2 cells) shape (`"autotune"`), or the trained selector's
-    pick (`"selector"`, FP64).  Batches run the tensor kernel, so the quadrature candidate
-    is excluded; items with the same form and launch share one Form."""
+    pick (`"selector"`, FP64).  A batch runs all items of one form and launch shape in one
+    launch, so the selector decides once per form, for the form's cells summed over the
+    batch: per-mesh picks that differ would split a form's items over several launches.
+    Batches run the tensor kernel, so the quadrature candidate is excluded; items with the
+    same form and launch share one Form."""
     import torch
 
     cands = candidates(precision)
     tensor_idx = [i for i, c in enumerate(cands) if c["kernel"] == "tensor"]
     forms, out, picks = {}, [], []
+    form_cells = {}
+    for w in workloads:
+        form_cells[(w.kind, w.dim, w.degree)] = form_cells.get((w.kind, w.dim, w.degree), 0) + w.cells
+    sel_pick = {}
 
     def form_of(w, j):  # one Form per (form variant, candidate), shared by the meshes
         key = (w.kind, w.dim, w.degree, j)
@@ -175,11 +182,14 @@ def batch_forms(workloads, precision="fp64", choice="default", db: TuneDB | None
                 if db is not None:
                     db.put(key, {"candidate": j, "tensor_candidate": j, "config": cands[j], "ms": min(t)})
         elif choice == "selector":
-            info = form_of(w, 0).info
-            rec = {"kind": w.kind, "dim": w.dim, "degree": w.degree, "cells": w.cells, "n_I": info["n_entries"],
-                   "n_alpha": info["n_alpha"], "ms": [1.0] * len(cands)}
-            pred = selector.predict_rel([rec])[0]
-            j = min(tensor_idx, key=lambda i: pred[i])
+            fk = (w.kind, w.dim, w.degree)
+            if fk not in sel_pick:
+                info = form_of(w, 0).info
+                rec = {"kind": w.kind, "dim": w.dim, "degree": w.degree, "cells": form_cells[fk],
+                       "n_I": info["n_entries"], "n_alpha": info["n_alpha"], "ms": [1.0] * len(cands)}
+                pred = selector.predict_rel([rec])[0]
+                sel_pick[fk] = min(tensor_idx, key=lambda i: pred[i])
+            j = sel_pick[fk]
         else:
             raise ValueError(f"unknown choice {choice!r}")
         out.append(form_of(w, j))
