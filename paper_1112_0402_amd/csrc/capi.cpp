@@ -124,13 +124,15 @@ int auto_bucket(int64_t cells) {
 // The learned kernel choice (the automatic tensor-vs-quadrature decision of Sec. 4.4): a
 // multilayer perceptron trained on timings of every candidate launch predicts
 // log(t_candidate / t_default) from seven features of the form and the cell count; the
-// argmin is taken.  The text file holds: "ffc_selector 1", the sizes, the feature means and
-// deviations, the target offset, the flat FP32 parameters (W1 [n_in][h], b1, W2 [h][h], b2,
-// W3 [h][n_out], b3) and one line per candidate launch.
+// lowest candidate is taken if it beats the default by more than the file's decision margin.
+// The text file holds: "ffc_selector 2", the sizes, the feature means and deviations, the
+// target offset, the margin (a fraction; version 1 files have none: plain argmin), the flat
+// FP32 parameters (W1 [n_in][h], b1, W2 [h][h], b2, W3 [h][n_out], b3) and one line per
+// candidate launch.
 struct SelectorNet {
     int n_in = 0, h = 0, n_out = 0;
     std::vector<double> mu, sd;
-    double tmu = 0.0;
+    double tmu = 0.0, margin = 0.0;
     std::vector<float> params;
     struct Cand {
         int kernel, tile_cells, waves, persistent, tile_window, geometry;
@@ -148,7 +150,8 @@ struct SelectorNet {
             return std::fscanf(fp, "%63s", buf) == 1 && std::strcmp(buf, want) == 0;
         };
         int version = 0;
-        bool ok = word("ffc_selector") && std::fscanf(fp, "%d", &version) == 1 && version == 1 && word("n_in") &&
+        bool ok = word("ffc_selector") && std::fscanf(fp, "%d", &version) == 1 && (version == 1 || version == 2) &&
+                  word("n_in") &&
                   std::fscanf(fp, "%d", &n_in) == 1 && word("n_hidden") && std::fscanf(fp, "%d", &h) == 1 &&
                   word("n_out") && std::fscanf(fp, "%d", &n_out) == 1 && n_in == 7 && h > 0 && h <= 4096 &&
                   n_out > 0 && n_out <= 64;
@@ -160,6 +163,8 @@ struct SelectorNet {
             ok = ok && word("sd");
             for (int i = 0; ok && i < n_in; ++i) ok = std::fscanf(fp, "%lf", &sd[i]) == 1 && sd[i] > 0.0;
             ok = ok && word("tmu") && std::fscanf(fp, "%lf", &tmu) == 1;
+            if (version == 2)
+                ok = ok && word("margin") && std::fscanf(fp, "%lf", &margin) == 1 && margin >= 0.0 && margin < 1.0;
         }
         long long np = 0;
         if (ok) ok = word("params") && std::fscanf(fp, "%lld", &np) == 1 &&
@@ -343,7 +348,8 @@ int create_auto(const ffc_form_desc* desc, const ffc::FormSpec& spec, ffc_form**
                 const double x[7] = {2.0, static_cast<double>(desc->degree), lI, la, static_cast<double>(desc->dim),
                                      static_cast<double>(b), b + lI};
                 const std::vector<double> y = net.predict(x);
-                const int best = static_cast<int>(std::min_element(y.begin(), y.end()) - y.begin());
+                int best = static_cast<int>(std::min_element(y.begin(), y.end()) - y.begin());
+                if (!(y[best] < y[0] - std::log1p(net.margin))) best = 0;  // within the margin: the default
                 auto it = sub_of_cand.find(best);
                 if (it == sub_of_cand.end()) {
                     const SelectorNet::Cand& c = net.cands[best];

@@ -184,15 +184,24 @@ def records_to_arrays(records):
     return X, T, M
 
 
-class Selector:
-    """Normalised features -> MLP -> argmin of the predicted time relative to the default
-    launch over the candidates."""
+# A candidate replaces the default launch only if it is predicted faster by more than this
+# fraction: the network's predictions carry errors of a few percent, and switching on a
+# predicted gain below them picks slower launches about as often as faster ones.  Chosen by
+# cross-validation over the stored sweep (mean regret and summed time at margins 0 .. 0.15,
+# per-size folds and leave-one-form-out folds, both best at 0.01 - 0.02).
+DECISION_MARGIN = 0.02
 
-    def __init__(self, n_hidden=64, seed=0):
+
+class Selector:
+    """Normalised features -> MLP -> the candidate with the lowest predicted time relative to
+    the default launch, if that beats the default by more than the decision margin."""
+
+    def __init__(self, n_hidden=64, seed=0, margin=DECISION_MARGIN):
         self.net = MLP(n_hidden=n_hidden, seed=seed)
         self.mu = np.zeros(N_FEATURES)
         self.sd = np.ones(N_FEATURES)
         self.tmu = 0.0
+        self.margin = margin
 
     def fit(self, records, epochs=3000, lr=3e-3, weight_decay=1e-3):
         X, T, M = records_to_arrays(records)
@@ -205,22 +214,31 @@ class Selector:
         X, _, _ = records_to_arrays(records)
         return self.net.predict((X - self.mu) / self.sd) + self.tmu
 
+    def decide(self, pred, allowed=None) -> int:
+        """The pick for one row of predict_rel: the lowest predicted candidate (among
+        `allowed`, default all) if it beats the default (candidate 0) by more than the margin,
+        else the default."""
+        idx = range(len(pred)) if allowed is None else allowed
+        j = min(idx, key=lambda i: pred[i])
+        return int(j) if pred[j] < pred[0] - math.log1p(self.margin) else 0
+
     def choose(self, records):
-        return [int(i) for i in np.argmin(self.predict_rel(records), axis=1)]
+        return [self.decide(y) for y in self.predict_rel(records)]
 
     def export(self, path, candidates=CANDIDATES_FP64):
         """Write the trained selector as the text file that the library's automatic kernel
         choice (FFC_KERNEL_AUTO) reads at form creation: sizes, feature normalisation, the
-        offset of the targets, the flat FP32 parameters and the candidate launches, one per
+        offset of the targets, the decision margin, the flat FP32 parameters and the candidate
+        launches, one per
         line as "kernel tile_cells waves persistent tile_window geometry" with kernel 1 =
         tensor, 2 = quadrature and geometry 0 = default, 1 = pass, 2 = fused."""
         from . import capi
 
         params = self.net.params.detach().cpu().numpy().astype(np.float32)
-        lines = ["ffc_selector 1", f"n_in {self.net.n_in} n_hidden {self.net.h} n_out {self.net.n_out}",
+        lines = ["ffc_selector 2", f"n_in {self.net.n_in} n_hidden {self.net.h} n_out {self.net.n_out}",
                  "mu " + " ".join(repr(float(v)) for v in self.mu),
                  "sd " + " ".join(repr(float(v)) for v in self.sd),
-                 f"tmu {self.tmu!r}",
+                 f"tmu {self.tmu!r}", f"margin {float(self.margin)!r}",
                  f"params {params.size} " + " ".join(repr(float(v)) for v in params),
                  f"candidates {len(candidates)}"]
         for c in candidates:
@@ -238,7 +256,8 @@ class Selector:
         import torch
 
         tok = open(path).read().split()
-        assert tok[0] == "ffc_selector" and tok[1] == "1", "not a selector file"
+        assert tok[0] == "ffc_selector" and tok[1] in ("1", "2"), "not a selector file"
+        version = int(tok[1])
         n_in, h, n_out = int(tok[3]), int(tok[5]), int(tok[7])
         assert n_in == N_FEATURES and n_out == len(CANDIDATES_FP64)
         i = 8
@@ -248,10 +267,14 @@ class Selector:
         sd = np.array([float(x) for x in tok[i + 1:i + 1 + n_in]]); i += 1 + n_in
         assert tok[i] == "tmu"
         tmu = float(tok[i + 1]); i += 2
+        margin = 0.0  # version 1 files: plain argmin
+        if version == 2:
+            assert tok[i] == "margin"
+            margin = float(tok[i + 1]); i += 2
         assert tok[i] == "params"
         n = int(tok[i + 1])
         params = np.array([float(x) for x in tok[i + 2:i + 2 + n]], dtype=np.float32)
-        sel = cls(n_hidden=h)
+        sel = cls(n_hidden=h, margin=margin)
         sel.mu, sel.sd, sel.tmu = mu, sd, tmu
         sel.net.params = torch.tensor(params, dtype=torch.float32, device="cuda")
         return sel

@@ -187,8 +187,7 @@ def batch_forms(workloads, precision="fp64", choice="default", db: TuneDB | None
                 info = form_of(w, 0).info
                 rec = {"kind": w.kind, "dim": w.dim, "degree": w.degree, "cells": form_cells[fk],
                        "n_I": info["n_entries"], "n_alpha": info["n_alpha"], "ms": [1.0] * len(cands)}
-                pred = selector.predict_rel([rec])[0]
-                sel_pick[fk] = min(tensor_idx, key=lambda i: pred[i])
+                sel_pick[fk] = selector.decide(selector.predict_rel([rec])[0], tensor_idx)
             j = sel_pick[fk]
         else:
             raise ValueError(f"unknown choice {choice!r}")
