@@ -120,7 +120,9 @@ typedef enum { FFC_FP64 = 0, FFC_SPLIT_BF16_3 = 1, FFC_SPLIT_BF16_6 = 2 } ffc_pr
  * count).  ffc_form_create reads the trained network from the file named by the
  * environment variable FFC_SELECTOR ("none": no file), else from
  * data/selector_mi355x_fp64.txt in the directory of this library; evaluates it on the host
- * for every cell count 2^0 .. 2^40; and creates one internal form per launch it picks, so
+ * for every cell count 2^0 .. 2^40 (a launch other than the default is picked only when
+ * predicted faster by more than the file's decision margin); and creates one internal form
+ * per launch it picks, so
  * ffc_tabulate_tensor only dispatches (to the pick for round(log2 cells)) and still never
  * allocates.  The network decides for FP64 Lagrange forms (FFC_MASS .. FFC_NS_CONVECTION),
  * the forms it was trained on; elsewhere, and when no file is found, every cell count takes
