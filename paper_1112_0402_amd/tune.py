@@ -176,30 +176,35 @@ def batch_forms(workloads, precision="fp64", choice="default", db: TuneDB | None
         return forms[key]
 
     def tune_form(ws):
-        """Median ms of each tensor candidate running these meshes as one batch."""
+        """The pick among the tensor candidates running these meshes as one batch: medians
+        over interleaved rounds (every candidate once per round, in a fresh seeded random
+        order, as in measure_all)."""
         X = [torch.from_numpy(w.coords).cuda() for w in ws]
         C = [None if w.coeffs is None else torch.from_numpy(w.coeffs).cuda() for w in ws]
-        outs = {}
-        times = []
+        outs, batches = {}, []
         for j in tensor_idx:
             f = form_of(ws[0], j)
             if f.out_dtype not in outs:
                 outs[f.out_dtype] = [f.empty_out(w.cells) for w in ws]
-            b = Batch([f] * len(ws), X, C, outs[f.out_dtype])
-            s = torch.cuda.current_stream()
-            for _ in range(2):
+            batches.append(Batch([f] * len(ws), X, C, outs[f.out_dtype]))
+        s = torch.cuda.current_stream()
+        for _ in range(2):
+            for b in batches:
                 b.run()
-            torch.cuda.synchronize()
-            ts = []
-            for _ in range(reps):
+        torch.cuda.synchronize()
+        ts = [[] for _ in batches]
+        rng = np.random.default_rng(777)
+        for _ in range(reps):
+            for k in rng.permutation(len(batches)):
                 a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 a.record(s)
-                b.run()
+                batches[k].run()
                 e.record(s)
                 e.synchronize()
-                ts.append(a.elapsed_time(e))
-            times.append(float(np.median(ts)))
+                ts[k].append(a.elapsed_time(e))
+        for b in batches:
             b.close()
+        times = [float(np.median(t)) for t in ts]
         # the default unless a candidate is faster by more than the margin: with ten
         # candidates timed on small batches, a plain argmin often keeps the luckiest timing
         best = int(np.argmin(times))
