@@ -716,6 +716,8 @@ DEFAULT_LAUNCHES = [
     ("laplace", 2, 4, (12, 32, None, 1)),   # 225 entries: 32-cell persistent tiles
     ("laplace", 2, 2, (0, 64, 2, 1)),       # 36 entries: 64-cell tiles of two waves
     ("laplace", 2, 1, (0, 32, 1, 1)),       # 9 entries: 32-cell tiles of one wave
+    ("wlaplace", 3, 1, (0, 32, 2, 1)),      # 16 entries with a coefficient: 32-cell tiles of two waves
+    ("wlaplace", 2, 2, (0, 32, 2, 1)),
 ]
 
 
@@ -849,3 +851,24 @@ def test_forms_on_concurrent_streams():
         assert torch.equal(o, r), (k, d, q, o_)
         if a:
             assert torch.equal(y, ry), (k, d, q, o_, "action")
+
+
+# split modes, tile launches of small tensors: (tile cells, waves) by default
+SPLIT_DEFAULT_TILES = [("laplace", 2, 1, "bf16x6", 64, 1), ("mass", 3, 1, "bf16x6", 64, 2),
+                       ("elasticity", 2, 1, "bf16x3", 64, 2), ("laplace", 2, 3, "bf16x6", 64, 4),
+                       ("ns", 2, 1, "bf16x3", 64, 4), ("wlaplace", 3, 1, "bf16x6", 64, 4)]
+
+
+@pytest.mark.parametrize("kind,dim,q,precision,tc,w", SPLIT_DEFAULT_TILES)
+def test_split_default_tile_shapes(kind, dim, q, precision, tc, w):
+    """The split modes' tile launch of small tensors takes the documented workgroup size; the
+    element tensors equal the 8-wave launch of the same tiles bit for bit (each 16-entry tile
+    runs the same MFMA chain on whichever wave owns it) and the oracle within the bound."""
+    require_gpu()
+    f = Form(kind, dim, q, precision=precision)
+    assert (f.info["persistent_waves"], f.info["tile_cells"], f.info["waves"]) == (0, tc, w), f.info
+    wl = meshgen.make_workload(kind, dim, q, 30 if dim == 2 else 8, 131, max_cells=2999)
+    a = _run(f, wl)
+    assert np.array_equal(a, _run(Form(kind, dim, q, precision=precision, tile_cells=tc, waves=8), wl))
+    ref = oracle.tabulate(kind, dim, q, wl.coords, wl.coeffs)
+    assert rel_fro(a, ref)[0] <= split_tol(precision, kind, dim, q)
