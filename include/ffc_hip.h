@@ -260,7 +260,10 @@ int ffc_tabulate_tensor_affine(const ffc_form* form, int64_t cells, const double
  * device [cells][n], overwritten.  FP64 tensor-kernel forms only (FFC_E_UNSUPPORTED
  * otherwise, or when the element tensors of a 16-cell tile do not fit the LDS of a CU).
  * Asynchronous on the form's stream, like ffc_tabulate_tensor; results equal A^K x_K
- * computed from ffc_tabulate_tensor's output to FP64 rounding.
+ * computed from ffc_tabulate_tensor's output to FP64 rounding.  Launch: the persistent
+ * kernel where the form has one on 16-cell tiles, else a per-tile kernel on the form's own
+ * tile_cells and waves when both were given and the tile fits, else on a shape chosen for
+ * the element tensor's size.
  * Linear forms: the source term L(v) = int f v dx, f in the element's own space (Sec. 5.5),
  * has the tensor representation b_K,i = A^0_{ia} |det J| f_a with the mass form's A^0, so
  * its element vectors are this call on an FFC_MASS form with x = the cells' f dofs. */

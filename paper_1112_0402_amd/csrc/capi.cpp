@@ -831,6 +831,17 @@ namespace {
 // resident per CU)
 bool apply_tile_shape(const ffc_form* f, int* tile_cells, int* waves) {
     const auto& rt = f->rt;
+    // tiny tensors: 32-cell tiles of one wave up to 9 entries, of two up to 36, so more
+    // workgroups stay resident (measured on MI355X at ~10^6 cells against 64-cell tiles of 4
+    // waves: Laplacian P1 on triangles 1.8x, P1 on tetrahedra and mass P1 1.5x, Laplacian P2 on
+    // triangles 1.3x, elasticity P1 on triangles 1.2x faster)
+    if (rt.n_I <= 36 &&
+        ffc::plan_lds(f->desc.dim, f->desc.kind, 32, rt.n_I, rt.n_alpha, 0, false, ffc::kLdsBudget).staged &&
+        ffc::apply_lds_bytes(f->desc.dim, f->desc.kind, 32, rt.n_I, rt.n_alpha, rt.n) <= 48 * 1024) {
+        *tile_cells = 32;
+        *waves = rt.n_I <= 9 ? 1 : 2;
+        return true;
+    }
     for (int ct : {64, 32, 16}) {
         const size_t lds = ffc::apply_lds_bytes(f->desc.dim, f->desc.kind, ct, rt.n_I, rt.n_alpha, rt.n);
         const ffc::LdsPlan p =
@@ -874,8 +885,16 @@ int ffc_apply_tensor(const ffc_form* form, int64_t cells, const double* coords, 
         if (e == hipSuccess) return FFC_OK;
     }
     int ct = 0, w = 0;
-    if (!apply_tile_shape(f, &ct, &w))
+    // a launch shape the form was created with (tile_cells and waves both given) when the
+    // action's tile fits it, else the action's own choice
+    const int dct = f->desc.tile_cells, dw = f->desc.waves;
+    if (dct && dw >= 1 && dw <= 16 &&
+        ffc::plan_lds(d, kind, dct, rt.n_I, rt.n_alpha, 0, false, ffc::kLdsBudget).staged &&
+        ffc::apply_lds_bytes(d, kind, dct, rt.n_I, rt.n_alpha, n) <= ffc::kLdsBudget) {
+        ct = dct, w = dw;
+    } else if (!apply_tile_shape(f, &ct, &w)) {
         return fail(FFC_E_UNSUPPORTED, "the element tensors of a 16-cell tile do not fit the LDS of a CU");
+    }
     ffc::ContractArgs a = contract_args(f, cells, nullptr, 0, coeffs, cells, y);
     a.coords = coords;
     a.xloc = x;
