@@ -459,9 +459,10 @@ def bench_assembly(args, torch, np):
         step_ms = timed(lambda: (form.tabulate(X, None, out=T), asm.assemble(T, values=vals)), args.steps, stream,
                         torch)
     entries = cells * n * n
-    # algorithmic bytes of one assembly: element tensors and their CSR indices read once,
-    # every value written once, the per-row lists (row and slot offsets, slots) read once
-    byt = entries * (8 + 4) + asm.nnz * 8 + cells * n * 4 + ng * 16
+    # algorithmic bytes of one assembly: element tensors and their in-row indices (16 bit)
+    # read once, every value written once, the per-row lists (row and slot offsets, slots)
+    # read once
+    byt = entries * (8 + 2) + asm.nnz * 8 + cells * n * 4 + ng * 16
     gbs = byt / (asm_ms * 1e-3) / 1e9
     result = {
         "metric": "assembled element-tensor entries/s (global CSR assembly after tabulation)",

@@ -17,16 +17,17 @@ namespace ffc {
 bool csr_pattern(int64_t cells, int n, const int32_t* dofmap, int64_t n_dofs, std::vector<int64_t>* row_ptr,
                  std::vector<int32_t>* col, std::vector<int64_t>* slot_ptr, std::vector<int32_t>* slots);
 
-// pos[c][i][j] = CSR index of entry (dofmap[c][i], dofmap[c][j]) (binary search in the row)
+// pos[c][i][j] = index of entry (dofmap[c][i], dofmap[c][j]) within its CSR row, i.e. its
+// CSR index minus the row start (binary search in the row; rows of at most 1024 entries)
 hipError_t scatter_positions(int64_t cells, int n, const int32_t* dofmap, const int64_t* row_ptr, const int32_t* col,
-                             int32_t* pos, hipStream_t s);
+                             uint16_t* pos, hipStream_t s);
 // Row gather: one wave per matrix row r sums, in slot order, the element-tensor rows that
 // land in r (each read as one contiguous run) into an LDS copy of the CSR row at the
-// entries' CSR indices pos, then writes the row once (plus its previous values if
+// entries' in-row indices pos, then writes the row once (plus its previous values if
 // accumulate).  No atomics, a fixed summation order.  tensors FP64 (tensor_bytes 8) or
 // FP32 (4, split-BF16 output); max_row = the longest CSR row.
 hipError_t gather_rows(int64_t n_rows, int n, const int64_t* slot_ptr, const int32_t* slots, const void* tensors,
-                       int tensor_bytes, const int32_t* pos, const int64_t* row_ptr, double* values, int accumulate,
+                       int tensor_bytes, const uint16_t* pos, const int64_t* row_ptr, double* values, int accumulate,
                        int max_row, hipStream_t s);
 
 // Matrix-free operator steps.  Gather: xl[k] = x[dofmap[k]] for k < m (m = cells * n).

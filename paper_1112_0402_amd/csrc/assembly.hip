@@ -69,7 +69,7 @@ namespace {
 
 __global__ void positions_kernel(int64_t cells, int n, const int32_t* __restrict__ dofmap,
                                  const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
-                                 int32_t* __restrict__ pos) {
+                                 uint16_t* __restrict__ pos) {
     const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t nn = static_cast<int64_t>(n) * n;
     if (e >= cells * nn) return;
@@ -85,7 +85,7 @@ __global__ void positions_kernel(int64_t cells, int n, const int32_t* __restrict
         else
             hi = mid;
     }
-    pos[e] = static_cast<int32_t>(lo);
+    pos[e] = static_cast<uint16_t>(lo - row_ptr[r]);  // rows hold at most 1024 entries
 }
 
 
@@ -96,7 +96,7 @@ constexpr int kRowWaves = 4;  // waves per workgroup of the gather
 template <typename T, int RPW>
 __global__ __launch_bounds__(64 * kRowWaves) void gather_rows_kernel(
     int64_t n_rows, int n, const int64_t* __restrict__ slot_ptr, const int32_t* __restrict__ slots,
-    const T* __restrict__ tensors, const int32_t* __restrict__ pos, const int64_t* __restrict__ row_ptr,
+    const T* __restrict__ tensors, const uint16_t* __restrict__ pos, const int64_t* __restrict__ row_ptr,
     double* __restrict__ values, int accumulate, int max_row) {
     extern __shared__ double rowbuf[];
     constexpr int L = 64 / RPW;  // lanes per row
@@ -127,7 +127,7 @@ __global__ __launch_bounds__(64 * kRowWaves) void gather_rows_kernel(
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (p[u] >= 0) b[p[u] - base] += static_cast<double>(v[u]);
+            if (p[u] >= 0) b[p[u]] += static_cast<double>(v[u]);
     }
     for (int k = j; k < len; k += L) values[base + k] = b[k];
 }
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(64 * kRowWaves) void gather_rows_kernel(
 }  // namespace
 
 hipError_t scatter_positions(int64_t cells, int n, const int32_t* dofmap, const int64_t* row_ptr, const int32_t* col,
-                             int32_t* pos, hipStream_t s) {
+                             uint16_t* pos, hipStream_t s) {
     const int64_t total = cells * n * n;
     if (total <= 0) return hipSuccess;
     positions_kernel<<<static_cast<unsigned>((total + 255) / 256), 256, 0, s>>>(cells, n, dofmap, row_ptr, col, pos);
@@ -144,7 +144,7 @@ hipError_t scatter_positions(int64_t cells, int n, const int32_t* dofmap, const 
 
 
 hipError_t gather_rows(int64_t n_rows, int n, const int64_t* slot_ptr, const int32_t* slots, const void* tensors,
-                       int tensor_bytes, const int32_t* pos, const int64_t* row_ptr, double* values, int accumulate,
+                       int tensor_bytes, const uint16_t* pos, const int64_t* row_ptr, double* values, int accumulate,
                        int max_row, hipStream_t s) {
     if (n_rows <= 0) return hipSuccess;
     if (n > 64) return hipErrorInvalidValue;  // one lane per element-tensor column

@@ -1211,7 +1211,7 @@ struct ffc_assembly {
     int n = 0, max_row = 0;
     std::vector<int64_t> row_ptr;
     std::vector<int32_t> col;
-    int32_t* d_pos = nullptr;       // [cells][n][n] CSR index of each element-tensor entry
+    uint16_t* d_pos = nullptr;      // [cells][n][n] index of each element-tensor entry within its CSR row
     int64_t* d_row_ptr = nullptr;   // [n_global + 1]
     int64_t* d_slot_ptr = nullptr;  // [n_global + 1]
     int32_t* d_slots = nullptr;     // [cells * n] element-tensor rows per matrix row
@@ -1261,7 +1261,7 @@ int ffc_assembly_create(int64_t cells, int32_t n_local, const int32_t* dofmap, i
             (void)hipFree(d_col);
             return rc;
         }
-        hipError_t e = hipMalloc(reinterpret_cast<void**>(&a->d_pos), entries * sizeof(int32_t));
+        hipError_t e = hipMalloc(reinterpret_cast<void**>(&a->d_pos), entries * sizeof(uint16_t));
         if (e == hipSuccess)
             e = ffc::scatter_positions(cells, n_local, a->d_dofmap, a->d_row_ptr, d_col, a->d_pos, a->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(a->stream);
