@@ -187,7 +187,30 @@ __global__ void sum_slots_kernel(int64_t n_rows, const int64_t* __restrict__ slo
     const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (r >= n_rows) return;
     double s = 0.0;
-    for (int64_t k = slot_ptr[r]; k < slot_ptr[r + 1]; ++k) s += yl[slots[k]];
+    const int64_t k0 = slot_ptr[r], k1 = slot_ptr[r + 1];
+    // loads of eight (then four) slots in flight together, added in slot order (the same sum
+    // as one slot at a time; each dof's slots are random reads of yl, so a lane otherwise
+    // waits out one load latency per slot)
+    int64_t k = k0;
+    for (; k + 8 <= k1; k += 8) {
+        int32_t a[8];
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = slots[k + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = yl[a[u]];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; k + 4 <= k1; k += 4) {
+        const int32_t a0 = slots[k], a1 = slots[k + 1], a2 = slots[k + 2], a3 = slots[k + 3];
+        const double v0 = yl[a0], v1 = yl[a1], v2 = yl[a2], v3 = yl[a3];
+        s += v0;
+        s += v1;
+        s += v2;
+        s += v3;
+    }
+    for (; k < k1; ++k) s += yl[slots[k]];
     y[r] = s;
 }
 }  // namespace
