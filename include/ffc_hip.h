@@ -154,8 +154,14 @@ typedef struct {
                             in registers for element tensors of at least 100 entries in FP64
                             -- 12 waves on 16-, 32- or 64-cell tiles below 576 entries, 16-cell
                             tiles from 576 -- and 144 in the split modes, 100 for forms with
-                            coefficients, when they fit),
-                            1 = persistent whenever it fits, -1 = one workgroup per cell tile */
+                            coefficients, when they fit; FP64 forms without coefficients of 400
+                            entries and more build that schedule for the operator action and
+                            batches but tabulate on one 16-cell tile per workgroup after a
+                            geometry pass, measured faster there),
+                            1 = persistent whenever it fits, -1 = one workgroup per cell tile.
+                            Default tile launches: the cell tile and workgroup size measured
+                            fastest for the element tensor's size (one or two waves for
+                            tensors of at most 36 entries); ffc_form_get_info reports them */
     int32_t geometry;    /* tensor kernel, ffc_tabulate_tensor: where the affine map is
                             computed.  FFC_GEOMETRY_PASS = a geometry kernel writes it to a
                             form-owned workspace that the contraction reads;
