@@ -75,3 +75,27 @@ def test_candidate_lists():
     assert tune.CANDIDATES_FP64[-1]["kernel"] == "quadrature"
     assert all(c["kernel"] == "tensor" for c in tune.CANDIDATES_SPLIT)
     assert len(tune.default_sweep_shapes()) == 18 * 6
+
+
+def test_decision_margin():
+    """A candidate replaces the default (index 0) only when predicted faster by more than
+    the margin; the allowed set restricts the choice; margin 0 is the plain argmin."""
+    sel = selector.Selector.__new__(selector.Selector)
+    sel.margin = 0.02
+    lg = math.log1p
+    assert sel.decide(np.array([0.0, -lg(0.01), 0.3])) == 0           # 1% predicted gain: keep the default
+    assert sel.decide(np.array([0.0, -lg(0.05), -lg(0.03)])) == 1     # 5% gain: take the best
+    assert sel.decide(np.array([0.0, -lg(0.05), -lg(0.03)]), allowed=[0, 2]) == 2
+    assert sel.decide(np.array([0.1, 0.0, 0.2])) == 1                 # the default predicted slower
+    sel.margin = 0.0
+    assert sel.decide(np.array([0.0, -1e-9, 0.3])) == 1
+    assert selector.DECISION_MARGIN == 0.02
+
+
+def test_selector_file_carries_the_margin():
+    """The shipped selector file is format 2 and states the decision margin the library's
+    automatic choice applies."""
+    tok = open(selector.DEFAULT_FILE).read().split()
+    assert tok[:2] == ["ffc_selector", "2"]
+    i = tok.index("margin")
+    assert tok[i - 2] == "tmu" and float(tok[i + 1]) == selector.DECISION_MARGIN
