@@ -414,16 +414,35 @@ int ffc_form_create(const ffc_form_desc* desc, ffc_form** out) {
             return rc;
     } else if (desc->precision == FFC_FP64) {
         // default grouping: greedy clustering over all rows for large element tensors (the
-        // persistent kernel), consecutive rows for small ones (64-cell tiles)
+        // persistent kernel), consecutive rows for small ones (64-cell tiles) -- and for
+        // mid-size ones (from kPersistentMidEntries) clustering too where it moves the 12-wave
+        // schedule into a smaller register-step bucket (elasticity P1 on tetrahedra: 8 instead
+        // of 16 steps per wave, 0.331 -> 0.253 ms at ~10^6 cells; with the bucket unchanged,
+        // fewer steps alone measured -2% to +13%)
         f->tile_window = desc->tile_window ? desc->tile_window : (rt.n_I >= kPersistentMinEntries ? -1 : 16);
         // symmetric forms: tiles over the entries i1 <= i2, where that takes fewer MFMA steps
-        ffc::TilesF64 t = ffc::make_tiles_f64(rt, f->tile_window, false);
-        f->sym_n = 0;
-        if (desc->symmetry == 0 && spec.kind != FFC_NS_CONVECTION) {
-            ffc::TilesF64 ts = ffc::make_tiles_f64(rt, f->tile_window, true);
-            if (ts.koff.back() < t.koff.back()) {
-                t = std::move(ts);
-                f->sym_n = rt.n;
+        auto tiles_for = [&](int window, int* sym_n) {
+            ffc::TilesF64 tt = ffc::make_tiles_f64(rt, window, false);
+            *sym_n = 0;
+            if (desc->symmetry == 0 && spec.kind != FFC_NS_CONVECTION) {
+                ffc::TilesF64 ts = ffc::make_tiles_f64(rt, window, true);
+                if (ts.koff.back() < tt.koff.back()) {
+                    tt = std::move(ts);
+                    *sym_n = rt.n;
+                }
+            }
+            return tt;
+        };
+        ffc::TilesF64 t = tiles_for(f->tile_window, &f->sym_n);
+        if (desc->tile_window == 0 && f->tile_window == 16 && rt.n_I >= kPersistentMidEntries) {
+            int sym_c = 0;
+            ffc::TilesF64 tc = tiles_for(-1, &sym_c);
+            auto bucket = [](int steps) { return steps <= 8 ? 8 : steps <= 16 ? 16 : 24; };
+            if (bucket(ffc::make_wave_schedule(tc, 12 - ffc::kIoWaves).max_steps) <
+                bucket(ffc::make_wave_schedule(t, 12 - ffc::kIoWaves).max_steps)) {
+                t = std::move(tc);
+                f->sym_n = sym_c;
+                f->tile_window = -1;
             }
         }
         f->n_tiles = t.n_tiles;

@@ -721,6 +721,7 @@ DEFAULT_LAUNCHES = [
     ("laplace", 2, 1, (0, 32, 1, 1)),       # 9 entries: 32-cell tiles of one wave
     ("wlaplace", 3, 1, (0, 32, 2, 1)),      # 16 entries with a coefficient: 32-cell tiles of two waves
     ("wlaplace", 2, 2, (0, 32, 2, 1)),
+    ("ns", 3, 1, (12, 64, None, 1)),        # 144 entries: rows clustered, 9 steps, 64-cell persistent tiles
 ]
 
 
